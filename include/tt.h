@@ -1,0 +1,207 @@
+/*
+ * tt.h -- C ABI of the MI355X Toeplitz spatio-angular MMSE tomographic
+ * reconstructor (Ono, Correia, Conan, Blanco, Neichel, Fusco, JOSA A 2018,
+ * "Fast Iterative Tomographic Wave-front Estimation with Recursive Toeplitz
+ * Reconstructor Structure for Large Scale Systems").
+ *
+ * The library solves the first step of the spatio-angular reconstructor
+ * (§2.C, first two-step equation, with the aperture masks of §2.F)
+ *
+ *     W_s (Sigma_ss + Sigma_eta) W_s^T zeta = s
+ *
+ * by conjugate gradients (§2.G) whose matrix-vector products use the
+ * two-level recursive block Toeplitz (2RBT) structure of Sigma_ss (§2.D) and
+ * the circulant-embedding product of §2.E (shuffle, 2-D FFT, per-frequency
+ * products summed over blocks, inverse FFT, reshuffle), and then the second
+ * step phi = W_phi Sigma_{phi_beta s} zeta through the per-layer grids and
+ * bilinear interpolation of the LGS phase-slope product (§2.D "Phase-Slope
+ * Covariance Matrix", §2.E LGS equation).  Covariances follow the Hudgin-like
+ * model with the von Karman structure function (App. A.2).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Subaperture (i, j) is row i (y) and column j (x); masks are row-major
+ *   n*n bytes, index i*n + j.  Phase points are the (n+1)^2 subaperture
+ *   corners, index i*(n+1) + j.
+ * - Slope vectors hold only valid subapertures (W_s): channel c = 2*g + p
+ *   (g = guide star, p = 0 x / 1 y), element c*n_vs + v where v enumerates
+ *   the valid subapertures in row-major order.  Slopes are phase differences
+ *   across one subaperture in radians at the wavelength of r0 (500 nm).
+ * - Reconstructed phase phi holds only valid phase points (W_phi: corners of
+ *   valid subapertures) in row-major order, in radians.
+ * - Pointers named d_* are device pointers on the context's device and are
+ *   owned by the caller; they must stay valid until the work enqueued on the
+ *   context's stream has finished.  Every other pointer is a host pointer that
+ *   is read during the call only (the library copies what it keeps).
+ * - Work is enqueued on the context's stream; calls return without waiting
+ *   unless documented otherwise.  A context is not thread-safe; use one
+ *   context per stream.
+ * - Errors: every call returns a tt_status; no exception crosses the ABI.
+ *   Outputs are valid only when the status is TT_OK (or TT_NOT_CONVERGED for
+ *   the solution of a solve).  tt_last_error() describes the last failure of
+ *   the calling thread.
+ */
+#ifndef TT_H
+#define TT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TT_OK = 0,
+    TT_INVALID_ARG = 1,     /* bad size, pointer or parameter; nothing was enqueued */
+    TT_HIP_ERROR = 2,       /* a HIP runtime call failed */
+    TT_OUT_OF_MEMORY = 3,   /* device allocation failed */
+    TT_NOT_CONVERGED = 4,   /* iteration cap reached; zeta holds the last iterate */
+    TT_BREAKDOWN = 5,       /* p^T A p <= 0 or a non-finite scalar in CG */
+    TT_NOT_READY = 6        /* tt_set_system (or a target) is missing */
+} tt_status;
+
+typedef enum {
+    TT_PREC_F32 = 0,        /* FP32 spectra and vectors, FP64 dot products, FP64
+                               residual refinement (true residual b - A x with the
+                               FP64 operator each time the FP32 residual has
+                               dropped by refine_drop); certifies tol in FP64 */
+    TT_PREC_F64 = 1         /* FP64 throughout */
+} tt_precision;
+
+typedef enum {
+    TT_SOLVER_PERSISTENT = 0, /* one persistent launch per solve segment, grid
+                                 barriers between phases, on-device convergence */
+    TT_SOLVER_KERNELS = 1     /* one launch per phase, host polls convergence */
+} tt_solver_kind;
+
+typedef enum {
+    TT_MODEL_HUDGIN = 0      /* App. A.2 Hudgin-like two-point slopes */
+} tt_gradient_model;
+
+/* Sensor geometry (§2, §2.D, §2.F).  The library copies every array. */
+typedef struct {
+    int n;                        /* subapertures across one sensor, 1..512 */
+    int n_gs;                     /* guide stars (one sensor each), 1..16 */
+    int pad_L;                    /* FFT side of the slope-slope products, >= 2n-1,
+                                     <= 1024 */
+    int gradient_model;           /* tt_gradient_model */
+    double D;                     /* pupil diameter [m]; subaperture d = D/n */
+    double h_lgs;                 /* LGS altitude [m]; <= 0 or +inf: natural guide stars */
+    const double* gs_xy;          /* 2*n_gs: direction (x, y) of each guide star [rad] */
+    const unsigned char* valid;   /* n*n, row-major, nonzero = valid subaperture (W_s) */
+} tt_geometry;
+
+/* Layered von Karman atmosphere (§2, App. A.2).  Layer k contributes
+ * w[k] * D(r) with D the von Karman structure function of r0, L0. */
+typedef struct {
+    int n_layer;                  /* 1..256 */
+    const double* h;              /* n_layer altitudes [m], 0 <= h < h_lgs */
+    const double* w;              /* n_layer fractional C_n^2 weights (not renormalised) */
+    double r0;                    /* Fried parameter [m] at the phase wavelength */
+    double L0;                    /* outer scale [m] */
+} tt_atmosphere;
+
+/* Reconstruction direction and the per-layer grids of the LGS phase-slope
+ * product (§2.D, §2.E): every layer uses a common n' x n' grid of spacing
+ * s_k d, s_k = 1 - h_k/h_lgs, centred on the direction. */
+typedef struct {
+    double beta_x, beta_y;        /* target direction [rad] (target at infinity) */
+    int n_prime;                  /* 0: ceil(n / min_k s_k) + 1 */
+    int pad_L;                    /* FFT side, >= n' + n - 1; 0: n' + n - 1 rounded up to even */
+} tt_target;
+
+typedef struct {
+    double tol;                   /* stop at ||s - A zeta||_2 <= tol ||s||_2 */
+    int max_iter;                 /* cap on CG iterations (all segments together) */
+    int precision;                /* tt_precision */
+    int solver;                   /* tt_solver_kind */
+    double refine_drop;           /* TT_PREC_F32: FP64 residual replacement when the
+                                     recursive residual fell by this factor since the
+                                     last one (0 -> 1e-2) */
+} tt_solve_opts;
+
+typedef struct {
+    int iterations;               /* CG iterations done */
+    int refinements;              /* FP64 residual replacements done */
+    int status;                   /* tt_status of the solve */
+    double rel_residual;          /* last FP64 ||s - A zeta|| / ||s|| (true residual) */
+    double recursive_residual;    /* last recursive ||r|| / ||s|| of the inner CG */
+} tt_solve_info;
+
+/* Sizes of a configured system. */
+typedef struct {
+    int n, n_gs, pad_L, n_vs, n_slopes;
+    int n_vphi;                   /* valid phase points (0 without a target) */
+    int n_prime, proj_pad_L;      /* projection grid and FFT side (0 without a target) */
+    int n_layer;
+    size_t spectra_bytes_f32;     /* packed slope-slope spectra, FP32 copy */
+    size_t spectra_bytes_f64;     /* packed slope-slope spectra, FP64 copy */
+    size_t proj_spectra_bytes;    /* phase-slope spectra of the projection (FP32) */
+} tt_system_info;
+
+typedef struct tt_ctx tt_ctx;
+typedef struct tt_kernels tt_kernels;
+
+/* Create a context on HIP device `device`, enqueuing on `stream` (a hipStream_t,
+ * NULL = the null stream).  Owns its device memory until tt_destroy. */
+tt_status tt_create(tt_ctx** out, int device, void* stream);
+tt_status tt_destroy(tt_ctx* ctx);
+
+/* Covariance generation, FP64 on the device (App. A.2 Hudgin slope-slope
+ * equations with the §2.D cone scaling; row a1 of the hot path).  For every
+ * unordered guide-star pair g <= h and component xx, xy (= yx), yy it evaluates
+ * the (2n-1)^2 unique elements of the 2RBT block Theta^{gh}_{pq} (§2.D):
+ *   t(u, v) = sum_k w_k Hud_pq( s_k (u d, v d) + h_k (alpha_h - alpha_g); s_k d ),
+ * u = column lag, v = row lag of the second slope relative to the first.
+ * The result is owned by the library until tt_kernels_destroy. Synchronous. */
+tt_status tt_generate_kernels(tt_ctx* ctx, const tt_geometry* geom,
+                              const tt_atmosphere* atm, tt_kernels** out);
+tt_status tt_kernels_destroy(tt_kernels* k);
+/* Copy the tables to host memory: `count` doubles laid out as
+ * [pair][component][v + n-1][u + n-1], pairs (g, h), g <= h, in row-major
+ * order of g then h, components xx, xy, yy.  count must equal
+ * n_gs (n_gs + 1) / 2 * 3 * (2n-1)^2.  Synchronous. */
+tt_status tt_kernels_copy(const tt_kernels* k, double* host_out, size_t count);
+
+/* Build the system (row a2 and set-up): FP64 2-D real DFT of every embedded
+ * table (K[(-u) mod L, (-v) mod L] = t(u, v)), packed per frequency as the
+ * 2 n_gs x 2 n_gs Hermitian matrix of §2.E's per-frequency products (FP64 and
+ * FP32 copies), the W_s index maps, the noise variance Sigma_eta = diag
+ * (noise_var[i] if noise_var != NULL, else noise_scalar; §2.C, §2.F), and, if
+ * target != NULL, the projection operators of §2.D/§2.E for that direction.
+ * Replaces any previous system of the context.  Synchronous. */
+tt_status tt_set_system(tt_ctx* ctx, const tt_kernels* k, const double* noise_var,
+                        double noise_scalar, const tt_target* target);
+tt_status tt_get_system_info(const tt_ctx* ctx, tt_system_info* out);
+
+/* y = W_s (Sigma_ss + Sigma_eta) W_s^T x, once, by the fused 2RBT product of
+ * §2.E (rows a3-a7).  d_x, d_y: n_slopes elements; they must not overlap. */
+tt_status tt_matvec(tt_ctx* ctx, const float* d_x, float* d_y);
+tt_status tt_matvec_f64(tt_ctx* ctx, const double* d_x, double* d_y);
+
+/* Solve W_s (Sigma_ss + Sigma_eta) W_s^T zeta = s by CG (rows a3-a8, a10) and,
+ * if d_phi != NULL, project phi = W_phi Sigma_{phi_beta s} zeta (row a9).
+ * d_s: n_slopes floats; d_x0: n_slopes doubles (warm start) or NULL (zeta0 = 0);
+ * d_zeta: n_slopes doubles (out); d_phi: n_vphi floats (out) or NULL.
+ * opts NULL = tol 1e-6, max_iter 20000, TT_PREC_F32, persistent.
+ * Waits for completion; info (may be NULL) receives the iteration counts and
+ * the final FP64 true residual.  Returns TT_OK, TT_NOT_CONVERGED or TT_BREAKDOWN
+ * (zeta = last iterate) or an argument / runtime error. */
+tt_status tt_solve_frame(tt_ctx* ctx, const float* d_s, const double* d_x0,
+                         double* d_zeta, float* d_phi, const tt_solve_opts* opts,
+                         tt_solve_info* info);
+
+/* phi = W_phi sum_k I'_k S2 F^-1 { sum_q Xi'~_{q,k} . F[S1 zeta_q] } (row a9,
+ * §2.E LGS phase-slope equation with a common n').  d_zeta: n_slopes doubles
+ * (rounded to FP32 for the products), d_phi: n_vphi floats.  Requires a target. */
+tt_status tt_project(tt_ctx* ctx, const double* d_zeta, float* d_phi);
+
+const char* tt_status_string(tt_status s);
+/* Message of the last failing call on the calling thread ("" if none). */
+const char* tt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TT_H */
