@@ -1,0 +1,319 @@
+// C entry points (include/tt.h).  Argument validation, ownership and the
+// order of the set-up steps live here; the arithmetic is in the other units.
+#include <algorithm>
+#include <cstring>
+
+#include "tt_internal.h"
+
+tt_status matvec_prepare(tt_ctx& c);
+
+namespace {
+thread_local std::string g_last_error;
+
+bool finite_all(const double* p, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+tt_status use_device(int dev) {
+    TT_HIP(hipSetDevice(dev));
+    return TT_OK;
+}
+
+#define TT_GUARD(expr)                                    \
+    do {                                                  \
+        try {                                             \
+            return (expr);                                \
+        } catch (const std::exception& e) {               \
+            tt_set_error(std::string("exception: ") + e.what()); \
+            return TT_OUT_OF_MEMORY;                      \
+        } catch (...) {                                   \
+            tt_set_error("unknown exception");            \
+            return TT_HIP_ERROR;                          \
+        }                                                 \
+    } while (0)
+
+tt_status create_impl(tt_ctx** out, int device, void* stream) {
+    TT_REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    TT_HIP(hipGetDeviceCount(&ndev));
+    TT_REQUIRE(device >= 0 && device < ndev, "device index out of range");
+    TT_CHECK(use_device(device));
+    tt_ctx* c = new tt_ctx();
+    c->device = device;
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete c;
+        tt_set_error("hipGetDeviceProperties failed");
+        return TT_HIP_ERROR;
+    }
+    c->num_cu = prop.multiProcessorCount;
+    *out = c;
+    return TT_OK;
+}
+
+tt_status generate_impl(tt_ctx* c, const tt_geometry* g, const tt_atmosphere* a, tt_kernels** out) {
+    TT_REQUIRE(c && g && a && out, "NULL argument");
+    *out = nullptr;
+    TT_REQUIRE(g->n >= 1 && g->n <= 512, "n must be in [1, 512]");
+    TT_REQUIRE(g->n_gs >= 1 && g->n_gs <= 16, "n_gs must be in [1, 16]");
+    TT_REQUIRE(g->pad_L >= 2 * g->n - 1 && g->pad_L <= 1024, "pad_L must be in [2n-1, 1024]");
+    TT_REQUIRE(g->gradient_model == TT_MODEL_HUDGIN, "unsupported gradient model");
+    TT_REQUIRE(std::isfinite(g->D) && g->D > 0, "D must be positive");
+    TT_REQUIRE(g->gs_xy && g->valid, "gs_xy and valid are required");
+    TT_REQUIRE(finite_all(g->gs_xy, 2 * g->n_gs), "non-finite guide-star direction");
+    int nv = 0;
+    for (int i = 0; i < g->n * g->n; ++i) nv += g->valid[i] != 0;
+    TT_REQUIRE(nv > 0, "no valid subaperture");
+    TT_REQUIRE(a->n_layer >= 1 && a->n_layer <= 256, "n_layer must be in [1, 256]");
+    TT_REQUIRE(a->h && a->w, "h and w are required");
+    TT_REQUIRE(finite_all(a->h, a->n_layer) && finite_all(a->w, a->n_layer), "non-finite layer data");
+    TT_REQUIRE(std::isfinite(a->r0) && a->r0 > 0 && std::isfinite(a->L0) && a->L0 > 0, "r0 and L0 must be positive");
+    const bool lgs = std::isfinite(g->h_lgs) && g->h_lgs > 0;
+    for (int k = 0; k < a->n_layer; ++k) {
+        TT_REQUIRE(a->h[k] >= 0, "negative layer altitude");
+        if (lgs) TT_REQUIRE(a->h[k] < g->h_lgs, "layer at or above the LGS altitude");
+    }
+    TT_CHECK(use_device(c->device));
+    tt_kernels* k = new tt_kernels();
+    k->device = c->device;
+    k->n = g->n;
+    k->n_gs = g->n_gs;
+    k->pad_L = g->pad_L;
+    k->model = g->gradient_model;
+    k->D = g->D;
+    k->d = g->D / g->n;
+    k->h_lgs = g->h_lgs;
+    k->lgs = lgs;
+    k->gs.assign(g->gs_xy, g->gs_xy + 2 * g->n_gs);
+    k->valid.resize((size_t)g->n * g->n);
+    for (int i = 0; i < g->n * g->n; ++i) k->valid[i] = g->valid[i] ? 1 : 0;
+    k->n_layer = a->n_layer;
+    k->h.assign(a->h, a->h + a->n_layer);
+    k->w.assign(a->w, a->w + a->n_layer);
+    k->r0 = a->r0;
+    k->L0 = a->L0;
+    const long m = 2 * g->n - 1;
+    k->count = (size_t)n_pairs_incl(g->n_gs) * 3 * m * m;
+    tt_status st = k->tables.alloc(k->count);
+    if (st == TT_OK) st = gen_tables_launch(*k, k->tables.p, c->stream);
+    if (st != TT_OK) {
+        delete k;
+        return st;
+    }
+    *out = k;
+    return TT_OK;
+}
+
+tt_status set_system_impl(tt_ctx* c, const tt_kernels* k, const double* noise_var, double noise_scalar,
+                          const tt_target* target) {
+    TT_REQUIRE(c && k, "NULL argument");
+    TT_REQUIRE(k->device == c->device, "kernels were generated on another device");
+    TT_CHECK(use_device(c->device));
+    c->ready = false;
+    c->proj.on = false;
+    c->n = k->n;
+    c->G = k->n_gs;
+    c->C = 2 * k->n_gs;
+    c->L = k->pad_L;
+    c->Lh = k->pad_L / 2 + 1;
+    c->n_layer = k->n_layer;
+    c->d = k->d;
+    c->h_lgs = k->h_lgs;
+    c->lgs = k->lgs;
+    c->gs = k->gs;
+    c->h = k->h;
+    c->w = k->w;
+    c->r0 = k->r0;
+    c->L0 = k->L0;
+    c->valid = k->valid;
+    // W_s index maps
+    std::vector<int> vmap((size_t)c->n * c->n, -1), vidx;
+    for (int i = 0; i < c->n * c->n; ++i)
+        if (k->valid[i]) {
+            vmap[i] = (int)vidx.size();
+            vidx.push_back(i);
+        }
+    c->n_vs = (int)vidx.size();
+    c->n_slopes = c->C * c->n_vs;
+    // noise
+    std::vector<double> nz(c->n_slopes, noise_scalar);
+    if (noise_var) nz.assign(noise_var, noise_var + c->n_slopes);
+    for (double v : nz) TT_REQUIRE(std::isfinite(v), "non-finite noise variance");
+    std::vector<float> nz32(nz.begin(), nz.end());
+    TT_CHECK(c->vmap.upload(vmap.data(), vmap.size(), c->stream));
+    TT_CHECK(c->vidx.upload(vidx.data(), vidx.size(), c->stream));
+    TT_CHECK(c->noise64.upload(nz.data(), nz.size(), c->stream));
+    TT_CHECK(c->noise32.upload(nz32.data(), nz32.size(), c->stream));
+    TT_HIP(hipStreamSynchronize(c->stream));
+    c->host_noise = nz;
+    TT_CHECK(build_twiddles(c->L, c->tw32, &c->tw64, c->stream));
+    TT_CHECK(build_slope_spectra(*c, *k));
+    const size_t tsz = (size_t)c->Lh * c->C * c->n;
+    TT_CHECK(c->T32.alloc(tsz));
+    TT_CHECK(c->U32.alloc(tsz));
+    TT_CHECK(c->T64.alloc(tsz));
+    TT_CHECK(c->U64.alloc(tsz));
+    TT_CHECK(cg_alloc(*c));
+    if (target) TT_CHECK(projection_setup(*c, target));
+    TT_HIP(hipStreamSynchronize(c->stream));
+    c->ready = true;
+    return TT_OK;
+}
+
+tt_status solve_impl(tt_ctx* c, const float* s, const double* x0, double* zeta, float* phi, const tt_solve_opts* opts,
+                     tt_solve_info* info) {
+    TT_REQUIRE(c && s && zeta, "NULL argument");
+    if (!c->ready) {
+        tt_set_error("tt_solve_frame: no system set");
+        return TT_NOT_READY;
+    }
+    if (phi && !c->proj.on) {
+        tt_set_error("tt_solve_frame: d_phi given but no target was set");
+        return TT_NOT_READY;
+    }
+    tt_solve_opts o;
+    o.tol = 1e-6;
+    o.max_iter = 20000;
+    o.precision = TT_PREC_F32;
+    o.solver = TT_SOLVER_PERSISTENT;
+    o.refine_drop = 1e-2;
+    if (opts) o = *opts;
+    TT_REQUIRE(std::isfinite(o.tol) && o.tol >= 0, "tol must be >= 0");
+    TT_REQUIRE(o.max_iter >= 0, "max_iter must be >= 0");
+    TT_REQUIRE(o.precision == TT_PREC_F32 || o.precision == TT_PREC_F64, "unknown precision");
+    TT_REQUIRE(o.solver == TT_SOLVER_PERSISTENT || o.solver == TT_SOLVER_KERNELS, "unknown solver");
+    TT_REQUIRE(std::isfinite(o.refine_drop) && o.refine_drop >= 0 && o.refine_drop < 1, "refine_drop in [0, 1)");
+    TT_CHECK(use_device(c->device));
+    tt_solve_info inf{};
+    if (o.solver == TT_SOLVER_PERSISTENT)
+        TT_CHECK(solve_persistent(*c, s, x0, zeta, o, inf));
+    else
+        TT_CHECK(solve_kernels(*c, s, x0, zeta, o, inf));
+    if (phi) {
+        TT_CHECK(projection_apply(*c, zeta, phi));
+        TT_HIP(hipStreamSynchronize(c->stream));
+    }
+    if (info) *info = inf;
+    return (tt_status)inf.status;
+}
+
+}  // namespace
+
+void tt_set_error(const std::string& msg) { g_last_error = msg; }
+
+extern "C" {
+
+tt_status tt_create(tt_ctx** out, int device, void* stream) { TT_GUARD(create_impl(out, device, stream)); }
+
+tt_status tt_destroy(tt_ctx* ctx) {
+    if (!ctx) return TT_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    delete ctx;
+    return TT_OK;
+}
+
+tt_status tt_generate_kernels(tt_ctx* ctx, const tt_geometry* geom, const tt_atmosphere* atm, tt_kernels** out) {
+    TT_GUARD(generate_impl(ctx, geom, atm, out));
+}
+
+tt_status tt_kernels_destroy(tt_kernels* k) {
+    if (!k) return TT_OK;
+    (void)hipSetDevice(k->device);
+    delete k;
+    return TT_OK;
+}
+
+tt_status tt_kernels_copy(const tt_kernels* k, double* host_out, size_t count) {
+    TT_REQUIRE(k && host_out, "NULL argument");
+    TT_REQUIRE(count == k->count, "count must equal n_gs(n_gs+1)/2 * 3 * (2n-1)^2");
+    TT_HIP(hipSetDevice(k->device));
+    TT_HIP(hipMemcpy(host_out, k->tables.p, count * sizeof(double), hipMemcpyDeviceToHost));
+    return TT_OK;
+}
+
+tt_status tt_set_system(tt_ctx* ctx, const tt_kernels* k, const double* noise_var, double noise_scalar,
+                        const tt_target* target) {
+    TT_GUARD(set_system_impl(ctx, k, noise_var, noise_scalar, target));
+}
+
+tt_status tt_get_system_info(const tt_ctx* c, tt_system_info* out) {
+    TT_REQUIRE(c && out, "NULL argument");
+    if (!c->ready) {
+        tt_set_error("tt_get_system_info: no system set");
+        return TT_NOT_READY;
+    }
+    tt_system_info s{};
+    s.n = c->n;
+    s.n_gs = c->G;
+    s.pad_L = c->L;
+    s.n_vs = c->n_vs;
+    s.n_slopes = c->n_slopes;
+    s.n_layer = c->n_layer;
+    s.n_vphi = c->proj.on ? c->proj.n_vphi : 0;
+    s.n_prime = c->proj.on ? c->proj.np : 0;
+    s.proj_pad_L = c->proj.on ? c->proj.Lp : 0;
+    s.spectra_bytes_f32 = c->M32.n * sizeof(float);
+    s.spectra_bytes_f64 = c->M64.n * sizeof(double);
+    s.proj_spectra_bytes = c->proj.on ? c->proj.spec.n * sizeof(c32) : 0;
+    *out = s;
+    return TT_OK;
+}
+
+tt_status tt_matvec(tt_ctx* c, const float* d_x, float* d_y) {
+    TT_REQUIRE(c && d_x && d_y, "NULL argument");
+    TT_REQUIRE(d_x != d_y, "d_x and d_y must not alias");
+    if (!c->ready) {
+        tt_set_error("tt_matvec: no system set");
+        return TT_NOT_READY;
+    }
+    TT_HIP(hipSetDevice(c->device));
+    return matvec_f32(*c, d_x, d_y, nullptr);
+}
+
+tt_status tt_matvec_f64(tt_ctx* c, const double* d_x, double* d_y) {
+    TT_REQUIRE(c && d_x && d_y, "NULL argument");
+    TT_REQUIRE(d_x != d_y, "d_x and d_y must not alias");
+    if (!c->ready) {
+        tt_set_error("tt_matvec_f64: no system set");
+        return TT_NOT_READY;
+    }
+    TT_HIP(hipSetDevice(c->device));
+    return matvec_f64(*c, d_x, d_y, nullptr);
+}
+
+tt_status tt_solve_frame(tt_ctx* ctx, const float* d_s, const double* d_x0, double* d_zeta, float* d_phi,
+                         const tt_solve_opts* opts, tt_solve_info* info) {
+    TT_GUARD(solve_impl(ctx, d_s, d_x0, d_zeta, d_phi, opts, info));
+}
+
+tt_status tt_project(tt_ctx* c, const double* d_zeta, float* d_phi) {
+    TT_REQUIRE(c && d_zeta && d_phi, "NULL argument");
+    if (!c->ready || !c->proj.on) {
+        tt_set_error("tt_project: no system or no target set");
+        return TT_NOT_READY;
+    }
+    TT_HIP(hipSetDevice(c->device));
+    return projection_apply(*c, d_zeta, d_phi);
+}
+
+const char* tt_status_string(tt_status s) {
+    switch (s) {
+        case TT_OK: return "TT_OK";
+        case TT_INVALID_ARG: return "TT_INVALID_ARG";
+        case TT_HIP_ERROR: return "TT_HIP_ERROR";
+        case TT_OUT_OF_MEMORY: return "TT_OUT_OF_MEMORY";
+        case TT_NOT_CONVERGED: return "TT_NOT_CONVERGED";
+        case TT_BREAKDOWN: return "TT_BREAKDOWN";
+        case TT_NOT_READY: return "TT_NOT_READY";
+    }
+    return "TT_UNKNOWN_STATUS";
+}
+
+const char* tt_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,192 @@
+// Internal definitions shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tt.h"
+
+// ---------------------------------------------------------------------------
+// error handling (no exception crosses the C ABI)
+// ---------------------------------------------------------------------------
+void tt_set_error(const std::string& msg);
+
+#define TT_REQUIRE(cond, msg)                                   \
+    do {                                                        \
+        if (!(cond)) {                                          \
+            tt_set_error(std::string(__func__) + ": " + (msg)); \
+            return TT_INVALID_ARG;                              \
+        }                                                       \
+    } while (0)
+
+#define TT_HIP(call)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            tt_set_error(std::string(#call) + " failed: " + hipGetErrorString(e_));         \
+            return e_ == hipErrorOutOfMemory ? TT_OUT_OF_MEMORY : TT_HIP_ERROR;             \
+        }                                                                                   \
+    } while (0)
+
+#define TT_CHECK(expr)                   \
+    do {                                 \
+        tt_status s_ = (expr);           \
+        if (s_ != TT_OK) return s_;      \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device buffers owned by the library
+// ---------------------------------------------------------------------------
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    tt_status alloc(size_t count) {
+        release();
+        if (count == 0) return TT_OK;
+        hipError_t e = hipMalloc((void**)&p, count * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            tt_set_error(std::string("hipMalloc failed: ") + hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? TT_OUT_OF_MEMORY : TT_HIP_ERROR;
+        }
+        n = count;
+        return TT_OK;
+    }
+    tt_status upload(const T* host, size_t count, hipStream_t s) {
+        TT_CHECK(alloc(count));
+        if (count) TT_HIP(hipMemcpyAsync(p, host, count * sizeof(T), hipMemcpyHostToDevice, s));
+        return TT_OK;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// complex helpers
+// ---------------------------------------------------------------------------
+template <typename R> struct cplx { R x, y; };
+using c32 = cplx<float>;
+using c64 = cplx<double>;
+
+// ---------------------------------------------------------------------------
+// generated covariance tables (row a1)
+// ---------------------------------------------------------------------------
+struct tt_kernels {
+    int device = 0;
+    int n = 0, n_gs = 0, pad_L = 0, model = 0;
+    double D = 0, d = 0, h_lgs = 0;
+    bool lgs = false;
+    std::vector<double> gs;            // 2 n_gs
+    std::vector<unsigned char> valid;  // n*n
+    int n_layer = 0;
+    std::vector<double> h, w;
+    double r0 = 0, L0 = 0;
+    DevBuf<double> tables;             // [pair(g<=h)][comp][2n-1][2n-1]
+    size_t count = 0;
+};
+
+// number of unordered pairs g <= h and their row-major index
+inline int n_pairs_incl(int G) { return G * (G + 1) / 2; }
+inline int pair_incl(int g, int h, int G) { return g * G - g * (g - 1) / 2 + (h - g); }
+
+// packed per-frequency Hermitian matrix: 3 reals per sensor (xx, xy, yy), then
+// for g < h (row-major) 3 complex (xx, xy = yx, yy): 3 G^2 reals in total.
+inline int packed_reals(int G) { return 3 * G * G; }
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct Projection {
+    bool on = false;
+    int np = 0, Lp = 0, Lph = 0, n_vphi = 0, n_layer = 0;
+    double beta_x = 0, beta_y = 0;
+    DevBuf<c32> spec;        // [f2][f1][layer][channel] complex, FP32
+    DevBuf<int> vphi;        // n_vphi: flat phase-point index i*(n+1)+j
+    DevBuf<double> sk;       // per-layer cone factors s_k
+    DevBuf<float> z32;       // zeta rounded to FP32
+    DevBuf<c32> twp;         // Lp twiddles
+    DevBuf<c32> T, Xw;       // work: row transforms [f2][C][n]; per-layer column outputs [f2][layer][n']
+    DevBuf<float> layer_out; // [layer][n'][n']
+};
+
+struct tt_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cu = 0;
+
+    // system
+    bool ready = false;
+    int n = 0, G = 0, C = 0, L = 0, Lh = 0, n_vs = 0, n_slopes = 0, n_layer = 0;
+    int nmodel = 0;
+    DevBuf<float> M32;        // [Lh][L][3G^2]
+    DevBuf<double> M64;
+    DevBuf<int> vmap;         // n*n: valid index v or -1
+    DevBuf<int> vidx;         // n_vs: flat index of valid subaperture v
+    DevBuf<float> noise32;    // n_slopes
+    DevBuf<double> noise64;
+    DevBuf<c32> tw32;         // L twiddles exp(-2 pi i k / L) as (cos, sin)
+    DevBuf<c64> tw64;
+
+    // matvec work buffers
+    DevBuf<c32> T32, U32;     // [Lh][C][n]
+    DevBuf<c64> T64, U64;
+
+    // solver work buffers
+    DevBuf<float> x32, r32, p32, q32;   // q = A p
+    DevBuf<double> x64, r64, p64, q64;
+    DevBuf<double> part;                // per-block partial sums
+    DevBuf<double> scal;                // solver scalars (see cg.hip)
+    DevBuf<unsigned int> bar;           // grid barrier counters
+    std::vector<double> host_noise;
+
+    Projection proj;
+    // copy of the geometry the system was built from (for the projection)
+    double d = 0, h_lgs = 0;
+    bool lgs = false;
+    std::vector<double> gs, h, w;
+    double r0 = 0, L0 = 0;
+    std::vector<unsigned char> valid;
+};
+
+// ---------------------------------------------------------------------------
+// module entry points (host side)
+// ---------------------------------------------------------------------------
+// vonkarman.hip
+tt_status gen_tables_launch(const tt_kernels& k, double* d_out, hipStream_t s);
+tt_status gen_phase_tables_launch(const tt_ctx& c, int np, double* d_out, hipStream_t s);
+double vk_host_bracket(double x);   // host copy of the device bracket (diagnostics)
+
+// spectra.hip
+tt_status build_slope_spectra(tt_ctx& c, const tt_kernels& k);
+tt_status build_twiddles(int L, DevBuf<c32>& t32, DevBuf<c64>* t64, hipStream_t s);
+tt_status table_spectra(const double* d_tables, long ntab, int m, int off, int L, DevBuf<c64>& S, hipStream_t s);
+
+// matvec.hip
+tt_status matvec_f32(tt_ctx& c, const float* x, float* y, double* part);
+tt_status matvec_f64(tt_ctx& c, const double* x, double* y, double* part);
+
+// cg.hip
+tt_status cg_alloc(tt_ctx& c);
+tt_status solve_kernels(tt_ctx& c, const float* s, const double* x0, double* zeta,
+                        const tt_solve_opts& o, tt_solve_info& info);
+tt_status solve_persistent(tt_ctx& c, const float* s, const double* x0, double* zeta,
+                           const tt_solve_opts& o, tt_solve_info& info);
+
+// project.hip
+tt_status projection_setup(tt_ctx& c, const tt_target* t);
+tt_status projection_apply(tt_ctx& c, const double* zeta, float* phi);
+
+// launch-shape helper
+inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }

@@ -1,0 +1,289 @@
+"""Thin Python binding of the C ABI in include/tt.h (argument marshalling only).
+
+Every step of the reconstructor runs in the HIP library libtt.so; this module
+only converts Python arguments to the C structs, passes device pointers of
+PyTorch tensors (PyTorch supplies device memory and the stream) and turns
+status codes into exceptions.  If the library is not built, importing the
+library raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtt.so")
+
+TT_OK, TT_INVALID_ARG, TT_HIP_ERROR, TT_OUT_OF_MEMORY, TT_NOT_CONVERGED, TT_BREAKDOWN, TT_NOT_READY = range(7)
+PREC_F32, PREC_F64 = 0, 1
+SOLVER_PERSISTENT, SOLVER_KERNELS = 0, 1
+MODEL_HUDGIN = 0
+
+# Every function declared in include/tt.h.
+EXPORTED = (
+    "tt_create", "tt_destroy", "tt_generate_kernels", "tt_kernels_destroy", "tt_kernels_copy",
+    "tt_set_system", "tt_get_system_info", "tt_matvec", "tt_matvec_f64", "tt_solve_frame",
+    "tt_project", "tt_status_string", "tt_last_error",
+)
+
+
+class TTError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_status_name(status)}: {msg}")
+        self.status = status
+
+
+class _Geometry(C.Structure):
+    _fields_ = [("n", C.c_int), ("n_gs", C.c_int), ("pad_L", C.c_int), ("gradient_model", C.c_int),
+                ("D", C.c_double), ("h_lgs", C.c_double), ("gs_xy", C.POINTER(C.c_double)),
+                ("valid", C.POINTER(C.c_ubyte))]
+
+
+class _Atmosphere(C.Structure):
+    _fields_ = [("n_layer", C.c_int), ("h", C.POINTER(C.c_double)), ("w", C.POINTER(C.c_double)),
+                ("r0", C.c_double), ("L0", C.c_double)]
+
+
+class _Target(C.Structure):
+    _fields_ = [("beta_x", C.c_double), ("beta_y", C.c_double), ("n_prime", C.c_int), ("pad_L", C.c_int)]
+
+
+class _SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("precision", C.c_int), ("solver", C.c_int),
+                ("refine_drop", C.c_double)]
+
+
+class _SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("refinements", C.c_int), ("status", C.c_int),
+                ("rel_residual", C.c_double), ("recursive_residual", C.c_double)]
+
+
+class _SystemInfo(C.Structure):
+    _fields_ = [("n", C.c_int), ("n_gs", C.c_int), ("pad_L", C.c_int), ("n_vs", C.c_int), ("n_slopes", C.c_int),
+                ("n_vphi", C.c_int), ("n_prime", C.c_int), ("proj_pad_L", C.c_int), ("n_layer", C.c_int),
+                ("spectra_bytes_f32", C.c_size_t), ("spectra_bytes_f64", C.c_size_t),
+                ("proj_spectra_bytes", C.c_size_t)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libtt.so (once).  Raises RuntimeError if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run `python -m paper_1806_07938_amd.build`")
+    lib = C.CDLL(path)
+    vp = C.c_void_p
+    lib.tt_create.argtypes = [C.POINTER(vp), C.c_int, vp]
+    lib.tt_destroy.argtypes = [vp]
+    lib.tt_generate_kernels.argtypes = [vp, C.POINTER(_Geometry), C.POINTER(_Atmosphere), C.POINTER(vp)]
+    lib.tt_kernels_destroy.argtypes = [vp]
+    lib.tt_kernels_copy.argtypes = [vp, C.POINTER(C.c_double), C.c_size_t]
+    lib.tt_set_system.argtypes = [vp, vp, C.POINTER(C.c_double), C.c_double, C.POINTER(_Target)]
+    lib.tt_get_system_info.argtypes = [vp, C.POINTER(_SystemInfo)]
+    lib.tt_matvec.argtypes = [vp, vp, vp]
+    lib.tt_matvec_f64.argtypes = [vp, vp, vp]
+    lib.tt_solve_frame.argtypes = [vp, vp, vp, vp, vp, C.POINTER(_SolveOpts), C.POINTER(_SolveInfo)]
+    lib.tt_project.argtypes = [vp, vp, vp]
+    lib.tt_status_string.argtypes = [C.c_int]
+    lib.tt_status_string.restype = C.c_char_p
+    lib.tt_last_error.argtypes = []
+    lib.tt_last_error.restype = C.c_char_p
+    for name in EXPORTED:
+        if name not in ("tt_status_string", "tt_last_error"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _status_name(s: int) -> str:
+    try:
+        return load().tt_status_string(s).decode()
+    except Exception:
+        return f"status {s}"
+
+
+def _check(status: int, allow=(TT_OK,)):
+    if status not in allow:
+        raise TTError(status, load().tt_last_error().decode())
+    return status
+
+
+def _dptr(t, dtype, numel: Optional[int] = None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"expected a contiguous {dtype} tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class SolveInfo:
+    iterations: int
+    refinements: int
+    status: int
+    rel_residual: float
+    recursive_residual: float
+
+
+class Kernels:
+    """Generated FP64 covariance tables (owned by the library)."""
+
+    def __init__(self, handle, n, n_gs):
+        self._h = handle
+        self.n, self.n_gs = n, n_gs
+
+    @property
+    def count(self):
+        return self.n_gs * (self.n_gs + 1) // 2 * 3 * (2 * self.n - 1) ** 2
+
+    def tables(self) -> np.ndarray:
+        """(pairs, 3, 2n-1, 2n-1) array: pairs (g, h), g <= h row-major; xx, xy, yy;
+        [v + n-1, u + n-1] with u the column lag and v the row lag."""
+        out = np.empty(self.count, dtype=np.float64)
+        _check(load().tt_kernels_copy(self._h, out.ctypes.data_as(C.POINTER(C.c_double)), out.size))
+        m = 2 * self.n - 1
+        return out.reshape(-1, 3, m, m)
+
+    def close(self):
+        if self._h:
+            load().tt_kernels_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """One library context bound to a device and a stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        lib = load()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream_obj = stream
+        sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        h = C.c_void_p()
+        _check(lib.tt_create(C.byref(h), device, C.c_void_p(sp)))
+        self._h = h
+        self.device = device
+        self._keep = []
+
+    # -- set-up -----------------------------------------------------------
+    def generate_kernels(self, n: int, n_gs: int, pad_L: int, D: float, h_lgs: float,
+                         gs_xy: Sequence[Sequence[float]], valid, h, w, r0: float, L0: float) -> Kernels:
+        gs = np.ascontiguousarray(np.asarray(gs_xy, dtype=np.float64).reshape(-1))
+        vm = np.ascontiguousarray(np.asarray(valid, dtype=np.uint8).reshape(-1))
+        hh = np.ascontiguousarray(np.asarray(h, dtype=np.float64))
+        ww = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+        geo = _Geometry(n, n_gs, pad_L, MODEL_HUDGIN, float(D), float(h_lgs) if math.isfinite(h_lgs) else math.inf,
+                        gs.ctypes.data_as(C.POINTER(C.c_double)), vm.ctypes.data_as(C.POINTER(C.c_ubyte)))
+        atm = _Atmosphere(hh.size, hh.ctypes.data_as(C.POINTER(C.c_double)),
+                          ww.ctypes.data_as(C.POINTER(C.c_double)), float(r0), float(L0))
+        out = C.c_void_p()
+        _check(load().tt_generate_kernels(self._h, C.byref(geo), C.byref(atm), C.byref(out)))
+        return Kernels(out, n, n_gs)
+
+    def set_system(self, kernels: Kernels, noise_scalar: float = 0.0, noise_var=None,
+                   target: Optional[tuple] = None, n_prime: int = 0, proj_pad_L: int = 0):
+        nv = None
+        if noise_var is not None:
+            arr = np.ascontiguousarray(np.asarray(noise_var, dtype=np.float64))
+            self._keep = [arr]
+            nv = arr.ctypes.data_as(C.POINTER(C.c_double))
+        tgt = None
+        if target is not None:
+            tgt = C.byref(_Target(float(target[0]), float(target[1]), int(n_prime), int(proj_pad_L)))
+        _check(load().tt_set_system(self._h, kernels._h, nv, float(noise_scalar), tgt))
+        self.info = self.system_info()
+
+    def system_info(self) -> dict:
+        s = _SystemInfo()
+        _check(load().tt_get_system_info(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in _SystemInfo._fields_}
+
+    # -- hot path ---------------------------------------------------------
+    def matvec(self, x, y=None):
+        import torch
+        n = self.info["n_slopes"]
+        if y is None:
+            y = torch.empty(n, dtype=torch.float32, device=x.device)
+        _check(load().tt_matvec(self._h, _dptr(x, torch.float32, n), _dptr(y, torch.float32, n)))
+        return y
+
+    def matvec_f64(self, x, y=None):
+        import torch
+        n = self.info["n_slopes"]
+        if y is None:
+            y = torch.empty(n, dtype=torch.float64, device=x.device)
+        _check(load().tt_matvec_f64(self._h, _dptr(x, torch.float64, n), _dptr(y, torch.float64, n)))
+        return y
+
+    def solve(self, s, x0=None, zeta=None, phi=None, project: bool = True, tol: float = 1e-6,
+              max_iter: int = 20000, precision: int = PREC_F32, solver: int = SOLVER_PERSISTENT,
+              refine_drop: float = 1e-2, allow=(TT_OK,)):
+        """Solve for zeta (float64) and, if a target is set and project, phi (float32)."""
+        import torch
+        n = self.info["n_slopes"]
+        if zeta is None:
+            zeta = torch.empty(n, dtype=torch.float64, device=s.device)
+        pphi = None
+        if project and self.info["n_vphi"] > 0:
+            if phi is None:
+                phi = torch.empty(self.info["n_vphi"], dtype=torch.float32, device=s.device)
+            pphi = _dptr(phi, torch.float32, self.info["n_vphi"])
+        else:
+            phi = None
+        opts = _SolveOpts(float(tol), int(max_iter), int(precision), int(solver), float(refine_drop))
+        inf = _SolveInfo()
+        px0 = _dptr(x0, torch.float64, n) if x0 is not None else None
+        st = load().tt_solve_frame(self._h, _dptr(s, torch.float32, n), px0, _dptr(zeta, torch.float64, n),
+                                   pphi, C.byref(opts), C.byref(inf))
+        _check(st, allow=allow)
+        return zeta, phi, SolveInfo(inf.iterations, inf.refinements, inf.status, inf.rel_residual,
+                                    inf.recursive_residual)
+
+    def project(self, zeta, phi=None):
+        import torch
+        n = self.info["n_slopes"]
+        if phi is None:
+            phi = torch.empty(self.info["n_vphi"], dtype=torch.float32, device=zeta.device)
+        _check(load().tt_project(self._h, _dptr(zeta, torch.float64, n), _dptr(phi, torch.float32, self.info["n_vphi"])))
+        return phi
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().tt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def system_from(ctx: Context, wl, target: bool = True, pad_L: Optional[int] = None, proj_pad_L: int = 0,
+                n_prime: int = 0) -> Kernels:
+    """Generate kernels and set the system of `ctx` from any object with the
+    attributes n, D, gs, h_lgs, h, w, r0, L0, valid, pad_L, noise_var, target."""
+    k = ctx.generate_kernels(wl.n, wl.gs.shape[0], int(pad_L or wl.pad_L), wl.D, wl.h_lgs, wl.gs, wl.valid,
+                             wl.h, wl.w, wl.r0, wl.L0)
+    ctx.set_system(k, noise_scalar=wl.noise_var, target=(tuple(wl.target) if target else None),
+                   n_prime=n_prime, proj_pad_L=proj_pad_L)
+    return k
