@@ -1,0 +1,171 @@
+#!/usr/bin/env python3
+"""Benchmark: ms per solve of the 74x74, 6-LGS, 35-layer tomographic system at
+relative residual 1e-6, on one MI355X.
+
+One step = one frame through the whole hot path: CG solve of
+(Sigma_ss + Sigma_eta) zeta = s with the fused 2RBT products (FP32, with
+FP64 residual replacement certifying the tolerance) followed by the LGS
+projection phi = W_phi Sigma_phi_s zeta.  Kernel generation and spectra
+(set-up, done once per atmosphere) are timed separately.  Inputs: 20 seeded
+frames of slopes measured through von Karman layers, resident in HBM before
+the timed region.
+
+Prints one JSON line.  The roofline object is for the dominant kernel, the
+persistent CG kernel: algorithmic bytes per iteration (packed FP32 spectra +
+slopes in and out) times iterations per launch, over the launch duration
+measured with HIP events on the library's stream.  The cpu_baseline object
+times the FP64 oracle (CG with its step-by-step 2RBT product) on one frame.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "ms per solve at rel. residual 1e-6 (6 LGS, 74x74 SH), plain vs learned PCG"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--frames", type=int, default=20)
+    ap.add_argument("--pad", type=int, default=148)
+    ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--solver", choices=["persistent", "kernels"], default="persistent")
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-variants", action="store_true", help="skip the FP64 / kernel-solver side numbers")
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, s_frame, tol):
+    """FP64 oracle: CG (textbook) with the step-by-step 2RBT product, one frame."""
+    from oracle.covariance import kernel_tables
+    from oracle.solve import cg
+    from oracle.toeplitz import ToeplitzOperator
+    workers = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    op = ToeplitzOperator(wl, tables=kernel_tables(wl, workers=workers))
+    setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    x, it = cg(op, s_frame.astype(np.float64), tol=tol, maxiter=20000)
+    solve_s = time.perf_counter() - t0
+    return {
+        "value": round(solve_s * 1e3, 1), "unit": "ms per solve", "cores": 1, "kind": "oracle",
+        "sample": (f"one frame of the same workload, FP64 CG to rel. residual {tol:g} ({it} iterations) with the "
+                   f"oracle's numpy 2RBT product (single-threaded FFTs); covariance tables built beforehand in "
+                   f"{setup:.1f} s on {workers} processes, not included"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is described in DESIGN.md but not implemented.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as W
+    from paper_1806_07938_amd import Context, system_from
+    from paper_1806_07938_amd.tt import PREC_F32, PREC_F64, SOLVER_KERNELS, SOLVER_PERSISTENT
+
+    dev = torch.device("cuda:0")
+    wl = W.c2(pad_L=args.pad)
+    frames = W.turbulent_slopes(wl, frames=args.frames).astype(np.float32)
+
+    ctx = Context(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kern = system_from(ctx, wl, target=True)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    info = ctx.info
+
+    S = torch.tensor(frames, device=dev)
+    zeta = torch.empty(wl.n_slopes, dtype=torch.float64, device=dev)
+    phi = torch.empty(info["n_vphi"], dtype=torch.float32, device=dev)
+    prec = PREC_F32 if args.precision == "f32" else PREC_F64
+    solver = SOLVER_PERSISTENT if args.solver == "persistent" else SOLVER_KERNELS
+
+    def run(k, prec=prec, solver=solver):
+        return ctx.solve(S[k % args.frames], zeta=zeta, phi=phi, tol=args.tol, precision=prec, solver=solver)[2]
+
+    for k in range(args.warmup):
+        run(k)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        infos.append(run(k))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+
+    iters = np.array([i.iterations for i in infos], dtype=np.float64)
+    kms = np.array([i.kernel_ms for i in infos])
+    launches = np.array([i.kernel_launches for i in infos], dtype=np.float64)
+    relres = max(i.rel_residual for i in infos)
+    ok = all(i.status == 0 for i in infos) and relres <= args.tol
+
+    spectra = info["spectra_bytes_f32"] if prec == PREC_F32 else info["spectra_bytes_f64"]
+    elem = 4 if prec == PREC_F32 else 8
+    bytes_iter = spectra + 2 * wl.n_slopes * elem
+    roofline = None
+    if solver == SOLVER_PERSISTENT and kms.sum() > 0:
+        avg_launch_ms = kms.sum() / launches.sum()
+        bytes_launch = bytes_iter * iters.sum() / launches.sum()
+        achieved = bytes_launch / (avg_launch_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": f"k_cg_persistent<{'float' if prec == PREC_F32 else 'double'}>",
+                    "avg_launch_ms": round(avg_launch_ms, 4), "bytes_per_iteration": int(bytes_iter),
+                    "iterations_per_launch": round(float(iters.sum() / launches.sum()), 1)}
+
+    out = {
+        "metric": METRIC, "value": round(ms_per_step, 4), "unit": "ms", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == PREC_F32 else "f64", "data": "synthetic",
+        "config": {"workload": (f"39 m pupil, 28% obstruction, 74x74 SH (3972 valid/WFS), 6 LGS at 90 km on a 60 "
+                                f"arcsec ring, 35 layers 30 m-26.5 km, r0 0.157 m, L0 25 m, sigma^2 0.1 rad^2, "
+                                f"L={args.pad}, on-axis target; plain CG to rel. residual {args.tol:g}"),
+                   "n": wl.n, "n_gs": wl.n_gs, "n_layer": wl.n_layer, "n_slopes": wl.n_slopes, "pad_L": args.pad,
+                   "solver": args.solver, "precision": args.precision + ("+f64 residual replacement"
+                                                                          if prec == PREC_F32 else ""),
+                   "frames": args.frames},
+        "valid": bool(ok),
+        "iterations_mean": round(float(iters.mean()), 1),
+        "refinements_mean": round(float(np.mean([i.refinements for i in infos])), 2),
+        "rel_residual_max": relres,
+        "setup_ms": round(setup_ms, 1),
+        "roofline": roofline,
+    }
+    if not args.no_variants:
+        side = {}
+        for name, p, sv in (("f64_persistent", PREC_F64, SOLVER_PERSISTENT), ("f32_kernels", PREC_F32, SOLVER_KERNELS)):
+            if p == prec and sv == solver:
+                continue
+            run(0, p, sv)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ii = [run(k, p, sv) for k in range(3)]
+            torch.cuda.synchronize()
+            side[name] = {"ms_per_solve": round((time.perf_counter() - t0) * 1e3 / 3, 3),
+                          "iterations_mean": round(float(np.mean([i.iterations for i in ii])), 1),
+                          "rel_residual_max": max(i.rel_residual for i in ii)}
+        out["variants"] = side
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, frames[0], args.tol)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

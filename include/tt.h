@@ -127,6 +127,9 @@ typedef struct {
     int status;                   /* tt_status of the solve */
     double rel_residual;          /* last FP64 ||s - A zeta|| / ||s|| (true residual) */
     double recursive_residual;    /* last recursive ||r|| / ||s|| of the inner CG */
+    double kernel_ms;             /* device time of the persistent solver launches, measured
+                                     with events on the context stream (0 for TT_SOLVER_KERNELS) */
+    int kernel_launches;          /* persistent solver launches (1 + replacements) */
 } tt_solve_info;
 
 /* Sizes of a configured system. */

@@ -114,6 +114,22 @@ def xi_prime_table(wl, k, g, p, n_prime, beta=None):
     return wl.w[k] * f(ox, oy, s * wl.d, wl.r0, wl.L0)
 
 
+def _xi_job(args):
+    wl, k, q, n_prime = args
+    return (k, q), xi_prime_table(wl, k, q // 2, q % 2, n_prime)
+
+
+def xi_prime_tables(wl, n_prime=None, workers=1):
+    """dict (k, q) -> unique elements of every Xi'_{q,k}; workers > 1 uses a process pool."""
+    n_prime = new_grid_size(wl) if n_prime is None else n_prime
+    jobs = [(wl, k, q, n_prime) for k in range(wl.n_layer) for q in range(2 * wl.n_gs)]
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            return dict(pool.map(_xi_job, jobs, chunksize=4))
+    return dict(_xi_job(j) for j in jobs)
+
+
 def default_proj_pad(n, n_prime):
     m = n_prime + n - 1
     return m + (m & 1)

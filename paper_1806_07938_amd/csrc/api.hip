@@ -115,6 +115,7 @@ tt_status set_system_impl(tt_ctx* c, const tt_kernels* k, const double* noise_va
     TT_CHECK(use_device(c->device));
     c->ready = false;
     c->proj.on = false;
+    c->tile_S = 0;
     c->n = k->n;
     c->G = k->n_gs;
     c->C = 2 * k->n_gs;

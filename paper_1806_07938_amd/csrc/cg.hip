@@ -19,20 +19,7 @@
 
 tt_status matvec_prepare(tt_ctx& c);
 
-struct CgScalars {
-    double rr[2];     // r.r of the current iterate, slot (iteration & 1)
-    double rr_max;    // r.r at the last replacement
-    double tol2;      // tol^2 ||s||^2
-    double drop2;     // refine_drop^2 (0: no replacement trigger)
-    double bnorm2;    // ||s||^2
-    double rr_true;   // last FP64 true residual
-    double pAp;       // last p.Ap
-    int state;        // 0 running, 1 replacement due, 2 recursive residual converged,
-                      // 3 breakdown, 4 iteration cap
-    int iter;         // iterations done
-};
-
-enum { ST_RUN = 0, ST_REFINE = 1, ST_CONV = 2, ST_BREAK = 3, ST_CAP = 4 };
+#include "cg_common.h"
 
 namespace {
 
@@ -205,11 +192,11 @@ __global__ void k_update_p(R* __restrict__ p, const R* __restrict__ r, const dou
 
 unsigned vec_blocks(long n) { return std::min<unsigned>(cdiv(n, NT), 1024u); }
 
-// r64 = s - A x64 (FP64 operator); S->rr_true = r64.r64 ; also copies partials for restart
+// r64 = s - A x64 (FP64 operator, scratch aux64); S->rr_true = r64.r64; partials left in part
 tt_status true_residual(tt_ctx& c, const float* s, CgScalars* S) {
     const long n = c.n_slopes;
-    TT_CHECK(matvec_f64(c, c.x64.p, c.q64.p, nullptr));
-    hipLaunchKernelGGL(k_resid, dim3(vec_blocks(n)), dim3(NT), 0, c.stream, s, c.q64.p, c.r64.p, n);
+    TT_CHECK(matvec_f64(c, c.x64.p, c.aux64.p, nullptr));
+    hipLaunchKernelGGL(k_resid, dim3(vec_blocks(n)), dim3(NT), 0, c.stream, s, c.aux64.p, c.r64.p, n);
     hipLaunchKernelGGL((k_dot_partial<double, double>), dim3(vec_blocks(n)), dim3(NT), 0, c.stream, c.r64.p,
                        c.r64.p, n, c.part.p);
     hipLaunchKernelGGL(k_set_true, dim3(1), dim3(NT), 0, c.stream, c.part.p, (int)vec_blocks(n), S);
@@ -229,9 +216,10 @@ tt_status cg_alloc(tt_ctx& c) {
     TT_CHECK(c.r64.alloc(n));
     TT_CHECK(c.p64.alloc(n));
     TT_CHECK(c.q64.alloc(n));
+    TT_CHECK(c.aux64.alloc(n));
     const size_t np = std::max<size_t>((size_t)c.C * c.n, 1024) + 1024;
     TT_CHECK(c.part.alloc(np * 2));
-    TT_CHECK(c.scal.alloc(16));
+    TT_CHECK(c.scal.alloc(64));
     TT_CHECK(c.bar.alloc(64));
     TT_HIP(hipMemsetAsync(c.bar.p, 0, 64 * sizeof(unsigned), c.stream));
     return matvec_prepare(c);
@@ -247,8 +235,8 @@ tt_status cg_setup(tt_ctx& c, const float* s, const double* x0, const tt_solve_o
     hipLaunchKernelGGL((k_dot_partial<float, float>), dim3(nb), dim3(NT), 0, c.stream, s, s, n, part_s);
     if (x0) {
         hipLaunchKernelGGL(k_copy<double>, dim3(nb), dim3(NT), 0, c.stream, x0, c.x64.p, n);
-        TT_CHECK(matvec_f64(c, c.x64.p, c.q64.p, nullptr));
-        hipLaunchKernelGGL(k_resid, dim3(nb), dim3(NT), 0, c.stream, s, c.q64.p, c.r64.p, n);
+        TT_CHECK(matvec_f64(c, c.x64.p, c.aux64.p, nullptr));
+        hipLaunchKernelGGL(k_resid, dim3(nb), dim3(NT), 0, c.stream, s, c.aux64.p, c.r64.p, n);
     } else {
         hipLaunchKernelGGL(k_fill<double>, dim3(nb), dim3(NT), 0, c.stream, c.x64.p, 0.0, n);
         hipLaunchKernelGGL(k_copy_f2d, dim3(nb), dim3(NT), 0, c.stream, s, c.r64.p, n);
@@ -389,8 +377,27 @@ tt_status solve_kernels(tt_ctx& c, const float* s, const double* x0, double* zet
     return cg_finish(c, s, zeta, f32, have_true, info, code);
 }
 
-// Persistent solver placeholder until persistent.hip provides it.
-tt_status solve_persistent(tt_ctx& c, const float* s, const double* x0, double* zeta, const tt_solve_opts& o,
-                           tt_solve_info& info) {
-    return solve_kernels(c, s, x0, zeta, o, info);
+tt_status cg_true_residual(tt_ctx& c, const float* s, bool f32, CgScalars* hS) {
+    const long n = c.n_slopes;
+    CgScalars* S = cg_scalars(c);
+    if (f32) hipLaunchKernelGGL(k_fold_x, dim3(vec_blocks(n)), dim3(NT), 0, c.stream, c.x64.p, c.x32.p, n);
+    TT_CHECK(true_residual(c, s, S));
+    TT_HIP(hipMemcpyAsync(hS, S, sizeof(CgScalars), hipMemcpyDeviceToHost, c.stream));
+    TT_HIP(hipStreamSynchronize(c.stream));
+    return TT_OK;
+}
+
+tt_status cg_fill_zero(tt_ctx& c, float* a32, double* a64) {
+    const long n = c.n_slopes;
+    if (a32) hipLaunchKernelGGL(k_fill<float>, dim3(vec_blocks(n)), dim3(NT), 0, c.stream, a32, 0.0f, n);
+    if (a64) hipLaunchKernelGGL(k_fill<double>, dim3(vec_blocks(n)), dim3(NT), 0, c.stream, a64, 0.0, n);
+    TT_HIP(hipGetLastError());
+    return TT_OK;
+}
+
+tt_status cg_copy_r64_to_r32(tt_ctx& c) {
+    const long n = c.n_slopes;
+    hipLaunchKernelGGL(k_copy_d2f, dim3(vec_blocks(n)), dim3(NT), 0, c.stream, c.r64.p, c.r32.p, n);
+    TT_HIP(hipGetLastError());
+    return TT_OK;
 }

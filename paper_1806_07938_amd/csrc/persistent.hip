@@ -1,0 +1,624 @@
+// Persistent CG solver (TT_SOLVER_PERSISTENT): one cooperative launch runs CG
+// iterations until convergence, a residual-replacement point, the iteration
+// cap or a breakdown.  Rows a3-a8 of the hot path in one kernel.
+//
+// CG form.  The single-reduction rearrangement of CG (Chronopoulos & Gear,
+// J. Comput. Appl. Math. 25 (1989)) computes both inner products of an
+// iteration after one matrix-vector product with the residual:
+//
+//   w_i = A r_i,  gamma_i = r_i.r_i,  delta_i = r_i.w_i,
+//   beta_i = gamma_i / gamma_{i-1} (0 at a start),
+//   alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1})  (gamma_i/delta_i at a start),
+//   p_i = r_i + beta_i p_{i-1},  s_i = w_i + beta_i s_{i-1}   (s_i = A p_i),
+//   x_{i+1} = x_i + alpha_i p_i,  r_{i+1} = r_i - alpha_i s_i.
+//
+// In exact arithmetic it produces the iterates of textbook CG (§2.G).  After an
+// FP64 residual replacement the recurrences restart (beta = 0, p = s = 0).
+//
+// The product A r is the fused 2RBT product of §2.E, split in two phases
+// separated by grid barriers (two barriers per iteration):
+//   row phase    (rows (c, a) of the n x n grids, up to RB rows per block at
+//                a time): inverse row transform of the column-phase output ->
+//                w = A r (+ sigma^2 r); vector updates; forward row transform of
+//                the new residual -> T[f2][c][a]; partial r.r and sigma^2 r.r;
+//   column phase (block = one f2 column and one of S ranges of f1):
+//                forward column transform of the C channels, per-frequency
+//                Hermitian products summed over input channels, partial inverse
+//                column transform -> U[f2][part][c][a], and the partial of
+//                r.(Sigma_ss r) by Parseval: r.C r = L^-2 sum_f w(f2) Re(X~^H Y~),
+//                valid because r vanishes outside the n x n corner.
+// Each block keeps its transform tiles (its f1 range of the column DFT matrix
+// in both orientations, the row DFT matrix) and its share of the packed
+// spectra in LDS for the whole launch when they fit (FP32 at the 74x74 size),
+// so the iteration reads no spectra from memory; otherwise the same tiles are
+// read from global memory.  Loops are laid out so that consecutive lanes read
+// consecutive LDS words.
+//
+// Barrier: two-level counters (per XCD, then global), see grid_sync.  Every
+// poll has a 2 s wall-clock limit and honours an abort word, so every wave
+// exits.  All blocks sum the partial arrays in the same order and take the same
+// decision at the top of every iteration.
+#include "cg_common.h"
+
+namespace {
+
+constexpr int PT = 512;                                  // threads per block
+constexpr int RB = 4;                                    // rows per block at a time
+constexpr unsigned long long SPIN_TICKS = 200000000ull;  // 2 s of the 100 MHz wall clock
+
+template <typename R>
+struct PArgs {
+    int n, C, G, L, Lh, n_vs, S, Lrm, nrows, nwg;
+    int it0, max_iter, first;
+    double gprev, aprev, gmax;
+    const int* vmap;
+    const R* M;              // packed spectra [f2][f1][3G^2]
+    const cplx<R>* Fa;       // [S][n][Lrm]  exp(-2 pi i f1 a / L), f1 = f1a(part) + j
+    const cplx<R>* Fb;       // [S][Lrm][n]  the same values, a fastest
+    const cplx<R>* Gr;       // [Lh][n]      exp(+2 pi i f2 b / L)
+    const R* noise;
+    R *x, *r, *p, *s;
+    cplx<R>* T;              // [f2][c][a]
+    cplx<R>* U;              // [f2][part][c][a]
+    double* pg;              // [2][nwg]  partial r.r
+    double* ps;              // [2][nwg]  partial sigma^2 r.r
+    double* pd;              // [nwg]     partial r.C r
+    CgScalars* S_;
+    PScalars* P;
+    unsigned* bar;           // barrier words: [0] top counter, [16] abort, [32 + 32 g] group counters
+};
+
+// Two-level grid barrier.  Blocks are dispatched round-robin over the 8 XCDs,
+// so block i joins group i % 8 (one L2 each).  Thread 0 of every block: agent
+// release fence, relaxed increment of its group counter; the last arriver of a
+// group increments the top counter; all poll the top counter with relaxed loads
+// (2 s wall-clock limit, abort word) and finish with an agent acquire fence.
+// Counters grow monotonically within a launch (reset before it).
+constexpr unsigned NGRP = 8;
+
+__device__ bool grid_sync(unsigned* bar, unsigned nwg, unsigned& epoch, int* s_flag) {
+    __syncthreads();
+    ++epoch;
+    if (threadIdx.x == 0) {
+        unsigned* top = bar;
+        unsigned* abort_w = bar + 16;
+        unsigned* grp = bar + 32;
+        const unsigned g = blockIdx.x % NGRP;
+        const unsigned ng = nwg < NGRP ? nwg : NGRP;
+        const unsigned gsz = (nwg - g + NGRP - 1) / NGRP;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned old = __hip_atomic_fetch_add(&grp[g * 32], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == epoch * gsz - 1u) __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 1;
+        const unsigned long long t0 = wall_clock64();
+        while (__hip_atomic_load(top, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch * ng) {
+            if (__hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                ok = 0;
+                break;
+            }
+            if (wall_clock64() - t0 > SPIN_TICKS) {
+                __hip_atomic_store(abort_w, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *s_flag = ok;
+    }
+    __syncthreads();
+    return *s_flag != 0;
+}
+
+__device__ double block_sum(double v, double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = PT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ double sum_all(const double* part, int np, double* red) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < np; i += PT) v += part[i];
+    return block_sum(v, red);
+}
+
+template <typename R>
+struct Tiles {
+    const cplx<R>* Fa;
+    const cplx<R>* Fb;
+    const cplx<R>* Gr;
+    const R* Ms;       // resident: [slot][Lrm]; else null
+    const R* Mg;       // global: M + f2 L P (used when Ms is null)
+    cplx<R>* work;
+};
+
+template <typename R>
+__device__ inline R mval(const Tiles<R>& t, int slot, int j, int Lrm, int f1a, int P) {
+    return t.Ms ? t.Ms[slot * Lrm + j] : t.Mg[(long)(f1a + j) * P + slot];
+}
+
+// Hermitian block (g, h) of the per-frequency matrix at local frequency j:
+// (xx, xy = yx, yy) as complex values.
+template <typename R>
+__device__ inline void mblock(const Tiles<R>& t, int g, int h, int j, int G, int Lrm, int f1a, cplx<R>* m3) {
+    const int P = 3 * G * G;
+    if (g == h) {
+        for (int k = 0; k < 3; ++k) m3[k] = cplx<R>{mval(t, 3 * g + k, j, Lrm, f1a, P), R(0)};
+    } else {
+        const int lo = g < h ? g : h, hi = g < h ? h : g;
+        const int base = 3 * G + 6 * (lo * (2 * G - lo - 1) / 2 + (hi - lo - 1));
+        const R sg = g < h ? R(1) : R(-1);
+        for (int k = 0; k < 3; ++k)
+            m3[k] = cplx<R>{mval(t, base + 2 * k, j, Lrm, f1a, P), sg * mval(t, base + 2 * k + 1, j, Lrm, f1a, P)};
+    }
+}
+
+template <typename R>
+__device__ void row_phase(const PArgs<R>& a, const Tiles<R>& t, bool update, R alpha, R beta, int par, double* red) {
+    const int n = a.n, Lh = a.Lh, L = a.L, C = a.C, S = a.S;
+    cplx<R>* Us = t.work;                       // [RB][Lh]
+    R* xs = reinterpret_cast<R*>(Us + RB * Lh); // [RB][n]
+    const R inv = R(1) / (R(L) * R(L));
+    const bool even = (L % 2) == 0;
+    double accg = 0.0, accs = 0.0;
+    for (int base = blockIdx.x; base < a.nrows; base += RB * a.nwg) {
+        int nrk = 0;
+        while (nrk < RB && base + nrk * a.nwg < a.nrows) ++nrk;
+        __syncthreads();
+        if (update) {
+            for (int i = threadIdx.x; i < nrk * Lh; i += PT) {
+                const int k = i / Lh, f2 = i % Lh;
+                const int row = base + k * a.nwg;
+                const int c = row / n, ra = row % n;
+                cplx<R> u{0, 0};
+                for (int part = 0; part < S; ++part) {
+                    const cplx<R> v = a.U[(((long)f2 * S + part) * C + c) * n + ra];
+                    u.x += v.x;
+                    u.y += v.y;
+                }
+                Us[k * Lh + f2] = u;
+            }
+            __syncthreads();
+        }
+        for (int i = threadIdx.x; i < nrk * n; i += PT) {
+            const int k = i / n, b = i % n;
+            const int row = base + k * a.nwg;
+            const int c = row / n, ra = row % n;
+            const int v = a.vmap[ra * n + b];
+            R rn = 0;
+            if (v >= 0) {
+                const long gi = (long)c * a.n_vs + v;
+                const R ro = a.r[gi];
+                if (update) {
+                    const cplx<R>* us = Us + k * Lh;
+                    R sacc = us[0].x;
+                    for (int f2 = 1; f2 < Lh; ++f2) {
+                        const cplx<R> u = us[f2];
+                        const cplx<R> w = t.Gr[f2 * n + b];
+                        const R wt = (even && 2 * f2 == L) ? R(1) : R(2);
+                        sacc += wt * (u.x * w.x - u.y * w.y);
+                    }
+                    const R wv = sacc * inv + a.noise[gi] * ro;
+                    const R pv = ro + beta * a.p[gi];
+                    const R sv = wv + beta * a.s[gi];
+                    a.p[gi] = pv;
+                    a.s[gi] = sv;
+                    a.x[gi] += alpha * pv;
+                    rn = ro - alpha * sv;
+                    a.r[gi] = rn;
+                } else {
+                    rn = ro;
+                }
+                accg += (double)rn * (double)rn;
+                accs += (double)a.noise[gi] * (double)rn * (double)rn;
+            }
+            xs[k * n + b] = rn;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < nrk * Lh; i += PT) {
+            const int k = i / Lh, f2 = i % Lh;
+            const int row = base + k * a.nwg;
+            const int c = row / n, ra = row % n;
+            const R* xr = xs + k * n;
+            const cplx<R>* g = t.Gr + f2 * n;
+            R re = 0, im = 0;
+            for (int b = 0; b < n; ++b) {
+                const cplx<R> w = g[b];
+                re += xr[b] * w.x;
+                im -= xr[b] * w.y;
+            }
+            a.T[((long)f2 * C + c) * n + ra] = cplx<R>{re, im};
+        }
+    }
+    const double gs = block_sum(accg, red);
+    const double ss = block_sum(accs, red);
+    if (threadIdx.x == 0) {
+        a.pg[par * a.nwg + blockIdx.x] = gs;
+        a.ps[par * a.nwg + blockIdx.x] = ss;
+    }
+}
+
+template <typename R>
+__device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, double* red) {
+    const int n = a.n, L = a.L, C = a.C, G = a.G, S = a.S, Lrm = a.Lrm;
+    double accd = 0.0;
+    if (blockIdx.x < a.Lh * S) {
+        const int f2 = blockIdx.x / S, part = blockIdx.x % S;
+        const int f1a = (int)((long)part * L / S), f1b = (int)((long)(part + 1) * L / S);
+        const int Lr = f1b - f1a;
+        cplx<R>* Tc = t.work;          // [C][n]
+        cplx<R>* Xh = Tc + C * n;      // [C][Lrm]
+        cplx<R>* Yh = Xh + C * Lrm;    // [C][Lrm]
+        __syncthreads();
+        for (int i = threadIdx.x; i < C * n; i += PT) Tc[i] = a.T[(long)f2 * C * n + i];
+        __syncthreads();
+        // forward column transform, two channels per lane
+        for (int i = threadIdx.x; i < (C / 2) * Lr; i += PT) {
+            const int cp = i / Lr, j = i % Lr;
+            const cplx<R>* t0 = Tc + (2 * cp) * n;
+            const cplx<R>* t1 = t0 + n;
+            R r0 = 0, i0 = 0, r1 = 0, i1 = 0;
+            for (int ra = 0; ra < n; ++ra) {
+                const cplx<R> f = t.Fa[ra * Lrm + j];
+                const cplx<R> u0 = t0[ra], u1 = t1[ra];
+                r0 += u0.x * f.x - u0.y * f.y;
+                i0 += u0.x * f.y + u0.y * f.x;
+                r1 += u1.x * f.x - u1.y * f.y;
+                i1 += u1.x * f.y + u1.y * f.x;
+            }
+            Xh[(2 * cp) * Lrm + j] = cplx<R>{r0, i0};
+            Xh[(2 * cp + 1) * Lrm + j] = cplx<R>{r1, i1};
+        }
+        __syncthreads();
+        // per-frequency products, x and y outputs of one sensor per lane
+        const double wt2 = ((f2 == 0) || ((L % 2) == 0 && 2 * f2 == L)) ? 1.0 : 2.0;
+        for (int i = threadIdx.x; i < G * Lr; i += PT) {
+            const int g = i / Lr, j = i % Lr;
+            R y0r = 0, y0i = 0, y1r = 0, y1i = 0;
+            for (int h = 0; h < G; ++h) {
+                cplx<R> m3[3];
+                mblock(t, g, h, j, G, Lrm, f1a, m3);
+                const cplx<R> xa = Xh[(2 * h) * Lrm + j], xb = Xh[(2 * h + 1) * Lrm + j];
+                y0r += m3[0].x * xa.x - m3[0].y * xa.y + m3[1].x * xb.x - m3[1].y * xb.y;
+                y0i += m3[0].x * xa.y + m3[0].y * xa.x + m3[1].x * xb.y + m3[1].y * xb.x;
+                y1r += m3[1].x * xa.x - m3[1].y * xa.y + m3[2].x * xb.x - m3[2].y * xb.y;
+                y1i += m3[1].x * xa.y + m3[1].y * xa.x + m3[2].x * xb.y + m3[2].y * xb.x;
+            }
+            Yh[(2 * g) * Lrm + j] = cplx<R>{y0r, y0i};
+            Yh[(2 * g + 1) * Lrm + j] = cplx<R>{y1r, y1i};
+            const cplx<R> x0 = Xh[(2 * g) * Lrm + j], x1 = Xh[(2 * g + 1) * Lrm + j];
+            accd += wt2 * ((double)x0.x * y0r + (double)x0.y * y0i + (double)x1.x * y1r + (double)x1.y * y1i);
+        }
+        __syncthreads();
+        // partial inverse column transform over this f1 range, two channels per lane
+        for (int i = threadIdx.x; i < (C / 2) * n; i += PT) {
+            const int pp = i / n, ra = i % n;
+            const cplx<R>* y0 = Yh + (2 * pp) * Lrm;
+            const cplx<R>* y1 = y0 + Lrm;
+            R r0 = 0, i0 = 0, r1 = 0, i1 = 0;
+            for (int j = 0; j < Lr; ++j) {
+                const cplx<R> f = t.Fb[j * n + ra];   // conj(f) is the inverse twiddle
+                const cplx<R> u0 = y0[j], u1 = y1[j];
+                r0 += u0.x * f.x + u0.y * f.y;
+                i0 += u0.y * f.x - u0.x * f.y;
+                r1 += u1.x * f.x + u1.y * f.y;
+                i1 += u1.y * f.x - u1.x * f.y;
+            }
+            cplx<R>* Uo = a.U + (((long)f2 * S + part) * C) * n;
+            Uo[(2 * pp) * n + ra] = cplx<R>{r0, i0};
+            Uo[(2 * pp + 1) * n + ra] = cplx<R>{r1, i1};
+        }
+    }
+    const double d = block_sum(accd, red);
+    if (threadIdx.x == 0) a.pd[blockIdx.x] = d / ((double)a.L * (double)a.L);
+}
+
+template <typename R, bool RES>
+__global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
+    extern __shared__ __align__(16) char smem_raw[];
+    __shared__ double red[PT];
+    __shared__ int s_flag;
+    const int n = a.n, Lh = a.Lh, Lrm = a.Lrm, S = a.S, L = a.L, P = 3 * a.G * a.G;
+    const bool colunit = blockIdx.x < Lh * S;
+    const int f2 = colunit ? blockIdx.x / S : 0, part = colunit ? blockIdx.x % S : 0;
+    const int f1a = (int)((long)part * L / S), f1b = (int)((long)(part + 1) * L / S);
+    Tiles<R> t;
+    t.Mg = a.M + (long)f2 * L * P;
+    if constexpr (RES) {
+        cplx<R>* Fa = reinterpret_cast<cplx<R>*>(smem_raw);
+        cplx<R>* Fb = Fa + n * Lrm;
+        cplx<R>* Gr = Fb + Lrm * n;
+        R* Ms = reinterpret_cast<R*>(Gr + Lh * n);
+        const cplx<R>* fa = a.Fa + (long)part * n * Lrm;
+        const cplx<R>* fb = a.Fb + (long)part * Lrm * n;
+        for (int i = threadIdx.x; i < n * Lrm; i += PT) {
+            Fa[i] = fa[i];
+            Fb[i] = fb[i];
+        }
+        for (int i = threadIdx.x; i < Lh * n; i += PT) Gr[i] = a.Gr[i];
+        const int Lr = f1b - f1a;
+        if (colunit)
+            for (int i = threadIdx.x; i < P * Lr; i += PT) {
+                const int slot = i / Lr, j = i % Lr;
+                Ms[slot * Lrm + j] = t.Mg[(long)(f1a + j) * P + slot];
+            }
+        t.Fa = Fa;
+        t.Fb = Fb;
+        t.Gr = Gr;
+        t.Ms = Ms;
+        t.work = reinterpret_cast<cplx<R>*>(Ms + P * Lrm);
+        __syncthreads();
+    } else {
+        t.Fa = a.Fa + (long)part * n * Lrm;
+        t.Fb = a.Fb + (long)part * Lrm * n;
+        t.Gr = a.Gr;
+        t.Ms = nullptr;
+        t.work = reinterpret_cast<cplx<R>*>(smem_raw);
+    }
+    unsigned epoch = 0;
+    int it = a.it0;
+    row_phase<R>(a, t, false, R(0), R(0), it & 1, red);
+    if (!grid_sync(a.bar, a.nwg, epoch, &s_flag)) return;
+    col_phase<R>(a, t, red);
+    if (!grid_sync(a.bar, a.nwg, epoch, &s_flag)) return;
+    double gprev = a.gprev, aprev = a.aprev;
+    bool first = a.first != 0;
+    const double tol2 = a.S_->tol2, drop2 = a.S_->drop2;
+    while (true) {
+        const int par = it & 1;
+        const double g = sum_all(a.pg + par * a.nwg, a.nwg, red);
+        const double sg = sum_all(a.ps + par * a.nwg, a.nwg, red);
+        const double dl = sum_all(a.pd, a.nwg, red) + sg;
+        int st = ST_RUN;
+        double alpha = 0.0, beta = 0.0;
+        if (!isfinite(g) || !isfinite(dl)) st = ST_BREAK;
+        else if (g <= tol2) st = ST_CONV;
+        else if (drop2 > 0.0 && g < drop2 * a.gmax) st = ST_REFINE;
+        else if (it >= a.max_iter) st = ST_CAP;
+        if (st == ST_RUN) {
+            if (first) {
+                beta = 0.0;
+                alpha = g / dl;
+            } else {
+                beta = g / gprev;
+                alpha = g / (dl - beta * g / aprev);
+            }
+            if (!(alpha > 0.0) || !isfinite(alpha)) st = ST_BREAK;
+        }
+        if (st != ST_RUN) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                a.P->gamma_prev = gprev;
+                a.P->alpha_prev = aprev;
+                a.P->gamma = g;
+                a.P->delta = dl;
+                a.P->first = first ? 1 : 0;
+                a.S_->state = st;
+                a.S_->iter = it;
+                a.S_->rr[it & 1] = g;
+            }
+            return;
+        }
+        row_phase<R>(a, t, true, (R)alpha, (R)beta, (it + 1) & 1, red);
+        gprev = g;
+        aprev = alpha;
+        first = false;
+        ++it;
+        if (!grid_sync(a.bar, a.nwg, epoch, &s_flag)) return;
+        col_phase<R>(a, t, red);
+        if (!grid_sync(a.bar, a.nwg, epoch, &s_flag)) return;
+    }
+}
+
+// LDS bytes: resident tiles (if RES) + work region (max of column and row needs)
+template <typename R>
+size_t lds_bytes(const tt_ctx& c, int Lrm, bool res) {
+    const size_t cs = sizeof(cplx<R>);
+    const size_t colw = cs * ((size_t)c.C * c.n + 2ull * c.C * Lrm);
+    const size_t roww = cs * (size_t)RB * c.Lh + sizeof(R) * (size_t)RB * c.n;
+    size_t b = std::max(colw, roww);
+    if (res) b += cs * (2ull * c.n * Lrm + (size_t)c.Lh * c.n) + sizeof(R) * (size_t)packed_reals(c.G) * Lrm;
+    return b;
+}
+
+// Host-built transform tiles for the persistent kernel (exact twiddle indices).
+template <typename R>
+tt_status build_tiles(tt_ctx& c, int S, int Lrm) {
+    const int n = c.n, L = c.L, Lh = c.Lh;
+    std::vector<double> co(L), si(L);
+    for (int k = 0; k < L; ++k) {
+        const double ang = 2.0 * M_PI * (double)k / (double)L;
+        co[k] = std::cos(ang);
+        si[k] = std::sin(ang);
+    }
+    std::vector<cplx<R>> fa((size_t)S * n * Lrm, cplx<R>{0, 0}), fb((size_t)S * Lrm * n, cplx<R>{0, 0}),
+        gr((size_t)Lh * n);
+    for (int part = 0; part < S; ++part) {
+        const int f1a = (int)((long)part * L / S), f1b = (int)((long)(part + 1) * L / S);
+        for (int j = 0; j < f1b - f1a; ++j)
+            for (int a = 0; a < n; ++a) {
+                const int m = (int)(((long)(f1a + j) * a) % L);
+                const cplx<R> v{(R)co[m], (R)(-si[m])};   // exp(-2 pi i f1 a / L)
+                fa[((size_t)part * n + a) * Lrm + j] = v;
+                fb[((size_t)part * Lrm + j) * n + a] = v;
+            }
+    }
+    for (int f2 = 0; f2 < Lh; ++f2)
+        for (int b = 0; b < n; ++b) {
+            const int m = (int)(((long)f2 * b) % L);
+            gr[(size_t)f2 * n + b] = cplx<R>{(R)co[m], (R)si[m]};   // exp(+2 pi i f2 b / L)
+        }
+    const size_t sc = sizeof(cplx<R>);
+    TT_CHECK(c.tFa.alloc(fa.size() * sc / sizeof(c64) + 1));
+    TT_CHECK(c.tFb.alloc(fb.size() * sc / sizeof(c64) + 1));
+    TT_CHECK(c.tGr.alloc(gr.size() * sc / sizeof(c64) + 1));
+    TT_HIP(hipMemcpyAsync(c.tFa.p, fa.data(), fa.size() * sc, hipMemcpyHostToDevice, c.stream));
+    TT_HIP(hipMemcpyAsync(c.tFb.p, fb.data(), fb.size() * sc, hipMemcpyHostToDevice, c.stream));
+    TT_HIP(hipMemcpyAsync(c.tGr.p, gr.data(), gr.size() * sc, hipMemcpyHostToDevice, c.stream));
+    TT_HIP(hipStreamSynchronize(c.stream));
+    return TT_OK;
+}
+
+template <typename R, bool RES>
+tt_status launch(tt_ctx& c, PArgs<R>& a, size_t lds, float* ms) {
+    TT_HIP(hipMemsetAsync(c.bar.p, 0, c.bar.n * sizeof(unsigned), c.stream));
+    void* args[] = {&a};
+    TT_HIP(hipEventRecord(c.ev0, c.stream));
+    TT_HIP(hipLaunchCooperativeKernel((const void*)k_cg_persistent<R, RES>, dim3(a.nwg), dim3(PT), args,
+                                      (unsigned)lds, c.stream));
+    TT_HIP(hipEventRecord(c.ev1, c.stream));
+    TT_HIP(hipEventSynchronize(c.ev1));
+    TT_HIP(hipEventElapsedTime(ms, c.ev0, c.ev1));
+    unsigned ab = 0;
+    TT_HIP(hipMemcpy(&ab, a.bar + 16, sizeof(ab), hipMemcpyDeviceToHost));
+    if (ab != 0u) {
+        tt_set_error("persistent solver: grid barrier timed out");
+        return TT_HIP_ERROR;
+    }
+    return TT_OK;
+}
+
+template <typename R, bool RES>
+tt_status run_persistent(tt_ctx& c, const float* s, double* zeta, const tt_solve_opts& o, tt_solve_info& info,
+                         PArgs<R>& a, size_t lds, CgScalars& h) {
+    const bool f32 = sizeof(R) == 4;
+    TT_HIP(hipFuncSetAttribute((const void*)k_cg_persistent<R, RES>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    int per_cu = 0;
+    TT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_cg_persistent<R, RES>, PT, lds));
+    if (per_cu < 1) {
+        tt_set_error("persistent solver does not fit on a compute unit");
+        return TT_INVALID_ARG;
+    }
+    int it = 0, first = 1;
+    double gprev = 0.0, aprev = 0.0, gmax = h.rr_true;
+    int code = TT_OK;
+    bool have_true = false;
+    while (true) {
+        a.it0 = it;
+        a.first = first;
+        a.gprev = gprev;
+        a.aprev = aprev;
+        a.gmax = gmax;
+        float ms = 0.f;
+        TT_CHECK((launch<R, RES>(c, a, lds, &ms)));
+        info.kernel_ms += ms;
+        info.kernel_launches++;
+        TT_HIP(hipMemcpy(&h, cg_scalars(c), sizeof(h), hipMemcpyDeviceToHost));
+        it = h.iter;
+        if (h.state == ST_BREAK) {
+            code = TT_BREAKDOWN;
+            break;
+        }
+        if (h.state == ST_CAP) {
+            code = TT_NOT_CONVERGED;
+            break;
+        }
+        // ST_CONV or ST_REFINE: certify / replace with the FP64 true residual
+        TT_CHECK(cg_true_residual(c, s, f32, &h));
+        have_true = true;
+        info.refinements++;
+        if (h.rr_true <= h.tol2) break;
+        if (it >= o.max_iter) {
+            code = TT_NOT_CONVERGED;
+            break;
+        }
+        if (f32) TT_CHECK(cg_copy_r64_to_r32(c));
+        // restart the recurrences from the replaced residual
+        TT_CHECK(cg_fill_zero(c, f32 ? (float*)a.p : nullptr, f32 ? nullptr : (double*)a.p));
+        TT_CHECK(cg_fill_zero(c, f32 ? (float*)a.s : nullptr, f32 ? nullptr : (double*)a.s));
+        gmax = h.rr_true;
+        first = 1;
+        gprev = aprev = 0.0;
+    }
+    return cg_finish(c, s, zeta, f32, have_true, info, code);
+}
+
+template <typename R>
+tt_status solve_persistent_t(tt_ctx& c, const float* s, const double* x0, double* zeta, const tt_solve_opts& o,
+                             tt_solve_info& info, R* x, R* r, R* p, R* sv, const R* M, const R* noise) {
+    const bool f32 = sizeof(R) == 4;
+    info = tt_solve_info{};
+    TT_CHECK(cg_setup(c, s, x0, o, f32));
+    TT_CHECK(cg_fill_zero(c, f32 ? (float*)p : nullptr, f32 ? nullptr : (double*)p));
+    TT_CHECK(cg_fill_zero(c, f32 ? (float*)sv : nullptr, f32 ? nullptr : (double*)sv));
+    CgScalars h;
+    TT_HIP(hipMemcpyAsync(&h, cg_scalars(c), sizeof(h), hipMemcpyDeviceToHost, c.stream));
+    TT_HIP(hipStreamSynchronize(c.stream));
+    if (h.bnorm2 == 0.0 || h.rr_true <= h.tol2) return cg_finish(c, s, zeta, f32, true, info, TT_OK);
+
+    // launch shape: one block per compute unit; the f1 axis split so that the
+    // Lh x S column units cover the blocks
+    const int nwg = c.num_cu;
+    int S = std::max(1, nwg / std::max(c.Lh, 1));
+    S = std::min(S, std::max(1, c.L / 8));
+    const int Lrm = (c.L + S - 1) / S;
+    const size_t lim = 160 * 1024 - PT * sizeof(double) - 256;   // minus the static LDS
+    const bool res = lds_bytes<R>(c, Lrm, true) <= lim;
+    const size_t lds = lds_bytes<R>(c, Lrm, res);
+    if (lds > lim) {
+        tt_set_error("persistent solver: system too large for LDS");
+        return TT_INVALID_ARG;
+    }
+    if (c.tile_S != S || c.tile_elem != (int)sizeof(R)) {
+        TT_CHECK(build_tiles<R>(c, S, Lrm));
+        c.tile_S = S;
+        c.tile_elem = (int)sizeof(R);
+    }
+    if (c.pU.n < (size_t)c.Lh * S * c.C * c.n) TT_CHECK(c.pU.alloc((size_t)c.Lh * S * c.C * c.n));
+    if (c.ppart.n < 5 * (size_t)nwg) TT_CHECK(c.ppart.alloc(5 * (size_t)nwg));
+    if (c.bar.n < 32 + 32 * NGRP) TT_CHECK(c.bar.alloc(32 + 32 * NGRP));
+
+    PArgs<R> a{};
+    a.nwg = nwg;
+    a.S = S;
+    a.Lrm = Lrm;
+    a.n = c.n;
+    a.C = c.C;
+    a.G = c.G;
+    a.L = c.L;
+    a.Lh = c.Lh;
+    a.n_vs = c.n_vs;
+    a.nrows = c.C * c.n;
+    a.max_iter = o.max_iter;
+    a.vmap = c.vmap.p;
+    a.M = M;
+    a.Fa = reinterpret_cast<const cplx<R>*>(c.tFa.p);
+    a.Fb = reinterpret_cast<const cplx<R>*>(c.tFb.p);
+    a.Gr = reinterpret_cast<const cplx<R>*>(c.tGr.p);
+    a.noise = noise;
+    a.x = x;
+    a.r = r;
+    a.p = p;
+    a.s = sv;
+    a.T = reinterpret_cast<cplx<R>*>(f32 ? (void*)c.T32.p : (void*)c.T64.p);
+    a.U = reinterpret_cast<cplx<R>*>(c.pU.p);
+    a.pg = c.ppart.p;
+    a.ps = c.ppart.p + 2 * nwg;
+    a.pd = c.ppart.p + 4 * nwg;
+    a.S_ = cg_scalars(c);
+    a.P = p_scalars(c);
+    a.bar = c.bar.p;
+    if (res) return run_persistent<R, true>(c, s, zeta, o, info, a, lds, h);
+    return run_persistent<R, false>(c, s, zeta, o, info, a, lds, h);
+}
+
+}  // namespace
+
+tt_status solve_persistent(tt_ctx& c, const float* s, const double* x0, double* zeta, const tt_solve_opts& o,
+                           tt_solve_info& info) {
+    if (!c.ev0) {
+        TT_HIP(hipEventCreate(&c.ev0));
+        TT_HIP(hipEventCreate(&c.ev1));
+    }
+    if (o.precision == TT_PREC_F32)
+        return solve_persistent_t<float>(c, s, x0, zeta, o, info, c.x32.p, c.r32.p, c.p32.p, c.q32.p, c.M32.p,
+                                         c.noise32.p);
+    return solve_persistent_t<double>(c, s, x0, zeta, o, info, c.x64.p, c.r64.p, c.p64.p, c.q64.p, c.M64.p,
+                                      c.noise64.p);
+}

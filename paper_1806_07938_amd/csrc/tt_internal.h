@@ -145,7 +145,12 @@ struct tt_ctx {
 
     // solver work buffers
     DevBuf<float> x32, r32, p32, q32;   // q = A p
-    DevBuf<double> x64, r64, p64, q64;
+    DevBuf<double> x64, r64, p64, q64, aux64;
+    DevBuf<double> ppart;               // persistent solver partial sums
+    DevBuf<c64> pU;                     // persistent solver column outputs [f2][split][C][n]
+    DevBuf<c64> tFa, tFb, tGr;          // persistent solver transform tiles
+    int tile_S = 0, tile_elem = 0;      // split and element size the tiles were built for
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
     DevBuf<double> part;                // per-block partial sums
     DevBuf<double> scal;                // solver scalars (see cg.hip)
     DevBuf<unsigned int> bar;           // grid barrier counters

@@ -60,7 +60,8 @@ class _SolveOpts(C.Structure):
 
 class _SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int), ("refinements", C.c_int), ("status", C.c_int),
-                ("rel_residual", C.c_double), ("recursive_residual", C.c_double)]
+                ("rel_residual", C.c_double), ("recursive_residual", C.c_double),
+                ("kernel_ms", C.c_double), ("kernel_launches", C.c_int)]
 
 
 class _SystemInfo(C.Structure):
@@ -135,6 +136,8 @@ class SolveInfo:
     status: int
     rel_residual: float
     recursive_residual: float
+    kernel_ms: float = 0.0
+    kernel_launches: int = 0
 
 
 class Kernels:
@@ -256,7 +259,7 @@ class Context:
                                    pphi, C.byref(opts), C.byref(inf))
         _check(st, allow=allow)
         return zeta, phi, SolveInfo(inf.iterations, inf.refinements, inf.status, inf.rel_residual,
-                                    inf.recursive_residual)
+                                    inf.recursive_residual, inf.kernel_ms, inf.kernel_launches)
 
     def project(self, zeta, phi=None):
         import torch

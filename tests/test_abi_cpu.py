@@ -1,0 +1,79 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/tt.h declares, and rejects bad arguments before touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tt.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tt_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1806_07938_amd import tt
+    return tt.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared()
+    assert "tt_solve_frame" in names and "tt_matvec" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    from paper_1806_07938_amd import tt
+    assert sorted(tt.EXPORTED) == names
+
+
+def test_status_strings(lib):
+    for code, name in enumerate(["TT_OK", "TT_INVALID_ARG", "TT_HIP_ERROR", "TT_OUT_OF_MEMORY",
+                                 "TT_NOT_CONVERGED", "TT_BREAKDOWN", "TT_NOT_READY"]):
+        assert lib.tt_status_string(code).decode() == name
+    assert lib.tt_status_string(99).decode() == "TT_UNKNOWN_STATUS"
+
+
+def test_null_arguments_rejected(lib):
+    from paper_1806_07938_amd import tt
+    assert lib.tt_create(None, 0, None) == tt.TT_INVALID_ARG
+    out = C.c_void_p()
+    assert lib.tt_generate_kernels(None, None, None, C.byref(out)) == tt.TT_INVALID_ARG
+    assert "NULL" in lib.tt_last_error().decode()
+    assert lib.tt_matvec(None, None, None) == tt.TT_INVALID_ARG
+    assert lib.tt_solve_frame(None, None, None, None, None, None, None) == tt.TT_INVALID_ARG
+    assert lib.tt_project(None, None, None) == tt.TT_INVALID_ARG
+    assert lib.tt_kernels_copy(None, None, 0) == tt.TT_INVALID_ARG
+    assert lib.tt_destroy(None) == tt.TT_OK
+    assert lib.tt_kernels_destroy(None) == tt.TT_OK
+
+
+def test_struct_layouts_match_header():
+    # field order and sizes of the ctypes mirrors agree with the C structs
+    from paper_1806_07938_amd import tt
+    text = open(HEADER).read()
+    for cname, py in (("tt_geometry", tt._Geometry), ("tt_atmosphere", tt._Atmosphere),
+                      ("tt_target", tt._Target), ("tt_solve_opts", tt._SolveOpts),
+                      ("tt_solve_info", tt._SolveInfo), ("tt_system_info", tt._SystemInfo)):
+        body = re.search(r"typedef struct \{((?:(?!typedef).)*?)\}\s*" + cname + ";", text, re.S).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        fields = []
+        for decl in body.split(";"):
+            decl = re.sub(r"\b(const|unsigned|char|int|double|size_t)\b|\*", " ", decl).strip()
+            fields += [nm.strip() for nm in decl.split(",") if nm.strip()]
+        assert [f for f, _ in py._fields_] == fields, cname
+
+
+def test_no_device_reports_error_not_crash(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    from paper_1806_07938_amd import tt
+    h = C.c_void_p()
+    st = lib.tt_create(C.byref(h), 0, None)
+    assert st in (tt.TT_HIP_ERROR, tt.TT_INVALID_ARG)
+    assert lib.tt_last_error().decode() != ""

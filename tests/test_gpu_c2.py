@@ -1,0 +1,113 @@
+"""GPU parity at the full 74x74, 6-LGS, 35-layer workload (47 664 slopes),
+in the launch configuration the benchmark times.
+
+The dense oracle does not fit here, so: covariance tables on sampled entries
+evaluated one by one; matrix-vector products and projections against the
+oracle's FP64 step-by-step 2RBT evaluation (itself pinned to the dense
+product on small grids); the solve through its FP64 true residual computed
+with the oracle's operator, never the library's."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_helpers import make_system, rel_maxabs, say, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+WORKERS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def c2():
+    wl = W.c2()
+    say("c2: building library system")
+    ctx, k = make_system(wl, target=True)
+    return wl, ctx, k
+
+
+@pytest.fixture(scope="module")
+def c2_oracle(c2):
+    from oracle.covariance import kernel_tables
+    from oracle.toeplitz import ToeplitzOperator
+    wl = c2[0]
+    say("c2: oracle tables with", WORKERS, "workers")
+    tabs = kernel_tables(wl, workers=WORKERS)
+    return ToeplitzOperator(wl, tables=tabs)
+
+
+def test_c2_sizes(c2):
+    wl, ctx, k = c2
+    info = ctx.info
+    assert info["n_vs"] == 3972 and info["n_slopes"] == 47664
+    assert info["n_prime"] == 106 and info["proj_pad_L"] == 180
+    assert info["spectra_bytes_f32"] == 148 * 75 * 108 * 4
+
+
+def test_c2_tables_sampled(c2):
+    from oracle.covariance import slope_pair_cov
+    wl, ctx, k = c2
+    say("c2 tables sampled")
+    got = k.tables()
+    rng = np.random.default_rng(0)
+    n, m = wl.n, 2 * wl.n - 1
+    pairs = [(g, h) for g in range(wl.n_gs) for h in range(g, wl.n_gs)]
+    comps = [(0, 0), (0, 1), (1, 1)]
+    worst = 0.0
+    scale = np.abs(got).max()
+    for _ in range(400):
+        pi = rng.integers(len(pairs))
+        ci = rng.integers(3)
+        v, u = rng.integers(m), rng.integers(m)
+        g, h = pairs[pi]
+        p, q = comps[ci]
+        rb = np.array([[(u - (n - 1)) * wl.d, (v - (n - 1)) * wl.d]])
+        ref = slope_pair_cov(wl, g, p, np.zeros((1, 2)), h, q, rb)[0]
+        worst = max(worst, abs(got[pi, ci, v, u] - ref) / scale)
+    assert worst < 1e-11
+
+
+def test_c2_matvec(c2, c2_oracle):
+    import torch
+    wl, ctx, k = c2
+    say("c2 matvec")
+    dev = torch_dev()
+    x = np.random.default_rng(5).standard_normal(wl.n_slopes)
+    ref = c2_oracle(x)
+    y64 = ctx.matvec_f64(torch.tensor(x, device=dev)).cpu().numpy()
+    assert rel_maxabs(y64, ref) < 1e-11
+    x32 = x.astype(np.float32)
+    y32 = ctx.matvec(torch.tensor(x32, device=dev)).cpu().numpy()
+    assert rel_maxabs(y32, c2_oracle(x32.astype(np.float64))) < 3e-6
+
+
+@pytest.mark.parametrize("solver", [0, 1])
+def test_c2_solve(c2, c2_oracle, solver):
+    import torch
+    wl, ctx, k = c2
+    say("c2 solve solver", solver)
+    dev = torch_dev()
+    s = W.turbulent_slopes(wl, seed=7)[0].astype(np.float32)
+    zeta, phi, info = ctx.solve(torch.tensor(s, device=dev), tol=1e-6, solver=solver)
+    z = zeta.cpu().numpy()
+    s64 = s.astype(np.float64)
+    res = np.linalg.norm(s64 - c2_oracle(z)) / np.linalg.norm(s64)
+    say("  iterations", info.iterations, "refinements", info.refinements, "lib relres", info.rel_residual,
+        "oracle relres", res)
+    assert info.status == 0
+    assert res <= 1.01e-6
+    assert abs(res - info.rel_residual) <= 1e-8
+
+
+def test_c2_projection(c2):
+    import torch
+    from oracle.projection import phi_paper_fft, xi_prime_tables
+    wl, ctx, k = c2
+    say("c2 projection")
+    dev = torch_dev()
+    z = np.random.default_rng(9).standard_normal(wl.n_slopes)
+    phi = ctx.project(torch.tensor(z, device=dev)).cpu().numpy()
+    tabs = xi_prime_tables(wl, workers=WORKERS)
+    ref = phi_paper_fft(wl, z.astype(np.float32).astype(np.float64), L=180, tables=tabs)
+    assert np.linalg.norm(phi - ref) / np.linalg.norm(ref) < 1e-5
