@@ -118,7 +118,7 @@ typedef struct {
     int solver;                   /* tt_solver_kind */
     double refine_drop;           /* TT_PREC_F32: FP64 residual replacement when the
                                      recursive residual fell by this factor since the
-                                     last one (0 -> 1e-2) */
+                                     last one (0 -> 1e-3) */
 } tt_solve_opts;
 
 typedef struct {

@@ -181,7 +181,7 @@ tt_status solve_impl(tt_ctx* c, const float* s, const double* x0, double* zeta, 
     o.max_iter = 20000;
     o.precision = TT_PREC_F32;
     o.solver = TT_SOLVER_PERSISTENT;
-    o.refine_drop = 1e-2;
+    o.refine_drop = 1e-3;
     if (opts) o = *opts;
     TT_REQUIRE(std::isfinite(o.tol) && o.tol >= 0, "tol must be >= 0");
     TT_REQUIRE(o.max_iter >= 0, "max_iter must be >= 0");

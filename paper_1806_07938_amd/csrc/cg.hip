@@ -243,7 +243,7 @@ tt_status cg_setup(tt_ctx& c, const float* s, const double* x0, const tt_solve_o
     }
     hipLaunchKernelGGL((k_dot_partial<double, double>), dim3(nb), dim3(NT), 0, c.stream, c.r64.p, c.r64.p, n,
                        part_r);
-    const double drop = f32 ? (o.refine_drop > 0 ? o.refine_drop : 1e-2) : 0.0;
+    const double drop = f32 ? (o.refine_drop > 0 ? o.refine_drop : 1e-3) : 0.0;
     hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(NT), 0, c.stream, part_s, part_r, (int)nb, S, o.tol, drop);
     if (f32) {
         hipLaunchKernelGGL(k_copy_d2f, dim3(nb), dim3(NT), 0, c.stream, c.r64.p, c.r32.p, n);

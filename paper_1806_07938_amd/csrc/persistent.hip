@@ -43,7 +43,6 @@
 namespace {
 
 constexpr int PT = 512;                                  // threads per block
-constexpr int RB = 4;                                    // rows per block at a time
 constexpr unsigned long long SPIN_TICKS = 200000000ull;  // 2 s of the 100 MHz wall clock
 
 template <typename R>
@@ -60,23 +59,29 @@ struct PArgs {
     R *x, *r, *p, *s;
     cplx<R>* T;              // [f2][c][a]
     cplx<R>* U;              // [f2][part][c][a]
-    double* pg;              // [2][nwg]  partial r.r
-    double* ps;              // [2][nwg]  partial sigma^2 r.r
-    double* pd;              // [nwg]     partial r.C r
+    double* part;            // [2][nwg][4]: partial r.r, sigma^2 r.r, r.C r (Parseval)
+    int vreg;                // CG vectors held in registers (rows per block * n <= threads)
+    int rbv;                 // rows per block at a time
     CgScalars* S_;
     PScalars* P;
     unsigned* bar;           // barrier words: [0] top counter, [16] abort, [32 + 32 g] group counters
 };
 
 // Two-level grid barrier.  Blocks are dispatched round-robin over the 8 XCDs,
-// so block i joins group i % 8 (one L2 each).  Thread 0 of every block: agent
-// release fence, relaxed increment of its group counter; the last arriver of a
-// group increments the top counter; all poll the top counter with relaxed loads
-// (2 s wall-clock limit, abort word) and finish with an agent acquire fence.
-// Counters grow monotonically within a launch (reset before it).
+// so block i joins group i % 8, the blocks sharing one L2.  Every wave first
+// drains its own memory operations (s_waitcnt 0: its stores are in the L2 of
+// its XCD, the L1 being write-through); thread 0 of every block then
+// increments its group counter.  The last arriver of a group issues one agent
+// release fence (write-back of that L2) and increments the top counter; every
+// block polls the top counter with relaxed loads (2 s wall-clock limit, abort
+// word) and finishes with an agent acquire fence.  One L2 write-back per XCD
+// instead of one per block.  Counters grow monotonically within a launch
+// (reset before it).  A stale read would show up as a failed FP64 true-residual
+// check after the launch, never as a silently accepted result.
 constexpr unsigned NGRP = 8;
 
 __device__ bool grid_sync(unsigned* bar, unsigned nwg, unsigned& epoch, int* s_flag) {
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     ++epoch;
     if (threadIdx.x == 0) {
@@ -86,9 +91,11 @@ __device__ bool grid_sync(unsigned* bar, unsigned nwg, unsigned& epoch, int* s_f
         const unsigned g = blockIdx.x % NGRP;
         const unsigned ng = nwg < NGRP ? nwg : NGRP;
         const unsigned gsz = (nwg - g + NGRP - 1) / NGRP;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const unsigned old = __hip_atomic_fetch_add(&grp[g * 32], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == epoch * gsz - 1u) __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == epoch * gsz - 1u) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         int ok = 1;
         const unsigned long long t0 = wall_clock64();
         while (__hip_atomic_load(top, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch * ng) {
@@ -110,22 +117,37 @@ __device__ bool grid_sync(unsigned* bar, unsigned nwg, unsigned& epoch, int* s_f
     return *s_flag != 0;
 }
 
-__device__ double block_sum(double v, double* red) {
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = PT / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    const double r = red[0];
-    __syncthreads();
-    return r;
+// Sum over the block with wave shuffles and one LDS pass; every lane gets the
+// same value, and the order of additions is fixed, so every block reduces
+// identical inputs to bit-identical results.
+__device__ inline double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
 }
 
-__device__ double sum_all(const double* part, int np, double* red) {
-    double v = 0.0;
-    for (int i = threadIdx.x; i < np; i += PT) v += part[i];
-    return block_sum(v, red);
+struct D3 {
+    double a, b, c;
+};
+
+__device__ D3 block_sum3(D3 v, double* red) {
+    v.a = wave_sum(v.a);
+    v.b = wave_sum(v.b);
+    v.c = wave_sum(v.c);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) {
+        red[w * 3] = v.a;
+        red[w * 3 + 1] = v.b;
+        red[w * 3 + 2] = v.c;
+    }
+    __syncthreads();
+    D3 r{0.0, 0.0, 0.0};
+    for (int i = 0; i < PT / 64; ++i) {
+        r.a += red[i * 3];
+        r.b += red[i * 3 + 1];
+        r.c += red[i * 3 + 2];
+    }
+    return r;
 }
 
 template <typename R>
@@ -159,52 +181,154 @@ __device__ inline void mblock(const Tiles<R>& t, int g, int h, int j, int G, int
     }
 }
 
+// State of one lane's grid point when the CG vectors live in registers.
 template <typename R>
-__device__ void row_phase(const PArgs<R>& a, const Tiles<R>& t, bool update, R alpha, R beta, int par, double* red) {
-    const int n = a.n, Lh = a.Lh, L = a.L, C = a.C, S = a.S;
-    cplx<R>* Us = t.work;                       // [RB][Lh]
-    R* xs = reinterpret_cast<R*>(Us + RB * Lh); // [RB][n]
-    const R inv = R(1) / (R(L) * R(L));
-    const bool even = (L % 2) == 0;
-    double accg = 0.0, accs = 0.0;
-    for (int base = blockIdx.x; base < a.nrows; base += RB * a.nwg) {
+struct Lane {
+    long gi;   // slope index, or -1 (no point / invalid subaperture)
+    R x, r, p, s, nz;
+};
+
+// Us[k][f2] = sum over f1 ranges of the column-phase outputs of row k
+template <typename R>
+__device__ void gather_u(const PArgs<R>& a, cplx<R>* Us, int base, int nrk) {
+    const int n = a.n, Lh = a.Lh, C = a.C, S = a.S;
+    for (int i = threadIdx.x; i < nrk * Lh; i += PT) {
+        const int k = i / Lh, f2 = i % Lh;
+        const int row = base + k * a.nwg;
+        const int c = row / n, ra = row % n;
+        const cplx<R>* u = a.U + ((long)f2 * S * C + c) * n + ra;
+        R ux = 0, uy = 0;
+        for (int part = 0; part < S; ++part) {
+            const cplx<R> q = u[(long)part * C * n];
+            ux += q.x;
+            uy += q.y;
+        }
+        Us[k * Lh + f2] = cplx<R>{ux, uy};
+    }
+}
+
+// sum_{f2} w(f2) Re(us[f2] exp(+2 pi i f2 b / L)), w = 1 at f2 = 0 and L/2, else 2
+template <typename R>
+__device__ inline R inv_row(const cplx<R>* us, const cplx<R>* Gr, int n, int b, int L, int Lh) {
+    const int fend = (L % 2 == 0) ? Lh - 1 : Lh;
+    R s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    int f2 = 1;
+    for (; f2 + 3 < fend; f2 += 4) {
+        const cplx<R> u0 = us[f2], u1 = us[f2 + 1], u2 = us[f2 + 2], u3 = us[f2 + 3];
+        const cplx<R> w0 = Gr[f2 * n + b], w1 = Gr[(f2 + 1) * n + b], w2 = Gr[(f2 + 2) * n + b],
+                      w3 = Gr[(f2 + 3) * n + b];
+        s0 += u0.x * w0.x - u0.y * w0.y;
+        s1 += u1.x * w1.x - u1.y * w1.y;
+        s2 += u2.x * w2.x - u2.y * w2.y;
+        s3 += u3.x * w3.x - u3.y * w3.y;
+    }
+    for (; f2 < fend; ++f2) {
+        const cplx<R> u0 = us[f2], w0 = Gr[f2 * n + b];
+        s0 += u0.x * w0.x - u0.y * w0.y;
+    }
+    R nyq = 0;
+    if (L % 2 == 0 && Lh > 1) {
+        const cplx<R> u0 = us[Lh - 1], w0 = Gr[(Lh - 1) * n + b];
+        nyq = u0.x * w0.x - u0.y * w0.y;
+    }
+    return us[0].x + R(2) * ((s0 + s1) + (s2 + s3)) + nyq;
+}
+
+// T[f2][c][a] = sum_b xr[b] exp(-2 pi i f2 b / L)
+template <typename R>
+__device__ void fwd_rows(const PArgs<R>& a, const cplx<R>* Gr, const R* xs, int base, int nrk) {
+    const int n = a.n, Lh = a.Lh, C = a.C;
+    for (int i = threadIdx.x; i < nrk * Lh; i += PT) {
+        const int k = i / Lh, f2 = i % Lh;
+        const int row = base + k * a.nwg;
+        const int c = row / n, ra = row % n;
+        const R* xr = xs + k * n;
+        const cplx<R>* g = Gr + f2 * n;
+        R r0 = 0, i0 = 0, r1 = 0, i1 = 0;
+        int b = 0;
+        for (; b + 1 < n; b += 2) {
+            const cplx<R> w0 = g[b], w1 = g[b + 1];
+            r0 += xr[b] * w0.x;
+            i0 -= xr[b] * w0.y;
+            r1 += xr[b + 1] * w1.x;
+            i1 -= xr[b + 1] * w1.y;
+        }
+        if (b < n) {
+            r0 += xr[b] * g[b].x;
+            i0 -= xr[b] * g[b].y;
+        }
+        a.T[((long)f2 * C + c) * n + ra] = cplx<R>{r0 + r1, i0 + i1};
+    }
+}
+
+// Row phase, CG vectors in registers (one lane per grid point of the block's rows).
+template <typename R>
+__device__ void row_phase_reg(const PArgs<R>& a, const Tiles<R>& t, Lane<R>& v, int nrk, bool update, R alpha,
+                              R beta, int par, double* red) {
+    const int n = a.n, Lh = a.Lh, L = a.L;
+    cplx<R>* Us = t.work;
+    R* xs = reinterpret_cast<R*>(Us + a.rbv * Lh);
+    __syncthreads();
+    if (update) {
+        gather_u(a, Us, blockIdx.x, nrk);
+        __syncthreads();
+    }
+    double g = 0.0, sg = 0.0;
+    if ((int)threadIdx.x < nrk * n) {
+        const int k = threadIdx.x / n, b = threadIdx.x % n;
+        R rn = 0;
+        if (v.gi >= 0) {
+            if (update) {
+                const R inv = R(1) / (R(L) * R(L));
+                const R wv = inv_row(Us + k * Lh, t.Gr, n, b, L, Lh) * inv + v.nz * v.r;
+                v.p = v.r + beta * v.p;
+                v.s = wv + beta * v.s;
+                v.x += alpha * v.p;
+                v.r = v.r - alpha * v.s;
+            }
+            rn = v.r;
+            g = (double)rn * (double)rn;
+            sg = (double)v.nz * g;
+        }
+        xs[k * n + b] = rn;
+    }
+    __syncthreads();
+    fwd_rows(a, t.Gr, xs, blockIdx.x, nrk);
+    const D3 tot = block_sum3(D3{g, sg, 0.0}, red);
+    if (threadIdx.x == 0) {
+        a.part[((long)par * a.nwg + blockIdx.x) * 4 + 0] = tot.a;
+        a.part[((long)par * a.nwg + blockIdx.x) * 4 + 1] = tot.b;
+    }
+}
+
+// Row phase with the CG vectors in global memory (systems with more rows per block).
+template <typename R>
+__device__ void row_phase_mem(const PArgs<R>& a, const Tiles<R>& t, bool update, R alpha, R beta, int par,
+                              double* red) {
+    const int n = a.n, Lh = a.Lh, L = a.L;
+    cplx<R>* Us = t.work;
+    R* xs = reinterpret_cast<R*>(Us + a.rbv * Lh);
+    double g = 0.0, sg = 0.0;
+    for (int base = blockIdx.x; base < a.nrows; base += a.rbv * a.nwg) {
         int nrk = 0;
-        while (nrk < RB && base + nrk * a.nwg < a.nrows) ++nrk;
+        while (nrk < a.rbv && base + nrk * a.nwg < a.nrows) ++nrk;
         __syncthreads();
         if (update) {
-            for (int i = threadIdx.x; i < nrk * Lh; i += PT) {
-                const int k = i / Lh, f2 = i % Lh;
-                const int row = base + k * a.nwg;
-                const int c = row / n, ra = row % n;
-                cplx<R> u{0, 0};
-                for (int part = 0; part < S; ++part) {
-                    const cplx<R> v = a.U[(((long)f2 * S + part) * C + c) * n + ra];
-                    u.x += v.x;
-                    u.y += v.y;
-                }
-                Us[k * Lh + f2] = u;
-            }
+            gather_u(a, Us, base, nrk);
             __syncthreads();
         }
         for (int i = threadIdx.x; i < nrk * n; i += PT) {
             const int k = i / n, b = i % n;
             const int row = base + k * a.nwg;
             const int c = row / n, ra = row % n;
-            const int v = a.vmap[ra * n + b];
+            const int vv = a.vmap[ra * n + b];
             R rn = 0;
-            if (v >= 0) {
-                const long gi = (long)c * a.n_vs + v;
+            if (vv >= 0) {
+                const long gi = (long)c * a.n_vs + vv;
                 const R ro = a.r[gi];
                 if (update) {
-                    const cplx<R>* us = Us + k * Lh;
-                    R sacc = us[0].x;
-                    for (int f2 = 1; f2 < Lh; ++f2) {
-                        const cplx<R> u = us[f2];
-                        const cplx<R> w = t.Gr[f2 * n + b];
-                        const R wt = (even && 2 * f2 == L) ? R(1) : R(2);
-                        sacc += wt * (u.x * w.x - u.y * w.y);
-                    }
-                    const R wv = sacc * inv + a.noise[gi] * ro;
+                    const R inv = R(1) / (R(L) * R(L));
+                    const R wv = inv_row(Us + k * Lh, t.Gr, n, b, L, Lh) * inv + a.noise[gi] * ro;
                     const R pv = ro + beta * a.p[gi];
                     const R sv = wv + beta * a.s[gi];
                     a.p[gi] = pv;
@@ -215,37 +339,23 @@ __device__ void row_phase(const PArgs<R>& a, const Tiles<R>& t, bool update, R a
                 } else {
                     rn = ro;
                 }
-                accg += (double)rn * (double)rn;
-                accs += (double)a.noise[gi] * (double)rn * (double)rn;
+                g += (double)rn * (double)rn;
+                sg += (double)a.noise[gi] * (double)rn * (double)rn;
             }
             xs[k * n + b] = rn;
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < nrk * Lh; i += PT) {
-            const int k = i / Lh, f2 = i % Lh;
-            const int row = base + k * a.nwg;
-            const int c = row / n, ra = row % n;
-            const R* xr = xs + k * n;
-            const cplx<R>* g = t.Gr + f2 * n;
-            R re = 0, im = 0;
-            for (int b = 0; b < n; ++b) {
-                const cplx<R> w = g[b];
-                re += xr[b] * w.x;
-                im -= xr[b] * w.y;
-            }
-            a.T[((long)f2 * C + c) * n + ra] = cplx<R>{re, im};
-        }
+        fwd_rows(a, t.Gr, xs, base, nrk);
     }
-    const double gs = block_sum(accg, red);
-    const double ss = block_sum(accs, red);
+    const D3 tot = block_sum3(D3{g, sg, 0.0}, red);
     if (threadIdx.x == 0) {
-        a.pg[par * a.nwg + blockIdx.x] = gs;
-        a.ps[par * a.nwg + blockIdx.x] = ss;
+        a.part[((long)par * a.nwg + blockIdx.x) * 4 + 0] = tot.a;
+        a.part[((long)par * a.nwg + blockIdx.x) * 4 + 1] = tot.b;
     }
 }
 
 template <typename R>
-__device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, double* red) {
+__device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, int par, double* red) {
     const int n = a.n, L = a.L, C = a.C, G = a.G, S = a.S, Lrm = a.Lrm;
     double accd = 0.0;
     if (blockIdx.x < a.Lh * S) {
@@ -258,22 +368,35 @@ __device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, double* red) {
         __syncthreads();
         for (int i = threadIdx.x; i < C * n; i += PT) Tc[i] = a.T[(long)f2 * C * n + i];
         __syncthreads();
-        // forward column transform, two channels per lane
+        // forward column transform, two channels per lane, two rows per step
         for (int i = threadIdx.x; i < (C / 2) * Lr; i += PT) {
             const int cp = i / Lr, j = i % Lr;
             const cplx<R>* t0 = Tc + (2 * cp) * n;
             const cplx<R>* t1 = t0 + n;
-            R r0 = 0, i0 = 0, r1 = 0, i1 = 0;
-            for (int ra = 0; ra < n; ++ra) {
+            R a0r = 0, a0i = 0, a1r = 0, a1i = 0, b0r = 0, b0i = 0, b1r = 0, b1i = 0;
+            int ra = 0;
+            for (; ra + 1 < n; ra += 2) {
+                const cplx<R> f = t.Fa[ra * Lrm + j], g = t.Fa[(ra + 1) * Lrm + j];
+                const cplx<R> u0 = t0[ra], u1 = t1[ra], w0 = t0[ra + 1], w1 = t1[ra + 1];
+                a0r += u0.x * f.x - u0.y * f.y;
+                a0i += u0.x * f.y + u0.y * f.x;
+                a1r += u1.x * f.x - u1.y * f.y;
+                a1i += u1.x * f.y + u1.y * f.x;
+                b0r += w0.x * g.x - w0.y * g.y;
+                b0i += w0.x * g.y + w0.y * g.x;
+                b1r += w1.x * g.x - w1.y * g.y;
+                b1i += w1.x * g.y + w1.y * g.x;
+            }
+            if (ra < n) {
                 const cplx<R> f = t.Fa[ra * Lrm + j];
                 const cplx<R> u0 = t0[ra], u1 = t1[ra];
-                r0 += u0.x * f.x - u0.y * f.y;
-                i0 += u0.x * f.y + u0.y * f.x;
-                r1 += u1.x * f.x - u1.y * f.y;
-                i1 += u1.x * f.y + u1.y * f.x;
+                a0r += u0.x * f.x - u0.y * f.y;
+                a0i += u0.x * f.y + u0.y * f.x;
+                a1r += u1.x * f.x - u1.y * f.y;
+                a1i += u1.x * f.y + u1.y * f.x;
             }
-            Xh[(2 * cp) * Lrm + j] = cplx<R>{r0, i0};
-            Xh[(2 * cp + 1) * Lrm + j] = cplx<R>{r1, i1};
+            Xh[(2 * cp) * Lrm + j] = cplx<R>{a0r + b0r, a0i + b0i};
+            Xh[(2 * cp + 1) * Lrm + j] = cplx<R>{a1r + b1r, a1i + b1i};
         }
         __syncthreads();
         // per-frequency products, x and y outputs of one sensor per lane
@@ -297,32 +420,45 @@ __device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, double* red) {
         }
         __syncthreads();
         // partial inverse column transform over this f1 range, two channels per lane
+        cplx<R>* Uo = a.U + (((long)f2 * S + part) * C) * n;
         for (int i = threadIdx.x; i < (C / 2) * n; i += PT) {
             const int pp = i / n, ra = i % n;
             const cplx<R>* y0 = Yh + (2 * pp) * Lrm;
             const cplx<R>* y1 = y0 + Lrm;
-            R r0 = 0, i0 = 0, r1 = 0, i1 = 0;
-            for (int j = 0; j < Lr; ++j) {
-                const cplx<R> f = t.Fb[j * n + ra];   // conj(f) is the inverse twiddle
-                const cplx<R> u0 = y0[j], u1 = y1[j];
-                r0 += u0.x * f.x + u0.y * f.y;
-                i0 += u0.y * f.x - u0.x * f.y;
-                r1 += u1.x * f.x + u1.y * f.y;
-                i1 += u1.y * f.x - u1.x * f.y;
+            R a0r = 0, a0i = 0, a1r = 0, a1i = 0, b0r = 0, b0i = 0, b1r = 0, b1i = 0;
+            int j = 0;
+            for (; j + 1 < Lr; j += 2) {
+                const cplx<R> f = t.Fb[j * n + ra], g = t.Fb[(j + 1) * n + ra];   // conj: inverse twiddles
+                const cplx<R> u0 = y0[j], u1 = y1[j], w0 = y0[j + 1], w1 = y1[j + 1];
+                a0r += u0.x * f.x + u0.y * f.y;
+                a0i += u0.y * f.x - u0.x * f.y;
+                a1r += u1.x * f.x + u1.y * f.y;
+                a1i += u1.y * f.x - u1.x * f.y;
+                b0r += w0.x * g.x + w0.y * g.y;
+                b0i += w0.y * g.x - w0.x * g.y;
+                b1r += w1.x * g.x + w1.y * g.y;
+                b1i += w1.y * g.x - w1.x * g.y;
             }
-            cplx<R>* Uo = a.U + (((long)f2 * S + part) * C) * n;
-            Uo[(2 * pp) * n + ra] = cplx<R>{r0, i0};
-            Uo[(2 * pp + 1) * n + ra] = cplx<R>{r1, i1};
+            if (j < Lr) {
+                const cplx<R> f = t.Fb[j * n + ra];
+                const cplx<R> u0 = y0[j], u1 = y1[j];
+                a0r += u0.x * f.x + u0.y * f.y;
+                a0i += u0.y * f.x - u0.x * f.y;
+                a1r += u1.x * f.x + u1.y * f.y;
+                a1i += u1.y * f.x - u1.x * f.y;
+            }
+            Uo[(2 * pp) * n + ra] = cplx<R>{a0r + b0r, a0i + b0i};
+            Uo[(2 * pp + 1) * n + ra] = cplx<R>{a1r + b1r, a1i + b1i};
         }
     }
-    const double d = block_sum(accd, red);
-    if (threadIdx.x == 0) a.pd[blockIdx.x] = d / ((double)a.L * (double)a.L);
+    const D3 tot = block_sum3(D3{accd, 0.0, 0.0}, red);
+    if (threadIdx.x == 0) a.part[((long)par * a.nwg + blockIdx.x) * 4 + 2] = tot.a / ((double)a.L * (double)a.L);
 }
 
 template <typename R, bool RES>
 __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
     extern __shared__ __align__(16) char smem_raw[];
-    __shared__ double red[PT];
+    __shared__ double red[3 * PT / 64];
     __shared__ int s_flag;
     const int n = a.n, Lh = a.Lh, Lrm = a.Lrm, S = a.S, L = a.L, P = 3 * a.G * a.G;
     const bool colunit = blockIdx.x < Lh * S;
@@ -361,20 +497,48 @@ __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
         t.Ms = nullptr;
         t.work = reinterpret_cast<cplx<R>*>(smem_raw);
     }
+    // lanes of the register-resident CG vectors
+    Lane<R> v{-1, 0, 0, 0, 0, 0};
+    int nrk = 0;
+    if (a.vreg) {
+        while (nrk < a.rbv && (int)blockIdx.x + nrk * a.nwg < a.nrows) ++nrk;
+        if ((int)threadIdx.x < nrk * n) {
+            const int k = threadIdx.x / n, b = threadIdx.x % n;
+            const int row = blockIdx.x + k * a.nwg;
+            const int c = row / n, ra = row % n;
+            const int vv = a.vmap[ra * n + b];
+            if (vv >= 0) {
+                v.gi = (long)c * a.n_vs + vv;
+                v.x = a.x[v.gi];
+                v.r = a.r[v.gi];
+                v.p = a.p[v.gi];
+                v.s = a.s[v.gi];
+                v.nz = a.noise[v.gi];
+            }
+        }
+    }
     unsigned epoch = 0;
     int it = a.it0;
-    row_phase<R>(a, t, false, R(0), R(0), it & 1, red);
+    if (a.vreg) row_phase_reg<R>(a, t, v, nrk, false, R(0), R(0), it & 1, red);
+    else row_phase_mem<R>(a, t, false, R(0), R(0), it & 1, red);
     if (!grid_sync(a.bar, a.nwg, epoch, &s_flag)) return;
-    col_phase<R>(a, t, red);
+    col_phase<R>(a, t, it & 1, red);
     if (!grid_sync(a.bar, a.nwg, epoch, &s_flag)) return;
     double gprev = a.gprev, aprev = a.aprev;
     bool first = a.first != 0;
     const double tol2 = a.S_->tol2, drop2 = a.S_->drop2;
     while (true) {
         const int par = it & 1;
-        const double g = sum_all(a.pg + par * a.nwg, a.nwg, red);
-        const double sg = sum_all(a.ps + par * a.nwg, a.nwg, red);
-        const double dl = sum_all(a.pd, a.nwg, red) + sg;
+        D3 pv{0.0, 0.0, 0.0};
+        for (int i = threadIdx.x; i < a.nwg; i += PT) {
+            const double* q = a.part + ((long)par * a.nwg + i) * 4;
+            pv.a += q[0];
+            pv.b += q[1];
+            pv.c += q[2];
+        }
+        const D3 tot = block_sum3(pv, red);
+        const double g = tot.a;
+        const double dl = tot.c + tot.b;
         int st = ST_RUN;
         double alpha = 0.0, beta = 0.0;
         if (!isfinite(g) || !isfinite(dl)) st = ST_BREAK;
@@ -392,6 +556,12 @@ __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
             if (!(alpha > 0.0) || !isfinite(alpha)) st = ST_BREAK;
         }
         if (st != ST_RUN) {
+            if (a.vreg && v.gi >= 0) {
+                a.x[v.gi] = v.x;
+                a.r[v.gi] = v.r;
+                a.p[v.gi] = v.p;
+                a.s[v.gi] = v.s;
+            }
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 a.P->gamma_prev = gprev;
                 a.P->alpha_prev = aprev;
@@ -404,23 +574,24 @@ __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
             }
             return;
         }
-        row_phase<R>(a, t, true, (R)alpha, (R)beta, (it + 1) & 1, red);
+        if (a.vreg) row_phase_reg<R>(a, t, v, nrk, true, (R)alpha, (R)beta, (it + 1) & 1, red);
+        else row_phase_mem<R>(a, t, true, (R)alpha, (R)beta, (it + 1) & 1, red);
         gprev = g;
         aprev = alpha;
         first = false;
         ++it;
         if (!grid_sync(a.bar, a.nwg, epoch, &s_flag)) return;
-        col_phase<R>(a, t, red);
+        col_phase<R>(a, t, it & 1, red);
         if (!grid_sync(a.bar, a.nwg, epoch, &s_flag)) return;
     }
 }
 
 // LDS bytes: resident tiles (if RES) + work region (max of column and row needs)
 template <typename R>
-size_t lds_bytes(const tt_ctx& c, int Lrm, bool res) {
+size_t lds_bytes(const tt_ctx& c, int Lrm, int rbv, bool res) {
     const size_t cs = sizeof(cplx<R>);
     const size_t colw = cs * ((size_t)c.C * c.n + 2ull * c.C * Lrm);
-    const size_t roww = cs * (size_t)RB * c.Lh + sizeof(R) * (size_t)RB * c.n;
+    const size_t roww = cs * (size_t)rbv * c.Lh + sizeof(R) * (size_t)rbv * c.n;
     size_t b = std::max(colw, roww);
     if (res) b += cs * (2ull * c.n * Lrm + (size_t)c.Lh * c.n) + sizeof(R) * (size_t)packed_reals(c.G) * Lrm;
     return b;
@@ -559,8 +730,12 @@ tt_status solve_persistent_t(tt_ctx& c, const float* s, const double* x0, double
     S = std::min(S, std::max(1, c.L / 8));
     const int Lrm = (c.L + S - 1) / S;
     const size_t lim = 160 * 1024 - PT * sizeof(double) - 256;   // minus the static LDS
-    const bool res = lds_bytes<R>(c, Lrm, true) <= lim;
-    const size_t lds = lds_bytes<R>(c, Lrm, res);
+    // rows per block: all of a block's rows at once when they fit the threads
+    const int rows_per_block = (c.C * c.n + nwg - 1) / nwg;
+    const bool vreg = rows_per_block * c.n <= PT;
+    const int rbv = vreg ? rows_per_block : std::max(1, std::min(4, PT / std::max(c.n, 1)));
+    const bool res = lds_bytes<R>(c, Lrm, rbv, true) <= lim;
+    const size_t lds = lds_bytes<R>(c, Lrm, rbv, res);
     if (lds > lim) {
         tt_set_error("persistent solver: system too large for LDS");
         return TT_INVALID_ARG;
@@ -571,7 +746,7 @@ tt_status solve_persistent_t(tt_ctx& c, const float* s, const double* x0, double
         c.tile_elem = (int)sizeof(R);
     }
     if (c.pU.n < (size_t)c.Lh * S * c.C * c.n) TT_CHECK(c.pU.alloc((size_t)c.Lh * S * c.C * c.n));
-    if (c.ppart.n < 5 * (size_t)nwg) TT_CHECK(c.ppart.alloc(5 * (size_t)nwg));
+    if (c.ppart.n < 8 * (size_t)nwg) TT_CHECK(c.ppart.alloc(8 * (size_t)nwg));
     if (c.bar.n < 32 + 32 * NGRP) TT_CHECK(c.bar.alloc(32 + 32 * NGRP));
 
     PArgs<R> a{};
@@ -598,9 +773,9 @@ tt_status solve_persistent_t(tt_ctx& c, const float* s, const double* x0, double
     a.s = sv;
     a.T = reinterpret_cast<cplx<R>*>(f32 ? (void*)c.T32.p : (void*)c.T64.p);
     a.U = reinterpret_cast<cplx<R>*>(c.pU.p);
-    a.pg = c.ppart.p;
-    a.ps = c.ppart.p + 2 * nwg;
-    a.pd = c.ppart.p + 4 * nwg;
+    a.part = c.ppart.p;
+    a.vreg = vreg ? 1 : 0;
+    a.rbv = rbv;
     a.S_ = cg_scalars(c);
     a.P = p_scalars(c);
     a.bar = c.bar.p;

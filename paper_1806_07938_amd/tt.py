@@ -239,7 +239,7 @@ class Context:
 
     def solve(self, s, x0=None, zeta=None, phi=None, project: bool = True, tol: float = 1e-6,
               max_iter: int = 20000, precision: int = PREC_F32, solver: int = SOLVER_PERSISTENT,
-              refine_drop: float = 1e-2, allow=(TT_OK,)):
+              refine_drop: float = 1e-3, allow=(TT_OK,)):
         """Solve for zeta (float64) and, if a target is set and project, phi (float32)."""
         import torch
         n = self.info["n_slopes"]
