@@ -76,7 +76,8 @@ typedef enum {
 } tt_solver_kind;
 
 typedef enum {
-    TT_MODEL_HUDGIN = 0      /* App. A.2 Hudgin-like two-point slopes */
+    TT_MODEL_HUDGIN = 0,     /* App. A.2 Hudgin-like two-point slopes */
+    TT_MODEL_FRIED = 1       /* App. A.3 Fried four-corner slopes */
 } tt_gradient_model;
 
 /* Sensor geometry (§2, §2.D, §2.F).  The library copies every array. */

@@ -1,7 +1,9 @@
 """Hudgin-like covariance model, dense matrices (App. A.2; §2.C-§2.F).
 
 A Hudgin-like slope is the phase difference between the two edge midpoints of
-a subaperture (App. A.2).  With the structure function D of the von Karman
+a subaperture (App. A.2); a Fried slope (App. A.3, selected by a workload
+attribute model = 'fried') is half the sum of the two corner-to-corner
+differences across the subaperture.  With the structure function D of the von Karman
 model, the slope-slope covariances of one layer at separation Delta and edge
 spacing delta are (App. A.2, Hudgin slope-slope equations):
 
@@ -57,6 +59,46 @@ def hudgin_xy(dx, dy, delta, r0, L0):
                   - _D(dx + h, dy - h, r0, L0) + _D(dx - h, dy - h, r0, L0))
 
 
+def fried_xx(dx, dy, delta, r0, L0):
+    """App. A.3 Fried slope-slope xx: 1/8 [-4 D + 2 F1 - 2 F2 + F3 + F4] (slopes in rad:
+    the printed 1/2 (lambda / 4 pi d)^2 is (lambda / 2 pi d)^2 / 8)."""
+    F1, F2, F3, F4 = _fried_F(dx, dy, delta, r0, L0)
+    return 0.125 * (-4.0 * _D(dx, dy, r0, L0) + 2.0 * F1 - 2.0 * F2 + F3 + F4)
+
+
+def fried_yy(dx, dy, delta, r0, L0):
+    F1, F2, F3, F4 = _fried_F(dx, dy, delta, r0, L0)
+    return 0.125 * (-4.0 * _D(dx, dy, r0, L0) - 2.0 * F1 + 2.0 * F2 + F3 + F4)
+
+
+def fried_xy(dx, dy, delta, r0, L0):
+    F1, F2, F3, F4 = _fried_F(dx, dy, delta, r0, L0)
+    return 0.125 * (F3 - F4)
+
+
+def _fried_F(dx, dy, delta, r0, L0):
+    F1 = _D(dx + delta, dy, r0, L0) + _D(dx - delta, dy, r0, L0)
+    F2 = _D(dx, dy + delta, r0, L0) + _D(dx, dy - delta, r0, L0)
+    F3 = _D(dx + delta, dy + delta, r0, L0) + _D(dx - delta, dy - delta, r0, L0)
+    F4 = _D(dx + delta, dy - delta, r0, L0) + _D(dx - delta, dy + delta, r0, L0)
+    return F1, F2, F3, F4
+
+
+def fried_phase_x(dx, dy, delta, r0, L0):
+    """App. A.3 Fried phase-slope x: 1/4 (-F5 + F6 + F7 - F8) in rad (printed lambda/(8 pi d))."""
+    h = 0.5 * delta
+    F5, F6 = _D(dx + h, dy + h, r0, L0), _D(dx - h, dy + h, r0, L0)
+    F7, F8 = _D(dx - h, dy - h, r0, L0), _D(dx + h, dy - h, r0, L0)
+    return 0.25 * (-F5 + F6 + F7 - F8)
+
+
+def fried_phase_y(dx, dy, delta, r0, L0):
+    h = 0.5 * delta
+    F5, F6 = _D(dx + h, dy + h, r0, L0), _D(dx - h, dy + h, r0, L0)
+    F7, F8 = _D(dx - h, dy - h, r0, L0), _D(dx + h, dy - h, r0, L0)
+    return 0.25 * (-F5 - F6 + F7 + F8)
+
+
 def hudgin_phase_x(dx, dy, delta, r0, L0):
     return 0.5 * (_D(dx - 0.5 * delta, dy, r0, L0) - _D(dx + 0.5 * delta, dy, r0, L0))
 
@@ -66,6 +108,16 @@ def hudgin_phase_y(dx, dy, delta, r0, L0):
 
 
 _SS = {(0, 0): hudgin_xx, (1, 1): hudgin_yy, (0, 1): hudgin_xy, (1, 0): hudgin_xy}
+_SS_FRIED = {(0, 0): fried_xx, (1, 1): fried_yy, (0, 1): fried_xy, (1, 0): fried_xy}
+
+
+def model_of(wl):
+    """Gradient model of a workload: 'hudgin' (App. A.2, default) or 'fried' (App. A.3)."""
+    return getattr(wl, "model", "hudgin")
+
+
+def phase_fns(wl):
+    return (fried_phase_x, fried_phase_y) if model_of(wl) == "fried" else (hudgin_phase_x, hudgin_phase_y)
 
 
 def slope_pair_cov(wl, gi, p, ra, gj, q, rb):
@@ -73,7 +125,7 @@ def slope_pair_cov(wl, gi, p, ra, gj, q, rb):
     with slope component q of sensor gj at centres rb (m, 2), element-wise,
     summed over layers (App. A.2 with the §2.D cone scaling)."""
     s = G.cone_scale(wl.h, wl.h_lgs)
-    f = _SS[(p, q)]
+    f = (_SS_FRIED if model_of(wl) == "fried" else _SS)[(p, q)]
     out = np.zeros(np.broadcast_shapes(ra.shape[:-1], rb.shape[:-1]))
     for k in range(wl.n_layer):
         base = wl.h[k] * (wl.gs[gj] - wl.gs[gi])
@@ -171,11 +223,12 @@ def phase_slope_cov(wl, rho, target=None):
     nv = r.shape[0]
     s = G.cone_scale(wl.h, wl.h_lgs)
     out = np.zeros((rho.shape[0], 2 * wl.n_gs * nv))
+    fx, fy = phase_fns(wl)
     for g in range(wl.n_gs):
         for k in range(wl.n_layer):
             ox = s[k] * r[None, :, 0] + wl.h[k] * (wl.gs[g, 0] - beta[0]) - rho[:, None, 0]
             oy = s[k] * r[None, :, 1] + wl.h[k] * (wl.gs[g, 1] - beta[1]) - rho[:, None, 1]
             dl = s[k] * wl.d
-            out[:, (2 * g) * nv:(2 * g + 1) * nv] += wl.w[k] * hudgin_phase_x(ox, oy, dl, wl.r0, wl.L0)
-            out[:, (2 * g + 1) * nv:(2 * g + 2) * nv] += wl.w[k] * hudgin_phase_y(ox, oy, dl, wl.r0, wl.L0)
+            out[:, (2 * g) * nv:(2 * g + 1) * nv] += wl.w[k] * fx(ox, oy, dl, wl.r0, wl.L0)
+            out[:, (2 * g + 1) * nv:(2 * g + 2) * nv] += wl.w[k] * fy(ox, oy, dl, wl.r0, wl.L0)
     return out

@@ -34,7 +34,7 @@ import math
 import numpy as np
 
 from . import geometry as G
-from .covariance import hudgin_phase_x, hudgin_phase_y, phase_slope_cov
+from .covariance import phase_fns, phase_slope_cov
 
 
 def new_grid_size(wl):
@@ -60,11 +60,12 @@ def xi_prime(wl, k, n_prime, beta=None):
     r = G.subap_centers(wl.n, wl.d)[G.valid_index(wl.valid)]
     nv = r.shape[0]
     out = np.zeros((rho.shape[0], 2 * wl.n_gs * nv))
+    fx, fy = phase_fns(wl)
     for g in range(wl.n_gs):
         ox = s * r[None, :, 0] + wl.h[k] * (wl.gs[g, 0] - beta[0]) - rho[:, None, 0]
         oy = s * r[None, :, 1] + wl.h[k] * (wl.gs[g, 1] - beta[1]) - rho[:, None, 1]
-        out[:, 2 * g * nv:(2 * g + 1) * nv] = wl.w[k] * hudgin_phase_x(ox, oy, s * wl.d, wl.r0, wl.L0)
-        out[:, (2 * g + 1) * nv:(2 * g + 2) * nv] = wl.w[k] * hudgin_phase_y(ox, oy, s * wl.d, wl.r0, wl.L0)
+        out[:, 2 * g * nv:(2 * g + 1) * nv] = wl.w[k] * fx(ox, oy, s * wl.d, wl.r0, wl.L0)
+        out[:, (2 * g + 1) * nv:(2 * g + 2) * nv] = wl.w[k] * fy(ox, oy, s * wl.d, wl.r0, wl.L0)
     return out
 
 
@@ -110,7 +111,7 @@ def xi_prime_table(wl, k, g, p, n_prime, beta=None):
     U, V = np.meshgrid(lag, lag)
     ox = s * wl.d * (U + off) + wl.h[k] * (wl.gs[g, 0] - beta[0])
     oy = s * wl.d * (V + off) + wl.h[k] * (wl.gs[g, 1] - beta[1])
-    f = hudgin_phase_x if p == 0 else hudgin_phase_y
+    f = phase_fns(wl)[p]
     return wl.w[k] * f(ox, oy, s * wl.d, wl.r0, wl.L0)
 
 

@@ -61,7 +61,8 @@ tt_status generate_impl(tt_ctx* c, const tt_geometry* g, const tt_atmosphere* a,
     TT_REQUIRE(g->n >= 1 && g->n <= 512, "n must be in [1, 512]");
     TT_REQUIRE(g->n_gs >= 1 && g->n_gs <= 16, "n_gs must be in [1, 16]");
     TT_REQUIRE(g->pad_L >= 2 * g->n - 1 && g->pad_L <= 1024, "pad_L must be in [2n-1, 1024]");
-    TT_REQUIRE(g->gradient_model == TT_MODEL_HUDGIN, "unsupported gradient model");
+    TT_REQUIRE(g->gradient_model == TT_MODEL_HUDGIN || g->gradient_model == TT_MODEL_FRIED,
+               "unsupported gradient model");
     TT_REQUIRE(std::isfinite(g->D) && g->D > 0, "D must be positive");
     TT_REQUIRE(g->gs_xy && g->valid, "gs_xy and valid are required");
     TT_REQUIRE(finite_all(g->gs_xy, 2 * g->n_gs), "non-finite guide-star direction");
@@ -122,6 +123,7 @@ tt_status set_system_impl(tt_ctx* c, const tt_kernels* k, const double* noise_va
     c->L = k->pad_L;
     c->Lh = k->pad_L / 2 + 1;
     c->n_layer = k->n_layer;
+    c->model = k->model;
     c->d = k->d;
     c->h_lgs = k->h_lgs;
     c->lgs = k->lgs;

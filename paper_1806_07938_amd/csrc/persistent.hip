@@ -17,8 +17,8 @@
 //
 // The product A r is the fused 2RBT product of §2.E, split in two phases
 // separated by grid barriers (two barriers per iteration):
-//   row phase    (rows (c, a) of the n x n grids, up to RB rows per block at
-//                a time): inverse row transform of the column-phase output ->
+//   row phase    (rows (c, a) of the n x n grids, a few consecutive rows per
+//                block): inverse row transform of the column-phase output ->
 //                w = A r (+ sigma^2 r); vector updates; forward row transform of
 //                the new residual -> T[f2][c][a]; partial r.r and sigma^2 r.r;
 //   column phase (block = one f2 column and one of S ranges of f1):
@@ -62,6 +62,7 @@ struct PArgs {
     double* part;            // [2][nwg][4]: partial r.r, sigma^2 r.r, r.C r (Parseval)
     int vreg;                // CG vectors held in registers (rows per block * n <= threads)
     int rbv;                 // rows per block at a time
+    int mfma;                // column transforms on the matrix cores (FP32); 0 = VALU
     CgScalars* S_;
     PScalars* P;
     unsigned* bar;           // barrier words: [0] top counter, [16] abort, [32 + 32 g] group counters
@@ -190,11 +191,11 @@ struct Lane {
 
 // Us[k][f2] = sum over f1 ranges of the column-phase outputs of row k
 template <typename R>
-__device__ void gather_u(const PArgs<R>& a, cplx<R>* Us, int base, int nrk) {
+__device__ void gather_u(const PArgs<R>& a, cplx<R>* Us, int base, int stride, int nrk) {
     const int n = a.n, Lh = a.Lh, C = a.C, S = a.S;
     for (int i = threadIdx.x; i < nrk * Lh; i += PT) {
         const int k = i / Lh, f2 = i % Lh;
-        const int row = base + k * a.nwg;
+        const int row = base + k * stride;
         const int c = row / n, ra = row % n;
         const cplx<R>* u = a.U + ((long)f2 * S * C + c) * n + ra;
         R ux = 0, uy = 0;
@@ -236,11 +237,11 @@ __device__ inline R inv_row(const cplx<R>* us, const cplx<R>* Gr, int n, int b, 
 
 // T[f2][c][a] = sum_b xr[b] exp(-2 pi i f2 b / L)
 template <typename R>
-__device__ void fwd_rows(const PArgs<R>& a, const cplx<R>* Gr, const R* xs, int base, int nrk) {
+__device__ void fwd_rows(const PArgs<R>& a, const cplx<R>* Gr, const R* xs, int base, int stride, int nrk) {
     const int n = a.n, Lh = a.Lh, C = a.C;
     for (int i = threadIdx.x; i < nrk * Lh; i += PT) {
         const int k = i / Lh, f2 = i % Lh;
-        const int row = base + k * a.nwg;
+        const int row = base + k * stride;
         const int c = row / n, ra = row % n;
         const R* xr = xs + k * n;
         const cplx<R>* g = Gr + f2 * n;
@@ -270,7 +271,7 @@ __device__ void row_phase_reg(const PArgs<R>& a, const Tiles<R>& t, Lane<R>& v, 
     R* xs = reinterpret_cast<R*>(Us + a.rbv * Lh);
     __syncthreads();
     if (update) {
-        gather_u(a, Us, blockIdx.x, nrk);
+        gather_u(a, Us, blockIdx.x * a.rbv, 1, nrk);
         __syncthreads();
     }
     double g = 0.0, sg = 0.0;
@@ -293,7 +294,7 @@ __device__ void row_phase_reg(const PArgs<R>& a, const Tiles<R>& t, Lane<R>& v, 
         xs[k * n + b] = rn;
     }
     __syncthreads();
-    fwd_rows(a, t.Gr, xs, blockIdx.x, nrk);
+    fwd_rows(a, t.Gr, xs, blockIdx.x * a.rbv, 1, nrk);
     const D3 tot = block_sum3(D3{g, sg, 0.0}, red);
     if (threadIdx.x == 0) {
         a.part[((long)par * a.nwg + blockIdx.x) * 4 + 0] = tot.a;
@@ -314,7 +315,7 @@ __device__ void row_phase_mem(const PArgs<R>& a, const Tiles<R>& t, bool update,
         while (nrk < a.rbv && base + nrk * a.nwg < a.nrows) ++nrk;
         __syncthreads();
         if (update) {
-            gather_u(a, Us, base, nrk);
+            gather_u(a, Us, base, a.nwg, nrk);
             __syncthreads();
         }
         for (int i = threadIdx.x; i < nrk * n; i += PT) {
@@ -345,12 +346,87 @@ __device__ void row_phase_mem(const PArgs<R>& a, const Tiles<R>& t, bool update,
             xs[k * n + b] = rn;
         }
         __syncthreads();
-        fwd_rows(a, t.Gr, xs, base, nrk);
+        fwd_rows(a, t.Gr, xs, base, a.nwg, nrk);
     }
     const D3 tot = block_sum3(D3{g, sg, 0.0}, red);
     if (threadIdx.x == 0) {
         a.part[((long)par * a.nwg + blockIdx.x) * 4 + 0] = tot.a;
         a.part[((long)par * a.nwg + blockIdx.x) * 4 + 1] = tot.b;
+    }
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Forward column transform on the matrix cores (FP32).  As a real product
+// X (Lr x 2C) = A (Lr x 2n) B (2n x 2C) with A[j][2a+e] = (Re, Im) F[f1a+j][a]
+// and B[2a+e][2c+f] built from T[c][a] so that column 2c is Re X_c and 2c+1 is
+// Im X_c.  v_mfma_f32_16x16x4f32 lane layout: A[l%16][l/16], B[l/16][l%16],
+// result element v of lane l at row 4(l/16)+v, column l%16.  One 16x16 output
+// tile per wave, the K loop in steps of 4.
+__device__ void col_fwd_mfma(const cplx<float>* Fa, const cplx<float>* Tc, cplx<float>* Xh, int n, int C, int Lr,
+                             int Lrm) {
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, kq = l >> 4, lc = l & 15;
+    const int MT = (Lr + 15) / 16, NT = (2 * C + 15) / 16, KS = (2 * n + 3) / 4;
+    for (int tp = wave; tp < MT * NT; tp += PT / 64) {
+        const int mt = tp % MT, nt = tp / MT;
+        const int j = mt * 16 + lc;
+        const int col = nt * 16 + lc, cB = col >> 1, fB = col & 1;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int s = 0; s < KS; ++s) {
+            const int k = 4 * s + kq, ai = k >> 1, e = k & 1;
+            float av = 0.f, bv = 0.f;
+            if (ai < n) {
+                if (j < Lr) {
+                    const cplx<float> f = Fa[ai * Lrm + j];
+                    av = e ? f.y : f.x;
+                }
+                if (cB < C) {
+                    const cplx<float> t = Tc[cB * n + ai];
+                    bv = e == 0 ? (fB ? t.y : t.x) : (fB ? t.x : -t.y);
+                }
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+        }
+        if (cB < C)
+            for (int v = 0; v < 4; ++v) {
+                const int jj = mt * 16 + 4 * kq + v;
+                if (jj < Lr) reinterpret_cast<float*>(&Xh[cB * Lrm + jj])[fB] = acc[v];
+            }
+    }
+}
+
+// Partial inverse column transform on the matrix cores (FP32):
+// U (n x 2C) = A (n x 2Lr) B (2Lr x 2C), A[a][2j+e] = (Re, Im) F[f1a+j][a],
+// B[2j+e][2p+f] from Y[p][j] so that U_p = sum_j Y_p[j] conj(F[f1a+j][a]).
+__device__ void col_inv_mfma(const cplx<float>* Fb, const cplx<float>* Yh, cplx<float>* Uo, int n, int C, int Lr,
+                             int Lrm) {
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, kq = l >> 4, lc = l & 15;
+    const int MT = (n + 15) / 16, NT = (2 * C + 15) / 16, KS = (2 * Lr + 3) / 4;
+    for (int tp = wave; tp < MT * NT; tp += PT / 64) {
+        const int mt = tp % MT, nt = tp / MT;
+        const int ar = mt * 16 + lc;
+        const int col = nt * 16 + lc, pB = col >> 1, fB = col & 1;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int s = 0; s < KS; ++s) {
+            const int k = 4 * s + kq, jj = k >> 1, e = k & 1;
+            float av = 0.f, bv = 0.f;
+            if (jj < Lr) {
+                if (ar < n) {
+                    const cplx<float> f = Fb[jj * n + ar];
+                    av = e ? f.y : f.x;
+                }
+                if (pB < C) {
+                    const cplx<float> y = Yh[pB * Lrm + jj];
+                    bv = e == 0 ? (fB ? y.y : y.x) : (fB ? -y.x : y.y);
+                }
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+        }
+        if (pB < C)
+            for (int v = 0; v < 4; ++v) {
+                const int a2 = mt * 16 + 4 * kq + v;
+                if (a2 < n) reinterpret_cast<float*>(&Uo[pB * n + a2])[fB] = acc[v];
+            }
     }
 }
 
@@ -368,7 +444,11 @@ __device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, int par, double*
         __syncthreads();
         for (int i = threadIdx.x; i < C * n; i += PT) Tc[i] = a.T[(long)f2 * C * n + i];
         __syncthreads();
-        // forward column transform, two channels per lane, two rows per step
+        // forward column transform: matrix cores (FP32) or two channels per lane on the VALU
+        if constexpr (sizeof(R) == 4) {
+            if (a.mfma) col_fwd_mfma(t.Fa, Tc, Xh, n, C, Lr, Lrm);
+        }
+        if (sizeof(R) != 4 || !a.mfma) {
         for (int i = threadIdx.x; i < (C / 2) * Lr; i += PT) {
             const int cp = i / Lr, j = i % Lr;
             const cplx<R>* t0 = Tc + (2 * cp) * n;
@@ -398,6 +478,7 @@ __device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, int par, double*
             Xh[(2 * cp) * Lrm + j] = cplx<R>{a0r + b0r, a0i + b0i};
             Xh[(2 * cp + 1) * Lrm + j] = cplx<R>{a1r + b1r, a1i + b1i};
         }
+        }
         __syncthreads();
         // per-frequency products, x and y outputs of one sensor per lane
         const double wt2 = ((f2 == 0) || ((L % 2) == 0 && 2 * f2 == L)) ? 1.0 : 2.0;
@@ -419,8 +500,12 @@ __device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, int par, double*
             accd += wt2 * ((double)x0.x * y0r + (double)x0.y * y0i + (double)x1.x * y1r + (double)x1.y * y1i);
         }
         __syncthreads();
-        // partial inverse column transform over this f1 range, two channels per lane
+        // partial inverse column transform over this f1 range
         cplx<R>* Uo = a.U + (((long)f2 * S + part) * C) * n;
+        if constexpr (sizeof(R) == 4) {
+            if (a.mfma) col_inv_mfma(t.Fb, Yh, Uo, n, C, Lr, Lrm);
+        }
+        if (sizeof(R) != 4 || !a.mfma) {
         for (int i = threadIdx.x; i < (C / 2) * n; i += PT) {
             const int pp = i / n, ra = i % n;
             const cplx<R>* y0 = Yh + (2 * pp) * Lrm;
@@ -449,6 +534,7 @@ __device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, int par, double*
             }
             Uo[(2 * pp) * n + ra] = cplx<R>{a0r + b0r, a0i + b0i};
             Uo[(2 * pp + 1) * n + ra] = cplx<R>{a1r + b1r, a1i + b1i};
+        }
         }
     }
     const D3 tot = block_sum3(D3{accd, 0.0, 0.0}, red);
@@ -501,10 +587,12 @@ __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
     Lane<R> v{-1, 0, 0, 0, 0, 0};
     int nrk = 0;
     if (a.vreg) {
-        while (nrk < a.rbv && (int)blockIdx.x + nrk * a.nwg < a.nrows) ++nrk;
+        // a block owns the consecutive rows blockIdx.x * rbv + k, k < nrk
+        nrk = a.nrows - (int)blockIdx.x * a.rbv;
+        nrk = nrk < 0 ? 0 : (nrk > a.rbv ? a.rbv : nrk);
         if ((int)threadIdx.x < nrk * n) {
             const int k = threadIdx.x / n, b = threadIdx.x % n;
-            const int row = blockIdx.x + k * a.nwg;
+            const int row = blockIdx.x * a.rbv + k;
             const int c = row / n, ra = row % n;
             const int vv = a.vmap[ra * n + b];
             if (vv >= 0) {
@@ -775,6 +863,11 @@ tt_status solve_persistent_t(tt_ctx& c, const float* s, const double* x0, double
     a.U = reinterpret_cast<cplx<R>*>(c.pU.p);
     a.part = c.ppart.p;
     a.vreg = vreg ? 1 : 0;
+    // The matrix-core column transforms (col_fwd_mfma / col_inv_mfma) are
+    // correct but measured slower than the VALU loops at this size (the
+    // operand staging is latency bound: 5.8 + 7.5 us against 4.1 + 3.4 us per
+    // column block at 74x74), so the VALU path is the default.
+    a.mfma = 0;
     a.rbv = rbv;
     a.S_ = cg_scalars(c);
     a.P = p_scalars(c);

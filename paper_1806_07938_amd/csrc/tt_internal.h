@@ -129,7 +129,7 @@ struct tt_ctx {
     // system
     bool ready = false;
     int n = 0, G = 0, C = 0, L = 0, Lh = 0, n_vs = 0, n_slopes = 0, n_layer = 0;
-    int nmodel = 0;
+    int model = 0;            // tt_gradient_model of the system
     DevBuf<float> M32;        // [Lh][L][3G^2]
     DevBuf<double> M64;
     DevBuf<int> vmap;         // n*n: valid index v or -1

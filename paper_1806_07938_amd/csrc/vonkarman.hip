@@ -1,7 +1,7 @@
 // Covariance generation in float64 on the device (row a1).
 //
-// Slope-slope tables (App. A.2 Hudgin-like slope-slope equations, §2.D cone
-// scaling): for every unordered guide-star pair g <= h, component c in
+// Slope-slope tables (App. A.2 Hudgin-like slope-slope equations, or the App.
+// A.3 Fried equations, §2.D cone scaling): for every unordered guide-star pair g <= h, component c in
 // {xx, xy (= yx), yy} and subaperture lag (U, V) in [-(n-1), n-1]^2 (U column,
 // V row, of the second slope relative to the first)
 //
@@ -40,7 +40,7 @@ __device__ inline double Dfun(double dx, double dy, const vk::Params& p) {
 }
 
 struct GenArgs {
-    int n, G, K;
+    int n, G, K, model;
     double d;
     vk::Params vk;
     const double* gs;   // 2G
@@ -69,7 +69,20 @@ __global__ void gen_slope_tables(GenArgs a, double* __restrict__ out, long total
         const double dy = sk * V * a.d + a.h[k] * by;
         const double del = sk * a.d;
         double v;
-        if (comp == 0) {
+        if (a.model == TT_MODEL_FRIED) {
+            // App. A.3: 1/8 [-4 D + 2 F1 - 2 F2 + F3 + F4] (xx), [-4 D - 2 F1 + 2 F2 + F3 + F4] (yy),
+            // 1/8 (F3 - F4) (xy = yx), slopes in rad
+            const double F3 = Dfun(dx + del, dy + del, a.vk) + Dfun(dx - del, dy - del, a.vk);
+            const double F4 = Dfun(dx + del, dy - del, a.vk) + Dfun(dx - del, dy + del, a.vk);
+            if (comp == 1) {
+                v = 0.125 * (F3 - F4);
+            } else {
+                const double F1 = Dfun(dx + del, dy, a.vk) + Dfun(dx - del, dy, a.vk);
+                const double F2 = Dfun(dx, dy + del, a.vk) + Dfun(dx, dy - del, a.vk);
+                const double sg = comp == 0 ? 1.0 : -1.0;
+                v = 0.125 * (-4.0 * Dfun(dx, dy, a.vk) + sg * (2.0 * F1 - 2.0 * F2) + F3 + F4);
+            }
+        } else if (comp == 0) {
             v = 0.5 * (-2.0 * Dfun(dx, dy, a.vk) + Dfun(dx + del, dy, a.vk) + Dfun(dx - del, dy, a.vk));
         } else if (comp == 2) {
             v = 0.5 * (-2.0 * Dfun(dx, dy, a.vk) + Dfun(dx, dy + del, a.vk) + Dfun(dx, dy - del, a.vk));
@@ -84,7 +97,7 @@ __global__ void gen_slope_tables(GenArgs a, double* __restrict__ out, long total
 }
 
 struct PhaseArgs {
-    int n, np, G, K;
+    int n, np, G, K, model;
     double d, bx, by;
     vk::Params vk;
     const double* gs;
@@ -108,8 +121,16 @@ __global__ void gen_phase_tables(PhaseArgs a, double* __restrict__ out, long tot
     const double dy = sk * a.d * (V + off) + a.h[k] * (a.gs[2 * g + 1] - a.by);
     const double e = 0.5 * sk * a.d;
     double v;
-    if (p == 0) v = 0.5 * (Dfun(dx - e, dy, a.vk) - Dfun(dx + e, dy, a.vk));
-    else v = 0.5 * (Dfun(dx, dy - e, a.vk) - Dfun(dx, dy + e, a.vk));
+    if (a.model == TT_MODEL_FRIED) {
+        // App. A.3: 1/4 (-F5 + F6 + F7 - F8) (x), 1/4 (-F5 - F6 + F7 + F8) (y)
+        const double F5 = Dfun(dx + e, dy + e, a.vk), F6 = Dfun(dx - e, dy + e, a.vk);
+        const double F7 = Dfun(dx - e, dy - e, a.vk), F8 = Dfun(dx + e, dy - e, a.vk);
+        v = p == 0 ? 0.25 * (-F5 + F6 + F7 - F8) : 0.25 * (-F5 - F6 + F7 + F8);
+    } else if (p == 0) {
+        v = 0.5 * (Dfun(dx - e, dy, a.vk) - Dfun(dx + e, dy, a.vk));
+    } else {
+        v = 0.5 * (Dfun(dx, dy - e, a.vk) - Dfun(dx, dy + e, a.vk));
+    }
     out[idx] = a.w[k] * v;
 }
 
@@ -137,6 +158,7 @@ tt_status gen_tables_launch(const tt_kernels& k, double* d_out, hipStream_t s) {
     const std::vector<double> cf = cone_factors(k.h, k.lgs, k.h_lgs);
     TT_CHECK(sc.upload(cf.data(), cf.size(), s));
     GenArgs a;
+    a.model = k.model;
     a.n = k.n;
     a.G = k.n_gs;
     a.K = k.n_layer;
@@ -162,6 +184,7 @@ tt_status gen_phase_tables_launch(const tt_ctx& c, int np, double* d_out, hipStr
     const std::vector<double> cf = cone_factors(c.h, c.lgs, c.h_lgs);
     TT_CHECK(sc.upload(cf.data(), cf.size(), s));
     PhaseArgs a;
+    a.model = c.model;
     a.n = c.n;
     a.np = np;
     a.G = c.G;

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libtt.so")
 TT_OK, TT_INVALID_ARG, TT_HIP_ERROR, TT_OUT_OF_MEMORY, TT_NOT_CONVERGED, TT_BREAKDOWN, TT_NOT_READY = range(7)
 PREC_F32, PREC_F64 = 0, 1
 SOLVER_PERSISTENT, SOLVER_KERNELS = 0, 1
-MODEL_HUDGIN = 0
+MODEL_HUDGIN, MODEL_FRIED = 0, 1
 
 # Every function declared in include/tt.h.
 EXPORTED = (
@@ -189,12 +189,13 @@ class Context:
 
     # -- set-up -----------------------------------------------------------
     def generate_kernels(self, n: int, n_gs: int, pad_L: int, D: float, h_lgs: float,
-                         gs_xy: Sequence[Sequence[float]], valid, h, w, r0: float, L0: float) -> Kernels:
+                         gs_xy: Sequence[Sequence[float]], valid, h, w, r0: float, L0: float,
+                         model: int = MODEL_HUDGIN) -> Kernels:
         gs = np.ascontiguousarray(np.asarray(gs_xy, dtype=np.float64).reshape(-1))
         vm = np.ascontiguousarray(np.asarray(valid, dtype=np.uint8).reshape(-1))
         hh = np.ascontiguousarray(np.asarray(h, dtype=np.float64))
         ww = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
-        geo = _Geometry(n, n_gs, pad_L, MODEL_HUDGIN, float(D), float(h_lgs) if math.isfinite(h_lgs) else math.inf,
+        geo = _Geometry(n, n_gs, pad_L, int(model), float(D), float(h_lgs) if math.isfinite(h_lgs) else math.inf,
                         gs.ctypes.data_as(C.POINTER(C.c_double)), vm.ctypes.data_as(C.POINTER(C.c_ubyte)))
         atm = _Atmosphere(hh.size, hh.ctypes.data_as(C.POINTER(C.c_double)),
                           ww.ctypes.data_as(C.POINTER(C.c_double)), float(r0), float(L0))
@@ -285,8 +286,9 @@ def system_from(ctx: Context, wl, target: bool = True, pad_L: Optional[int] = No
                 n_prime: int = 0) -> Kernels:
     """Generate kernels and set the system of `ctx` from any object with the
     attributes n, D, gs, h_lgs, h, w, r0, L0, valid, pad_L, noise_var, target."""
+    model = MODEL_FRIED if getattr(wl, "model", "hudgin") == "fried" else MODEL_HUDGIN
     k = ctx.generate_kernels(wl.n, wl.gs.shape[0], int(pad_L or wl.pad_L), wl.D, wl.h_lgs, wl.gs, wl.valid,
-                             wl.h, wl.w, wl.r0, wl.L0)
+                             wl.h, wl.w, wl.r0, wl.L0, model=model)
     ctx.set_system(k, noise_scalar=wl.noise_var, target=(tuple(wl.target) if target else None),
                    n_prime=n_prime, proj_pad_L=proj_pad_L)
     return k

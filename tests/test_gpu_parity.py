@@ -110,3 +110,22 @@ def test_projection(case):
     ref = phi_paper_dense(wl, z.astype(np.float32).astype(np.float64))
     assert phi.shape == ref.shape
     assert np.linalg.norm(phi - ref) / np.linalg.norm(ref) < 1e-5
+
+
+@pytest.mark.parametrize("case", [dict(n=4, n_gs=3, lgs=True, n_layer=2, seed=3), dict(n=6, n_gs=2, lgs=False, n_layer=3, seed=8)])
+def test_fried_model(case):
+    # App. A.3 Fried gradient model: tables, matrix-vector product and projection
+    import torch
+    from oracle.covariance import system_matrix
+    from oracle.projection import phi_paper_dense
+    wl = W.tiny(**case)
+    wl.model = "fried"
+    say("fried", wl.name)
+    dev = torch_dev()
+    ctx, k = make_system(wl, target=True)
+    assert rel_maxabs(k.tables(), oracle_tables_packed(wl)) < 1e-11
+    x = np.random.default_rng(4).standard_normal(wl.n_slopes)
+    assert rel_maxabs(ctx.matvec_f64(torch.tensor(x, device=dev)).cpu().numpy(), system_matrix(wl) @ x) < 1e-11
+    phi = ctx.project(torch.tensor(x, device=dev)).cpu().numpy()
+    ref = phi_paper_dense(wl, x.astype(np.float32).astype(np.float64))
+    assert np.linalg.norm(phi - ref) / np.linalg.norm(ref) < 1e-5

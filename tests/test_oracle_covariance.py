@@ -141,3 +141,61 @@ def test_config1_counts():
     wl = W.c1()
     assert wl.n_vs == 76 and wl.n_slopes == 456
     assert W.pupil_mask(74, 39.0, 0.28).sum() == 3972
+
+
+def fried_stencil_product_cov(wl):
+    """Fried slopes (App. A.3) as +-1/2 combinations of the four corner phases."""
+    idx = G.valid_index(wl.valid)
+    r = G.subap_centers(wl.n, wl.d)[idx]
+    s = G.cone_scale(wl.h, wl.h_lgs)
+    nv = r.shape[0]
+    nslope = 2 * wl.n_gs * nv
+    corners = np.array([[1, 1], [-1, 1], [-1, -1], [1, -1]], dtype=float)   # a, b, c, d
+    wx = np.array([1, -1, -1, 1]) * 0.5
+    wy = np.array([1, 1, -1, -1]) * 0.5
+    total = np.zeros((nslope, nslope))
+    for k in range(wl.n_layer):
+        pts, Gm = [], np.zeros((nslope, 4 * nslope))
+        row = 0
+        for g in range(wl.n_gs):
+            for p in range(2):
+                wts = wx if p == 0 else wy
+                for v in range(nv):
+                    base = s[k] * r[v] + wl.h[k] * wl.gs[g]
+                    for q in range(4):
+                        pts.append(base + 0.5 * s[k] * wl.d * corners[q])
+                        Gm[row, len(pts) - 1] = wts[q]
+                    row += 1
+        pts = np.array(pts)
+        diff = pts[:, None, :] - pts[None, :, :]
+        Cpp = 5.0 - 0.5 * structure_function(np.hypot(diff[..., 0], diff[..., 1]), wl.r0, wl.L0)
+        total += wl.w[k] * (Gm @ Cpp @ Gm.T)
+    return total
+
+
+@pytest.mark.parametrize("case", CASES[1:4])
+def test_fried_matches_corner_stencil(case):
+    wl = W.tiny(**case)
+    wl.model = "fried"
+    S = C.slope_covariance(wl)
+    R = fried_stencil_product_cov(wl)
+    assert np.abs(S - R).max() <= 1e-10 * np.abs(R).max()
+    tabs = C.kernel_tables(wl)
+    assert np.allclose(tabs[(0, 1, 0, 1)], tabs[(0, 1, 1, 0)], rtol=0, atol=1e-12)
+
+
+def test_fried_has_an_invisible_waffle_mode():
+    # App. A.3: the Fried model does not see the checkerboard (waffle) phase
+    wl = W.tiny(n=4, n_gs=1, lgs=False, n_layer=1, seed=1, mask="full")
+    n, d = wl.n, wl.d
+    i, j = np.divmod(np.arange((n + 1) ** 2), n + 1)
+    waffle = (-1.0) ** (i + j)
+    sx = np.zeros((n, n))
+    sy = np.zeros((n, n))
+    ph = waffle.reshape(n + 1, n + 1)
+    for a in range(n):
+        for b in range(n):
+            pa, pb, pc, pd = ph[a + 1, b + 1], ph[a + 1, b], ph[a, b], ph[a, b + 1]
+            sx[a, b] = 0.5 * (pa - pb - pc + pd)
+            sy[a, b] = 0.5 * (pa + pb - pc - pd)
+    assert np.abs(sx).max() == 0 and np.abs(sy).max() == 0

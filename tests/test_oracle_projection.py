@@ -90,3 +90,28 @@ def test_interpolation_gap_is_small_for_config1():
 def test_grid_size_config2():
     assert P.new_grid_size(W.c2()) == 106
     assert P.new_grid_size(W.c1()) == 13
+
+
+def test_fried_phase_slope_matches_corner_points():
+    wl = W.tiny(n=3, n_gs=2, lgs=True, n_layer=2, seed=4)
+    wl.model = "fried"
+    rho = G.phase_points(wl.n, wl.d)
+    from oracle.covariance import phase_slope_cov
+    A = phase_slope_cov(wl, rho)
+    idx = G.valid_index(wl.valid)
+    r = G.subap_centers(wl.n, wl.d)[idx]
+    s = G.cone_scale(wl.h, wl.h_lgs)
+    cov = lambda a, b: 2.0 - 0.5 * structure_function(np.hypot(*(a - b).T), wl.r0, wl.L0)
+    corners = np.array([[1, 1], [-1, 1], [-1, -1], [1, -1]], dtype=float)
+    wts = {0: [0.5, -0.5, -0.5, 0.5], 1: [0.5, 0.5, -0.5, -0.5]}
+    B = np.zeros_like(A)
+    col = 0
+    for g in range(wl.n_gs):
+        for p in range(2):
+            for v in range(r.shape[0]):
+                for k in range(wl.n_layer):
+                    c0 = s[k] * r[v] + wl.h[k] * wl.gs[g]
+                    for q in range(4):
+                        B[:, col] += wl.w[k] * wts[p][q] * cov(rho, (c0 + 0.5 * s[k] * wl.d * corners[q])[None])
+                col += 1
+    assert np.abs(A - B).max() <= 1e-11 * np.abs(B).max()

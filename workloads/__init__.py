@@ -52,6 +52,7 @@ class Workload:
     pad_L: int                  # FFT side for the slope-slope products
     valid: np.ndarray           # (n, n) bool, row-major, row i = y, column j = x
     target: tuple = (0.0, 0.0)  # reconstruction direction [rad]
+    model: str = "hudgin"       # gradient model of the reconstructor: "hudgin" or "fried"
 
     @property
     def d(self) -> float:
