@@ -43,7 +43,29 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the FP64 / kernel-solver side numbers")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy a 256 MiB device buffer 3 times (reference kernel for rocprofv3 "
+                         "FETCH_SIZE / WRITE_SIZE scale factors)")
     return ap.parse_args()
+
+
+def traffic_record():
+    """HBM traffic of the persistent kernel measured with rocprofv3 counters
+    (profiles/*_traffic.md), valid only while the kernel source is unchanged."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_cg_persistent_f32_c2_L148_traffic.md")
+    src = os.path.join(ROOT, "paper_1806_07938_amd", "csrc", "persistent.hip")
+    try:
+        rec = {}
+        for line in open(path):
+            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_iteration", "kernel_source_sha256"):
+                k, v = line.split(":", 1)
+                rec[k] = v.strip()
+        if rec.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+            return None
+        return float(rec["traffic_bytes_per_iteration"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(wl, s_frame, tol):
@@ -78,6 +100,13 @@ def main():
     from paper_1806_07938_amd.tt import PREC_F32, PREC_F64, SOLVER_KERNELS, SOLVER_PERSISTENT
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        cx = torch.ones(64 * 1024 * 1024, device=dev)
+        cy = torch.empty_like(cx)
+        for _ in range(3):
+            cy.copy_(cx)
+        torch.cuda.synchronize()
+        del cx, cy
     wl = W.c2(pad_L=args.pad)
     frames = W.turbulent_slopes(wl, frames=args.frames).astype(np.float32)
 
@@ -123,8 +152,11 @@ def main():
         avg_launch_ms = kms.sum() / launches.sum()
         bytes_launch = bytes_iter * iters.sum() / launches.sum()
         achieved = bytes_launch / (avg_launch_ms * 1e-3) / 1e9
+        tpi = traffic_record() if (prec == PREC_F32 and args.pad == 148) else None
+        traffic = round(tpi * iters.sum() / launches.sum()) if tpi else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
                     "kernel": f"k_cg_persistent<{'float' if prec == PREC_F32 else 'double'}>",
                     "avg_launch_ms": round(avg_launch_ms, 4), "bytes_per_iteration": int(bytes_iter),
                     "iterations_per_launch": round(float(iters.sum() / launches.sum()), 1)}
