@@ -66,7 +66,15 @@ typedef enum {
                                residual refinement (true residual b - A x with the
                                FP64 operator each time the FP32 residual has
                                dropped by refine_drop); certifies tol in FP64 */
-    TT_PREC_F64 = 1         /* FP64 throughout */
+    TT_PREC_F64 = 1,        /* FP64 throughout */
+    TT_PREC_F16 = 2,        /* as TT_PREC_F32, but the column DFT stages of the
+                               2RBT product (the dense contractions over the
+                               first FFT axis, forward and inverse) run on the
+                               matrix cores with FP16 operands (twiddles and data,
+                               the data scaled per column block by a power of two)
+                               and FP32 accumulation; the FP64 refinement still
+                               certifies tol.  TT_SOLVER_PERSISTENT only. */
+    TT_PREC_BF16 = 3        /* as TT_PREC_F16 with BF16 operands */
 } tt_precision;
 
 typedef enum {

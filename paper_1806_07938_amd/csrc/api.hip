@@ -187,7 +187,11 @@ tt_status solve_impl(tt_ctx* c, const float* s, const double* x0, double* zeta, 
     if (opts) o = *opts;
     TT_REQUIRE(std::isfinite(o.tol) && o.tol >= 0, "tol must be >= 0");
     TT_REQUIRE(o.max_iter >= 0, "max_iter must be >= 0");
-    TT_REQUIRE(o.precision == TT_PREC_F32 || o.precision == TT_PREC_F64, "unknown precision");
+    TT_REQUIRE(o.precision == TT_PREC_F32 || o.precision == TT_PREC_F64 || o.precision == TT_PREC_F16 ||
+                   o.precision == TT_PREC_BF16,
+               "unknown precision");
+    TT_REQUIRE(o.solver == TT_SOLVER_PERSISTENT || (o.precision != TT_PREC_F16 && o.precision != TT_PREC_BF16),
+               "TT_PREC_F16 / TT_PREC_BF16 need TT_SOLVER_PERSISTENT");
     TT_REQUIRE(o.solver == TT_SOLVER_PERSISTENT || o.solver == TT_SOLVER_KERNELS, "unknown solver");
     TT_REQUIRE(std::isfinite(o.refine_drop) && o.refine_drop >= 0 && o.refine_drop < 1, "refine_drop in [0, 1)");
     TT_CHECK(use_device(c->device));

@@ -40,6 +40,9 @@
 // decision at the top of every iteration.
 #include "cg_common.h"
 
+#include <algorithm>
+#include <cstring>
+
 namespace {
 
 constexpr int PT = 512;                                  // threads per block
@@ -62,7 +65,9 @@ struct PArgs {
     double* part;            // [2][nwg][4]: partial r.r, sigma^2 r.r, r.C r (Parseval)
     int vreg;                // CG vectors held in registers (rows per block * n <= threads)
     int rbv;                 // rows per block at a time
-    int mfma;                // column transforms on the matrix cores (FP32); 0 = VALU
+    const uint2* FAm;        // [S][MTf][TKf][64] forward column-transform operand fragments (MF > 0)
+    const uint2* FBm;        // [S][MTi][TKi][64] inverse column-transform operand fragments (MF > 0)
+    int MTf, TKf, MTi, TKi;  // fragment tiles and K steps of the two column transforms
     CgScalars* S_;
     PScalars* P;
     unsigned* bar;           // barrier words: [0] top counter, [16] abort, [32 + 32 g] group counters
@@ -153,8 +158,10 @@ __device__ D3 block_sum3(D3 v, double* red) {
 
 template <typename R>
 struct Tiles {
-    const cplx<R>* Fa;
+    const cplx<R>* Fa;    // VALU column transforms
     const cplx<R>* Fb;
+    const uint2* FAm;     // matrix-core column transforms: this block's fragments
+    const uint2* FBm;
     const cplx<R>* Gr;
     const R* Ms;       // resident: [slot][Lrm]; else null
     const R* Mg;       // global: M + f2 L P (used when Ms is null)
@@ -198,11 +205,21 @@ __device__ void gather_u(const PArgs<R>& a, cplx<R>* Us, int base, int stride, i
         const int row = base + k * stride;
         const int c = row / n, ra = row % n;
         const cplx<R>* u = a.U + ((long)f2 * S * C + c) * n + ra;
-        R ux = 0, uy = 0;
-        for (int part = 0; part < S; ++part) {
-            const cplx<R> q = u[(long)part * C * n];
-            ux += q.x;
-            uy += q.y;
+        // the first (up to) four ranges loaded together, then summed in order
+        cplx<R> q[4];
+#pragma unroll
+        for (int part = 0; part < 4; ++part) q[part] = part < S ? u[(long)part * C * n] : cplx<R>{0, 0};
+        R ux = q[0].x, uy = q[0].y;
+#pragma unroll
+        for (int part = 1; part < 4; ++part)
+            if (part < S) {
+                ux += q[part].x;
+                uy += q[part].y;
+            }
+        for (int part = 4; part < S; ++part) {
+            const cplx<R> w = u[(long)part * C * n];
+            ux += w.x;
+            uy += w.y;
         }
         Us[k * Lh + f2] = cplx<R>{ux, uy};
     }
@@ -267,13 +284,9 @@ template <typename R>
 __device__ void row_phase_reg(const PArgs<R>& a, const Tiles<R>& t, Lane<R>& v, int nrk, bool update, R alpha,
                               R beta, int par, double* red) {
     const int n = a.n, Lh = a.Lh, L = a.L;
-    cplx<R>* Us = t.work;
+    cplx<R>* Us = t.work;   // filled by gather_u before the call when update is set
     R* xs = reinterpret_cast<R*>(Us + a.rbv * Lh);
     __syncthreads();
-    if (update) {
-        gather_u(a, Us, blockIdx.x * a.rbv, 1, nrk);
-        __syncthreads();
-    }
     double g = 0.0, sg = 0.0;
     if ((int)threadIdx.x < nrk * n) {
         const int k = threadIdx.x / n, b = threadIdx.x % n;
@@ -356,82 +369,162 @@ __device__ void row_phase_mem(const PArgs<R>& a, const Tiles<R>& t, bool update,
 }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef short i16x4 __attribute__((ext_vector_type(4)));
 
-// Forward column transform on the matrix cores (FP32).  As a real product
-// X (Lr x 2C) = A (Lr x 2n) B (2n x 2C) with A[j][2a+e] = (Re, Im) F[f1a+j][a]
-// and B[2a+e][2c+f] built from T[c][a] so that column 2c is Re X_c and 2c+1 is
-// Im X_c.  v_mfma_f32_16x16x4f32 lane layout: A[l%16][l/16], B[l/16][l%16],
-// result element v of lane l at row 4(l/16)+v, column l%16.  One 16x16 output
-// tile per wave, the K loop in steps of 4.
-__device__ void col_fwd_mfma(const cplx<float>* Fa, const cplx<float>* Tc, cplx<float>* Xh, int n, int C, int Lr,
-                             int Lrm) {
+// Column transforms on the matrix cores.  Both are real products
+//   forward  X (Lr x 2C) = A (Lr x 2n) B (2n x 2C):  A[j][(a,e)] = (Re, Im) F[f1a+j][a],
+//            B[(a,0)][2c+f] = (Re T, Im T)[f],  B[(a,1)][2c+f] = (-Im T, Re T)[f],  T = T[c][a]
+//   inverse  U (n x 2C) = A' (n x 2Lr) B' (2Lr x 2C): A'[a][(j,e)] = (Re, Im) F[f1a+j][a],
+//            B'[(j,0)][2p+f] = (Re Y, Im Y)[f],  B'[(j,1)][2p+f] = (Im Y, -Re Y)[f],  Y = Y[p][j]
+// so that column 2c (2p) of the result is the real and column 2c+1 the
+// imaginary part of X_c = sum_a F[.][a] T[c][a]  (U_p = sum_j Y[p][j] conj F[j][a]).
+// One 16 x 16 output tile per wave at a time; the K index (a, e) (or (j, e)) is
+// taken in an order that lets a lane read one complex operand per K step pair:
+//   MF = 1, FP32, v_mfma_f32_16x16x4f32: lane (kq = l/16, lc = l%16) supplies
+//       A[lc][k], B[k][lc] with k = (4t + kq, e) at the two steps (t, e = 0, 1);
+//   MF = 2, 3, FP16 / BF16 operands, v_mfma_f32_16x16x16{f16,bf16_1k}: lane
+//       supplies the 4 K values (8t + 2kq, e), (8t + 2kq + 1, e), e = 0, 1.
+// The result element v of lane l is row 4 kq + v, column lc of the tile.
+// The constant operand (A, A') is precomputed in exactly this lane order
+// (uint2 per lane per step: one complex FP32, or four 16-bit values), zero
+// outside the transform, so that a wave reads 64 consecutive 8-byte words per
+// step.  FP16 / BF16 data operands are multiplied by sc, a power of two that
+// brings the block's largest magnitude to [2^13, 2^14); results are multiplied
+// by 1/sc, both exact.
+__device__ inline unsigned short bf16_bits(float x) {
+    const unsigned u = __float_as_uint(x);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);   // round to nearest even
+}
+
+template <int MF>
+__device__ inline f32x4 mfma_k16(uint2 av, float b0, float b1, float b2, float b3, float sc, f32x4 acc) {
+    if constexpr (MF == 2) {
+        const f16x4 A = __builtin_bit_cast(f16x4, av);
+        const f16x4 B = {(_Float16)(b0 * sc), (_Float16)(b1 * sc), (_Float16)(b2 * sc), (_Float16)(b3 * sc)};
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(A, B, acc, 0, 0, 0);
+    } else {
+        const i16x4 A = __builtin_bit_cast(i16x4, av);
+        const i16x4 B = {(short)bf16_bits(b0 * sc), (short)bf16_bits(b1 * sc), (short)bf16_bits(b2 * sc),
+                         (short)bf16_bits(b3 * sc)};
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B, acc, 0, 0, 0);
+    }
+}
+
+// power of two bringing a largest magnitude (float bits, >= 0) to [2^13, 2^14)
+__device__ inline float mf_scale(int mbits) {
+    const int e = (mbits >> 23) & 0xff;
+    if (mbits <= 0 || e == 0xff) return 1.0f;
+    int se = 267 - e;
+    se = se < 1 ? 1 : (se > 253 ? 253 : se);
+    return __uint_as_float((unsigned)se << 23);
+}
+
+// One K step of a column transform: operands already loaded (av: constant
+// side; w0, w1: data-side complex values, masked), accumulated into acc.
+//   fwd (INV = false): B = ((Re, Im)[f], (-Im, Re)[f]) of w
+//   inv (INV = true):  B = ((Re, Im)[f], (Im, -Re)[f]) of w
+template <int MF, bool INV>
+__device__ inline f32x4 col_step(uint2 av, cplx<float> w0, cplx<float> w1, int f, float sc, f32x4 acc) {
+    const float p0 = f ? w0.y : w0.x;
+    const float q0 = INV ? (f ? -w0.x : w0.y) : (f ? w0.x : -w0.y);
+    if constexpr (MF == 1) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.x), p0, acc, 0, 0, 0);
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av.y), q0, acc, 0, 0, 0);
+    } else {
+        const float p1 = f ? w1.y : w1.x;
+        const float q1 = INV ? (f ? -w1.x : w1.y) : (f ? w1.x : -w1.y);
+        return mfma_k16<MF>(av, p0, q0, p1, q1, sc, acc);
+    }
+}
+
+// data-side operand(s) of K step t for this lane: index k0 (and k0 + 1) of
+// the row src, masked to zero outside [0, kmax) or for an unused column
+template <int MF>
+__device__ inline void col_load(const cplx<float>* src, int t, int kq, int kmax, bool colok, cplx<float>& w0,
+                                cplx<float>& w1) {
+    const int k0 = MF == 1 ? 4 * t + kq : 8 * t + 2 * kq;
+    w0 = src[k0 < kmax ? k0 : 0];
+    if (!(colok && k0 < kmax)) w0 = cplx<float>{0.f, 0.f};
+    if constexpr (MF != 1) {
+        w1 = src[k0 + 1 < kmax ? k0 + 1 : 0];
+        if (!(colok && k0 + 1 < kmax)) w1 = cplx<float>{0.f, 0.f};
+    }
+}
+
+// One output tile per wave at a time: the K loop runs in groups of 4 steps
+// (all loads of a group issued before its products, on two accumulators) and
+// a remainder of single steps.  INV selects the inverse transform.
+template <int MF, bool INV>
+__device__ void col_mf(const uint2* FR, const cplx<float>* src, int srcstride, int kmax, float* dst, int dststride,
+                       int rmax, int C, int MT, int TK, float sc) {
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, kq = l >> 4, lc = l & 15;
-    const int MT = (Lr + 15) / 16, NT = (2 * C + 15) / 16, KS = (2 * n + 3) / 4;
+    const int NT = (2 * C + 15) / 16;
+    const float isc = 1.0f / sc;
     for (int tp = wave; tp < MT * NT; tp += PT / 64) {
         const int mt = tp % MT, nt = tp / MT;
-        const int j = mt * 16 + lc;
-        const int col = nt * 16 + lc, cB = col >> 1, fB = col & 1;
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        for (int s = 0; s < KS; ++s) {
-            const int k = 4 * s + kq, ai = k >> 1, e = k & 1;
-            float av = 0.f, bv = 0.f;
-            if (ai < n) {
-                if (j < Lr) {
-                    const cplx<float> f = Fa[ai * Lrm + j];
-                    av = e ? f.y : f.x;
-                }
-                if (cB < C) {
-                    const cplx<float> t = Tc[cB * n + ai];
-                    bv = e == 0 ? (fB ? t.y : t.x) : (fB ? t.x : -t.y);
-                }
+        const int c = nt * 8 + (lc >> 1), f = lc & 1;
+        const bool cv = c < C;
+        const cplx<float>* sp = src + (cv ? c : 0) * srcstride;
+        const uint2* fr = FR + (long)mt * TK * 64 + l;
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+        int t = 0;
+        for (; t + 4 <= TK; t += 4) {
+            uint2 av[4];
+            cplx<float> w0[4], w1[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                av[u] = fr[(t + u) * 64];
+                col_load<MF>(sp, t + u, kq, kmax, cv, w0[u], w1[u]);
             }
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+#pragma unroll
+            for (int u = 0; u < 4; u += 2) {
+                acc0 = col_step<MF, INV>(av[u], w0[u], w1[u], f, sc, acc0);
+                acc1 = col_step<MF, INV>(av[u + 1], w0[u + 1], w1[u + 1], f, sc, acc1);
+            }
         }
-        if (cB < C)
+        for (; t < TK; ++t) {
+            cplx<float> w0, w1;
+            col_load<MF>(sp, t, kq, kmax, cv, w0, w1);
+            acc0 = col_step<MF, INV>(fr[t * 64], w0, w1, f, sc, acc0);
+        }
+        if (cv)
             for (int v = 0; v < 4; ++v) {
-                const int jj = mt * 16 + 4 * kq + v;
-                if (jj < Lr) reinterpret_cast<float*>(&Xh[cB * Lrm + jj])[fB] = acc[v];
+                const int row = mt * 16 + 4 * kq + v;
+                const float r = acc0[v] + acc1[v];
+                if (row < rmax) dst[2 * (c * dststride + row) + f] = MF == 1 ? r : r * isc;
             }
     }
 }
 
-// Partial inverse column transform on the matrix cores (FP32):
-// U (n x 2C) = A (n x 2Lr) B (2Lr x 2C), A[a][2j+e] = (Re, Im) F[f1a+j][a],
-// B[2j+e][2p+f] from Y[p][j] so that U_p = sum_j Y_p[j] conj(F[f1a+j][a]).
-__device__ void col_inv_mfma(const cplx<float>* Fb, const cplx<float>* Yh, cplx<float>* Uo, int n, int C, int Lr,
-                             int Lrm) {
-    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, kq = l >> 4, lc = l & 15;
-    const int MT = (n + 15) / 16, NT = (2 * C + 15) / 16, KS = (2 * Lr + 3) / 4;
-    for (int tp = wave; tp < MT * NT; tp += PT / 64) {
-        const int mt = tp % MT, nt = tp / MT;
-        const int ar = mt * 16 + lc;
-        const int col = nt * 16 + lc, pB = col >> 1, fB = col & 1;
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        for (int s = 0; s < KS; ++s) {
-            const int k = 4 * s + kq, jj = k >> 1, e = k & 1;
-            float av = 0.f, bv = 0.f;
-            if (jj < Lr) {
-                if (ar < n) {
-                    const cplx<float> f = Fb[jj * n + ar];
-                    av = e ? f.y : f.x;
-                }
-                if (pB < C) {
-                    const cplx<float> y = Yh[pB * Lrm + jj];
-                    bv = e == 0 ? (fB ? y.y : y.x) : (fB ? -y.x : y.y);
-                }
-            }
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
-        }
-        if (pB < C)
-            for (int v = 0; v < 4; ++v) {
-                const int a2 = mt * 16 + 4 * kq + v;
-                if (a2 < n) reinterpret_cast<float*>(&Uo[pB * n + a2])[fB] = acc[v];
-            }
-    }
+// forward: Xh[c][j] = sum_a F[f1a+j][a] Tc[c][a], j < Lr
+template <int MF>
+__device__ inline void col_fwd_mf(const uint2* FA, const cplx<float>* Tc, cplx<float>* Xh, int n, int C, int Lr,
+                                  int Lrm, int MT, int TK, float sc) {
+    col_mf<MF, false>(FA, Tc, n, n, reinterpret_cast<float*>(Xh), Lrm, Lr, C, MT, TK, sc);
 }
 
-template <typename R>
-__device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, int par, double* red) {
+// inverse (partial over this f1 range): Uo[p][a] = sum_j Yh[p][j] conj F[f1a+j][a], a < n
+template <int MF>
+__device__ inline void col_inv_mf(const uint2* FB, const cplx<float>* Yh, cplx<float>* Uo, int n, int C, int Lr,
+                                  int Lrm, int MT, int TK, float sc) {
+    col_mf<MF, true>(FB, Yh, Lrm, Lr, reinterpret_cast<float*>(Uo), n, n, C, MT, TK, sc);
+}
+
+// largest |value| over the block, as float bits, accumulated into *slot
+__device__ inline void block_max_bits(float m, int* slot) {
+    int b = (int)__float_as_uint(m);
+    for (int o = 32; o > 0; o >>= 1) {
+        const int q = __shfl_xor(b, o);
+        b = q > b ? q : b;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(slot, b);
+}
+
+// MF: column transforms on the VALU (0) or on the matrix cores with FP32 (1),
+// FP16 (2) or BF16 (3) operands and FP32 accumulation.
+template <typename R, int MF>
+__device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, int par, double* red, int* s_mx) {
     const int n = a.n, L = a.L, C = a.C, G = a.G, S = a.S, Lrm = a.Lrm;
     double accd = 0.0;
     if (blockIdx.x < a.Lh * S) {
@@ -441,14 +534,22 @@ __device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, int par, double*
         cplx<R>* Tc = t.work;          // [C][n]
         cplx<R>* Xh = Tc + C * n;      // [C][Lrm]
         cplx<R>* Yh = Xh + C * Lrm;    // [C][Lrm]
+        if (MF >= 2 && threadIdx.x == 0) s_mx[0] = s_mx[1] = 0;
         __syncthreads();
-        for (int i = threadIdx.x; i < C * n; i += PT) Tc[i] = a.T[(long)f2 * C * n + i];
-        __syncthreads();
-        // forward column transform: matrix cores (FP32) or two channels per lane on the VALU
-        if constexpr (sizeof(R) == 4) {
-            if (a.mfma) col_fwd_mfma(t.Fa, Tc, Xh, n, C, Lr, Lrm);
+        {
+            R m = 0;
+            for (int i = threadIdx.x; i < C * n; i += PT) {
+                const cplx<R> q = a.T[(long)f2 * C * n + i];
+                Tc[i] = q;
+                if constexpr (MF >= 2) m = fmaxf(m, fmaxf(fabsf(q.x), fabsf(q.y)));
+            }
+            if constexpr (MF >= 2) block_max_bits(m, s_mx);
         }
-        if (sizeof(R) != 4 || !a.mfma) {
+        __syncthreads();
+        // forward column transform: matrix cores, or two channels per lane on the VALU
+        if constexpr (MF > 0) {
+            col_fwd_mf<MF>(t.FAm, Tc, Xh, n, C, Lr, Lrm, a.MTf, a.TKf, MF >= 2 ? mf_scale(s_mx[0]) : 1.0f);
+        } else {
         for (int i = threadIdx.x; i < (C / 2) * Lr; i += PT) {
             const int cp = i / Lr, j = i % Lr;
             const cplx<R>* t0 = Tc + (2 * cp) * n;
@@ -482,6 +583,7 @@ __device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, int par, double*
         __syncthreads();
         // per-frequency products, x and y outputs of one sensor per lane
         const double wt2 = ((f2 == 0) || ((L % 2) == 0 && 2 * f2 == L)) ? 1.0 : 2.0;
+        R ym = 0;
         for (int i = threadIdx.x; i < G * Lr; i += PT) {
             const int g = i / Lr, j = i % Lr;
             R y0r = 0, y0i = 0, y1r = 0, y1i = 0;
@@ -498,14 +600,15 @@ __device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, int par, double*
             Yh[(2 * g + 1) * Lrm + j] = cplx<R>{y1r, y1i};
             const cplx<R> x0 = Xh[(2 * g) * Lrm + j], x1 = Xh[(2 * g + 1) * Lrm + j];
             accd += wt2 * ((double)x0.x * y0r + (double)x0.y * y0i + (double)x1.x * y1r + (double)x1.y * y1i);
+            if constexpr (MF >= 2) ym = fmaxf(ym, fmaxf(fmaxf(fabsf(y0r), fabsf(y0i)), fmaxf(fabsf(y1r), fabsf(y1i))));
         }
+        if constexpr (MF >= 2) block_max_bits(ym, s_mx + 1);
         __syncthreads();
         // partial inverse column transform over this f1 range
         cplx<R>* Uo = a.U + (((long)f2 * S + part) * C) * n;
-        if constexpr (sizeof(R) == 4) {
-            if (a.mfma) col_inv_mfma(t.Fb, Yh, Uo, n, C, Lr, Lrm);
-        }
-        if (sizeof(R) != 4 || !a.mfma) {
+        if constexpr (MF > 0) {
+            col_inv_mf<MF>(t.FBm, Yh, Uo, n, C, Lr, Lrm, a.MTi, a.TKi, MF >= 2 ? mf_scale(s_mx[1]) : 1.0f);
+        } else {
         for (int i = threadIdx.x; i < (C / 2) * n; i += PT) {
             const int pp = i / n, ra = i % n;
             const cplx<R>* y0 = Yh + (2 * pp) * Lrm;
@@ -541,28 +644,48 @@ __device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, int par, double*
     if (threadIdx.x == 0) a.part[((long)par * a.nwg + blockIdx.x) * 4 + 2] = tot.a / ((double)a.L * (double)a.L);
 }
 
-template <typename R, bool RES>
+template <typename R, bool RES, int MF>
 __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
     extern __shared__ __align__(16) char smem_raw[];
     __shared__ double red[3 * PT / 64];
     __shared__ int s_flag;
+    __shared__ int s_mx[2];
     const int n = a.n, Lh = a.Lh, Lrm = a.Lrm, S = a.S, L = a.L, P = 3 * a.G * a.G;
     const bool colunit = blockIdx.x < Lh * S;
     const int f2 = colunit ? blockIdx.x / S : 0, part = colunit ? blockIdx.x % S : 0;
     const int f1a = (int)((long)part * L / S), f1b = (int)((long)(part + 1) * L / S);
+    const long fragA = (long)a.MTf * a.TKf * 64, fragB = (long)a.MTi * a.TKi * 64;
     Tiles<R> t;
     t.Mg = a.M + (long)f2 * L * P;
+    t.Fa = t.Fb = nullptr;
+    t.FAm = t.FBm = nullptr;
     if constexpr (RES) {
-        cplx<R>* Fa = reinterpret_cast<cplx<R>*>(smem_raw);
-        cplx<R>* Fb = Fa + n * Lrm;
-        cplx<R>* Gr = Fb + Lrm * n;
-        R* Ms = reinterpret_cast<R*>(Gr + Lh * n);
-        const cplx<R>* fa = a.Fa + (long)part * n * Lrm;
-        const cplx<R>* fb = a.Fb + (long)part * Lrm * n;
-        for (int i = threadIdx.x; i < n * Lrm; i += PT) {
-            Fa[i] = fa[i];
-            Fb[i] = fb[i];
+        char* q = smem_raw;
+        if constexpr (MF > 0) {
+            uint2* FAm = reinterpret_cast<uint2*>(q);
+            uint2* FBm = FAm + fragA;
+            const uint2* fa = a.FAm + part * fragA;
+            const uint2* fb = a.FBm + part * fragB;
+            for (int i = threadIdx.x; i < fragA; i += PT) FAm[i] = fa[i];
+            for (int i = threadIdx.x; i < fragB; i += PT) FBm[i] = fb[i];
+            t.FAm = FAm;
+            t.FBm = FBm;
+            q = reinterpret_cast<char*>(FBm + fragB);
+        } else {
+            cplx<R>* Fa = reinterpret_cast<cplx<R>*>(q);
+            cplx<R>* Fb = Fa + n * Lrm;
+            const cplx<R>* fa = a.Fa + (long)part * n * Lrm;
+            const cplx<R>* fb = a.Fb + (long)part * Lrm * n;
+            for (int i = threadIdx.x; i < n * Lrm; i += PT) {
+                Fa[i] = fa[i];
+                Fb[i] = fb[i];
+            }
+            t.Fa = Fa;
+            t.Fb = Fb;
+            q = reinterpret_cast<char*>(Fb + Lrm * n);
         }
+        cplx<R>* Gr = reinterpret_cast<cplx<R>*>(q);
+        R* Ms = reinterpret_cast<R*>(Gr + Lh * n);
         for (int i = threadIdx.x; i < Lh * n; i += PT) Gr[i] = a.Gr[i];
         const int Lr = f1b - f1a;
         if (colunit)
@@ -570,15 +693,18 @@ __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
                 const int slot = i / Lr, j = i % Lr;
                 Ms[slot * Lrm + j] = t.Mg[(long)(f1a + j) * P + slot];
             }
-        t.Fa = Fa;
-        t.Fb = Fb;
         t.Gr = Gr;
         t.Ms = Ms;
         t.work = reinterpret_cast<cplx<R>*>(Ms + P * Lrm);
         __syncthreads();
     } else {
-        t.Fa = a.Fa + (long)part * n * Lrm;
-        t.Fb = a.Fb + (long)part * Lrm * n;
+        if constexpr (MF > 0) {
+            t.FAm = a.FAm + part * fragA;
+            t.FBm = a.FBm + part * fragB;
+        } else {
+            t.Fa = a.Fa + (long)part * n * Lrm;
+            t.Fb = a.Fb + (long)part * Lrm * n;
+        }
         t.Gr = a.Gr;
         t.Ms = nullptr;
         t.work = reinterpret_cast<cplx<R>*>(smem_raw);
@@ -610,20 +736,30 @@ __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
     if (a.vreg) row_phase_reg<R>(a, t, v, nrk, false, R(0), R(0), it & 1, red);
     else row_phase_mem<R>(a, t, false, R(0), R(0), it & 1, red);
     if (!grid_sync(a.bar, a.nwg, epoch, &s_flag)) return;
-    col_phase<R>(a, t, it & 1, red);
+    col_phase<R, MF>(a, t, it & 1, red, s_mx);
     if (!grid_sync(a.bar, a.nwg, epoch, &s_flag)) return;
     double gprev = a.gprev, aprev = a.aprev;
     bool first = a.first != 0;
     const double tol2 = a.S_->tol2, drop2 = a.S_->drop2;
     while (true) {
         const int par = it & 1;
+        // The loads of the partial sums and of this block's column-phase outputs
+        // (for the next row phase) are issued together: one memory round trip.
         D3 pv{0.0, 0.0, 0.0};
-        for (int i = threadIdx.x; i < a.nwg; i += PT) {
-            const double* q = a.part + ((long)par * a.nwg + i) * 4;
-            pv.a += q[0];
-            pv.b += q[1];
-            pv.c += q[2];
+        if (a.nwg <= PT) {
+            if ((int)threadIdx.x < a.nwg) {
+                const double* q = a.part + ((long)par * a.nwg + threadIdx.x) * 4;
+                pv = D3{q[0], q[1], q[2]};
+            }
+        } else {
+            for (int i = threadIdx.x; i < a.nwg; i += PT) {
+                const double* q = a.part + ((long)par * a.nwg + i) * 4;
+                pv.a += q[0];
+                pv.b += q[1];
+                pv.c += q[2];
+            }
         }
+        if (a.vreg) gather_u(a, t.work, blockIdx.x * a.rbv, 1, nrk);
         const D3 tot = block_sum3(pv, red);
         const double g = tot.a;
         const double dl = tot.c + tot.b;
@@ -669,25 +805,134 @@ __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
         first = false;
         ++it;
         if (!grid_sync(a.bar, a.nwg, epoch, &s_flag)) return;
-        col_phase<R>(a, t, it & 1, red);
+        col_phase<R, MF>(a, t, it & 1, red, s_mx);
         if (!grid_sync(a.bar, a.nwg, epoch, &s_flag)) return;
     }
 }
 
+// Fragment tiles and K steps of the matrix-core column transforms (MF > 0).
+struct FragShape {
+    int MTf = 0, TKf = 0, MTi = 0, TKi = 0;
+    long a_words() const { return (long)MTf * TKf * 64; }
+    long b_words() const { return (long)MTi * TKi * 64; }
+};
+
+FragShape frag_shape(int MF, int n, int Lrm) {
+    FragShape f;
+    if (MF == 0) return f;
+    const int kstep = MF == 1 ? 4 : 8;   // K values (a or j) per lane step pair / per step
+    f.MTf = (Lrm + 15) / 16;
+    f.TKf = (n + kstep - 1) / kstep;
+    f.MTi = (n + 15) / 16;
+    f.TKi = (Lrm + kstep - 1) / kstep;
+    return f;
+}
+
 // LDS bytes: resident tiles (if RES) + work region (max of column and row needs)
 template <typename R>
-size_t lds_bytes(const tt_ctx& c, int Lrm, int rbv, bool res) {
+size_t lds_bytes(const tt_ctx& c, int Lrm, int rbv, bool res, int MF) {
     const size_t cs = sizeof(cplx<R>);
     const size_t colw = cs * ((size_t)c.C * c.n + 2ull * c.C * Lrm);
     const size_t roww = cs * (size_t)rbv * c.Lh + sizeof(R) * (size_t)rbv * c.n;
     size_t b = std::max(colw, roww);
-    if (res) b += cs * (2ull * c.n * Lrm + (size_t)c.Lh * c.n) + sizeof(R) * (size_t)packed_reals(c.G) * Lrm;
+    if (res) {
+        const FragShape fs = frag_shape(MF, c.n, Lrm);
+        b += MF > 0 ? 8 * (size_t)(fs.a_words() + fs.b_words()) : cs * 2ull * c.n * Lrm;
+        b += cs * (size_t)c.Lh * c.n + sizeof(R) * (size_t)packed_reals(c.G) * Lrm;
+    }
     return b;
 }
 
-// Host-built transform tiles for the persistent kernel (exact twiddle indices).
+// IEEE binary16 and bfloat16 bit patterns, round to nearest even (host).
+uint16_t half_bits(double v) {
+    const uint16_t sgn = std::signbit(v) ? 0x8000 : 0;
+    double x = std::fabs(v);
+    if (x == 0.0) return sgn;
+    if (x >= 65520.0) return sgn | 0x7c00;
+    int e = 0;
+    std::frexp(x, &e);                       // x = m 2^e, m in [0.5, 1)
+    if (e - 1 < -14) {                       // subnormal: multiples of 2^-24
+        const double q = std::nearbyint(std::ldexp(x, 24));
+        return sgn | (uint16_t)q;            // q = 1024 is the smallest normal
+    }
+    double q = std::nearbyint(std::ldexp(x, 11 - e) - 1024.0);   // 10 mantissa bits
+    int E = e - 1 + 15;
+    if (q >= 1024.0) {
+        q = 0.0;
+        ++E;
+    }
+    if (E >= 31) return sgn | 0x7c00;
+    return sgn | (uint16_t)(E << 10) | (uint16_t)q;
+}
+
+uint16_t bf16_bits_host(double v) {
+    const float f = (float)v;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// Operand fragments of the matrix-core column transforms for every f1 range,
+// in the lane order of col_fwd_mf / col_inv_mf; zero outside the transform.
+void build_frags(int MF, int n, int L, int S, int Lrm, const std::vector<double>& co, const std::vector<double>& si,
+                 std::vector<uint2>& FA, std::vector<uint2>& FB) {
+    const FragShape fs = frag_shape(MF, n, Lrm);
+    FA.assign((size_t)S * fs.a_words(), uint2{0u, 0u});
+    FB.assign((size_t)S * fs.b_words(), uint2{0u, 0u});
+    auto enc = [MF](double v) -> uint32_t {
+        if (MF == 1) {
+            const float f = (float)v;
+            uint32_t u;
+            std::memcpy(&u, &f, 4);
+            return u;
+        }
+        return MF == 2 ? half_bits(v) : bf16_bits_host(v);
+    };
+    for (int part = 0; part < S; ++part) {
+        const int f1a = (int)((long)part * L / S), Lr = (int)((long)(part + 1) * L / S) - f1a;
+        // (Re, Im) exp(-2 pi i f1 a / L) at local frequency j, encoded; zero outside
+        auto F = [&](int j, int a, uint32_t* re, uint32_t* im) {
+            *re = *im = 0u;
+            if (j < Lr && a < n) {
+                const int m = (int)(((long)(f1a + j) * a) % L);
+                *re = enc(co[m]);
+                *im = enc(-si[m]);
+            }
+        };
+        for (int pass = 0; pass < 2; ++pass) {
+            const int MT = pass == 0 ? fs.MTf : fs.MTi, TK = pass == 0 ? fs.TKf : fs.TKi;
+            uint2* out = (pass == 0 ? FA.data() : FB.data()) + (size_t)part * MT * TK * 64;
+            for (int mt = 0; mt < MT; ++mt)
+                for (int t = 0; t < TK; ++t)
+                    for (int l = 0; l < 64; ++l) {
+                        const int kq = l >> 4, lc = l & 15, row = mt * 16 + lc;
+                        uint2& w = out[((size_t)mt * TK + t) * 64 + l];
+                        if (MF == 1) {
+                            const int k = 4 * t + kq;
+                            if (pass == 0) F(row, k, &w.x, &w.y);   // j = row, a = k
+                            else F(k, row, &w.x, &w.y);             // j = k, a = row
+                        } else {
+                            const int k0 = 8 * t + 2 * kq;
+                            uint32_t r0, i0, r1, i1;
+                            if (pass == 0) {
+                                F(row, k0, &r0, &i0);
+                                F(row, k0 + 1, &r1, &i1);
+                            } else {
+                                F(k0, row, &r0, &i0);
+                                F(k0 + 1, row, &r1, &i1);
+                            }
+                            w.x = r0 | (i0 << 16);
+                            w.y = r1 | (i1 << 16);
+                        }
+                    }
+        }
+    }
+}
+
+// Host-built transform tiles for the persistent kernel (exact twiddle indices):
+// the VALU tiles (Fa, Fb), the row tiles (Gr) and, for MF > 0, the fragments.
 template <typename R>
-tt_status build_tiles(tt_ctx& c, int S, int Lrm) {
+tt_status build_tiles(tt_ctx& c, int S, int Lrm, int MF) {
     const int n = c.n, L = c.L, Lh = c.Lh;
     std::vector<double> co(L), si(L);
     for (int k = 0; k < L; ++k) {
@@ -719,16 +964,24 @@ tt_status build_tiles(tt_ctx& c, int S, int Lrm) {
     TT_HIP(hipMemcpyAsync(c.tFa.p, fa.data(), fa.size() * sc, hipMemcpyHostToDevice, c.stream));
     TT_HIP(hipMemcpyAsync(c.tFb.p, fb.data(), fb.size() * sc, hipMemcpyHostToDevice, c.stream));
     TT_HIP(hipMemcpyAsync(c.tGr.p, gr.data(), gr.size() * sc, hipMemcpyHostToDevice, c.stream));
-    TT_HIP(hipStreamSynchronize(c.stream));
+    if (MF > 0) {
+        std::vector<uint2> FA, FB;
+        build_frags(MF, n, L, S, Lrm, co, si, FA, FB);
+        TT_CHECK(c.tFAm.alloc(FA.size() + 1));
+        TT_CHECK(c.tFBm.alloc(FB.size() + 1));
+        TT_HIP(hipMemcpyAsync(c.tFAm.p, FA.data(), FA.size() * sizeof(uint2), hipMemcpyHostToDevice, c.stream));
+        TT_HIP(hipMemcpyAsync(c.tFBm.p, FB.data(), FB.size() * sizeof(uint2), hipMemcpyHostToDevice, c.stream));
+    }
+    TT_HIP(hipStreamSynchronize(c.stream));   // the host vectors are released on return
     return TT_OK;
 }
 
-template <typename R, bool RES>
+template <typename R, bool RES, int MF>
 tt_status launch(tt_ctx& c, PArgs<R>& a, size_t lds, float* ms) {
     TT_HIP(hipMemsetAsync(c.bar.p, 0, c.bar.n * sizeof(unsigned), c.stream));
     void* args[] = {&a};
     TT_HIP(hipEventRecord(c.ev0, c.stream));
-    TT_HIP(hipLaunchCooperativeKernel((const void*)k_cg_persistent<R, RES>, dim3(a.nwg), dim3(PT), args,
+    TT_HIP(hipLaunchCooperativeKernel((const void*)k_cg_persistent<R, RES, MF>, dim3(a.nwg), dim3(PT), args,
                                       (unsigned)lds, c.stream));
     TT_HIP(hipEventRecord(c.ev1, c.stream));
     TT_HIP(hipEventSynchronize(c.ev1));
@@ -742,14 +995,18 @@ tt_status launch(tt_ctx& c, PArgs<R>& a, size_t lds, float* ms) {
     return TT_OK;
 }
 
-template <typename R, bool RES>
+// the recurrences stopped on a non-positive or non-finite step with finite
+// residual norms (an inexact operator), not on non-finite data
+inline bool finite_breakdown(const CgScalars& h) { return std::isfinite(h.rr[h.iter & 1]) && std::isfinite(h.rr_true); }
+
+template <typename R, bool RES, int MF>
 tt_status run_persistent(tt_ctx& c, const float* s, double* zeta, const tt_solve_opts& o, tt_solve_info& info,
                          PArgs<R>& a, size_t lds, CgScalars& h) {
     const bool f32 = sizeof(R) == 4;
-    TT_HIP(hipFuncSetAttribute((const void*)k_cg_persistent<R, RES>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    TT_HIP(hipFuncSetAttribute((const void*)k_cg_persistent<R, RES, MF>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     int per_cu = 0;
-    TT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_cg_persistent<R, RES>, PT, lds));
+    TT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_cg_persistent<R, RES, MF>, PT, lds));
     if (per_cu < 1) {
         tt_set_error("persistent solver does not fit on a compute unit");
         return TT_INVALID_ARG;
@@ -765,14 +1022,39 @@ tt_status run_persistent(tt_ctx& c, const float* s, double* zeta, const tt_solve
         a.aprev = aprev;
         a.gmax = gmax;
         float ms = 0.f;
-        TT_CHECK((launch<R, RES>(c, a, lds, &ms)));
+        TT_CHECK((launch<R, RES, MF>(c, a, lds, &ms)));
         info.kernel_ms += ms;
         info.kernel_launches++;
         TT_HIP(hipMemcpy(&h, cg_scalars(c), sizeof(h), hipMemcpyDeviceToHost));
         it = h.iter;
         if (h.state == ST_BREAK) {
-            code = TT_BREAKDOWN;
-            break;
+            // With FP16 / BF16 column transforms the inner operator is inexact
+            // and not exactly symmetric, which can end the recurrences early;
+            // the last iterate is kept (the failed step is not applied), so the
+            // solve continues from the FP64 true residual while that keeps
+            // falling (by 10% or more per restart), and otherwise ends with
+            // TT_NOT_CONVERGED.
+            if (MF < 2 || !finite_breakdown(h)) {
+                code = TT_BREAKDOWN;
+                break;
+            }
+            const double prev = gmax;
+            TT_CHECK(cg_true_residual(c, s, f32, &h));
+            have_true = true;
+            info.refinements++;
+            if (h.rr_true <= h.tol2) break;
+            if (!(h.rr_true < 0.81 * prev) || it >= o.max_iter) {
+                // no further progress: the last iterate is returned
+                code = std::isfinite(h.rr_true) ? TT_NOT_CONVERGED : TT_BREAKDOWN;
+                break;
+            }
+            TT_CHECK(cg_copy_r64_to_r32(c));
+            TT_CHECK(cg_fill_zero(c, (float*)a.p, nullptr));
+            TT_CHECK(cg_fill_zero(c, (float*)a.s, nullptr));
+            gmax = h.rr_true;
+            first = 1;
+            gprev = aprev = 0.0;
+            continue;
         }
         if (h.state == ST_CAP) {
             code = TT_NOT_CONVERGED;
@@ -798,9 +1080,17 @@ tt_status run_persistent(tt_ctx& c, const float* s, double* zeta, const tt_solve
     return cg_finish(c, s, zeta, f32, have_true, info, code);
 }
 
+template <typename R, int MF>
+tt_status run_mode(tt_ctx& c, const float* s, double* zeta, const tt_solve_opts& o, tt_solve_info& info,
+                   PArgs<R>& a, size_t lds, bool res, CgScalars& h) {
+    if (res) return run_persistent<R, true, MF>(c, s, zeta, o, info, a, lds, h);
+    return run_persistent<R, false, MF>(c, s, zeta, o, info, a, lds, h);
+}
+
+// MF: column-transform mode (0 VALU, 1 FP32, 2 FP16, 3 BF16 matrix cores)
 template <typename R>
 tt_status solve_persistent_t(tt_ctx& c, const float* s, const double* x0, double* zeta, const tt_solve_opts& o,
-                             tt_solve_info& info, R* x, R* r, R* p, R* sv, const R* M, const R* noise) {
+                             tt_solve_info& info, R* x, R* r, R* p, R* sv, const R* M, const R* noise, int MF) {
     const bool f32 = sizeof(R) == 4;
     info = tt_solve_info{};
     TT_CHECK(cg_setup(c, s, x0, o, f32));
@@ -817,21 +1107,23 @@ tt_status solve_persistent_t(tt_ctx& c, const float* s, const double* x0, double
     int S = std::max(1, nwg / std::max(c.Lh, 1));
     S = std::min(S, std::max(1, c.L / 8));
     const int Lrm = (c.L + S - 1) / S;
-    const size_t lim = 160 * 1024 - PT * sizeof(double) - 256;   // minus the static LDS
+    const size_t lim = 160 * 1024 - 512;   // minus the static LDS (reduction scratch and flags)
     // rows per block: all of a block's rows at once when they fit the threads
     const int rows_per_block = (c.C * c.n + nwg - 1) / nwg;
     const bool vreg = rows_per_block * c.n <= PT;
     const int rbv = vreg ? rows_per_block : std::max(1, std::min(4, PT / std::max(c.n, 1)));
-    const bool res = lds_bytes<R>(c, Lrm, rbv, true) <= lim;
-    const size_t lds = lds_bytes<R>(c, Lrm, rbv, res);
+    const bool res = lds_bytes<R>(c, Lrm, rbv, true, MF) <= lim;
+    const size_t lds = lds_bytes<R>(c, Lrm, rbv, res, MF);
     if (lds > lim) {
         tt_set_error("persistent solver: system too large for LDS");
         return TT_INVALID_ARG;
     }
-    if (c.tile_S != S || c.tile_elem != (int)sizeof(R)) {
-        TT_CHECK(build_tiles<R>(c, S, Lrm));
+    if (c.tile_S != S || c.tile_elem != (int)sizeof(R) || c.tile_mf != MF) {
+        c.tile_S = 0;   // rebuilt below; left invalid if the build fails
+        TT_CHECK(build_tiles<R>(c, S, Lrm, MF));
         c.tile_S = S;
         c.tile_elem = (int)sizeof(R);
+        c.tile_mf = MF;
     }
     if (c.pU.n < (size_t)c.Lh * S * c.C * c.n) TT_CHECK(c.pU.alloc((size_t)c.Lh * S * c.C * c.n));
     if (c.ppart.n < 8 * (size_t)nwg) TT_CHECK(c.ppart.alloc(8 * (size_t)nwg));
@@ -854,6 +1146,13 @@ tt_status solve_persistent_t(tt_ctx& c, const float* s, const double* x0, double
     a.Fa = reinterpret_cast<const cplx<R>*>(c.tFa.p);
     a.Fb = reinterpret_cast<const cplx<R>*>(c.tFb.p);
     a.Gr = reinterpret_cast<const cplx<R>*>(c.tGr.p);
+    const FragShape fs = frag_shape(MF, c.n, Lrm);
+    a.FAm = reinterpret_cast<const uint2*>(c.tFAm.p);
+    a.FBm = reinterpret_cast<const uint2*>(c.tFBm.p);
+    a.MTf = fs.MTf;
+    a.TKf = fs.TKf;
+    a.MTi = fs.MTi;
+    a.TKi = fs.TKi;
     a.noise = noise;
     a.x = x;
     a.r = r;
@@ -863,17 +1162,19 @@ tt_status solve_persistent_t(tt_ctx& c, const float* s, const double* x0, double
     a.U = reinterpret_cast<cplx<R>*>(c.pU.p);
     a.part = c.ppart.p;
     a.vreg = vreg ? 1 : 0;
-    // The matrix-core column transforms (col_fwd_mfma / col_inv_mfma) are
-    // correct but measured slower than the VALU loops at this size (the
-    // operand staging is latency bound: 5.8 + 7.5 us against 4.1 + 3.4 us per
-    // column block at 74x74), so the VALU path is the default.
-    a.mfma = 0;
     a.rbv = rbv;
     a.S_ = cg_scalars(c);
     a.P = p_scalars(c);
     a.bar = c.bar.p;
-    if (res) return run_persistent<R, true>(c, s, zeta, o, info, a, lds, h);
-    return run_persistent<R, false>(c, s, zeta, o, info, a, lds, h);
+    if constexpr (sizeof(R) == 4) {
+        switch (MF) {
+            case 1: return run_mode<R, 1>(c, s, zeta, o, info, a, lds, res, h);
+            case 2: return run_mode<R, 2>(c, s, zeta, o, info, a, lds, res, h);
+            case 3: return run_mode<R, 3>(c, s, zeta, o, info, a, lds, res, h);
+            default: break;
+        }
+    }
+    return run_mode<R, 0>(c, s, zeta, o, info, a, lds, res, h);
 }
 
 }  // namespace
@@ -884,9 +1185,12 @@ tt_status solve_persistent(tt_ctx& c, const float* s, const double* x0, double* 
         TT_HIP(hipEventCreate(&c.ev0));
         TT_HIP(hipEventCreate(&c.ev1));
     }
-    if (o.precision == TT_PREC_F32)
-        return solve_persistent_t<float>(c, s, x0, zeta, o, info, c.x32.p, c.r32.p, c.p32.p, c.q32.p, c.M32.p,
-                                         c.noise32.p);
-    return solve_persistent_t<double>(c, s, x0, zeta, o, info, c.x64.p, c.r64.p, c.p64.p, c.q64.p, c.M64.p,
-                                      c.noise64.p);
+    if (o.precision == TT_PREC_F64)
+        return solve_persistent_t<double>(c, s, x0, zeta, o, info, c.x64.p, c.r64.p, c.p64.p, c.q64.p, c.M64.p,
+                                          c.noise64.p, 0);
+    // FP32 vectors and products; the column transforms on the matrix cores
+    // with FP32, FP16 or BF16 operands
+    const int MF = o.precision == TT_PREC_F16 ? 2 : o.precision == TT_PREC_BF16 ? 3 : 1;
+    return solve_persistent_t<float>(c, s, x0, zeta, o, info, c.x32.p, c.r32.p, c.p32.p, c.q32.p, c.M32.p,
+                                     c.noise32.p, MF);
 }

@@ -149,7 +149,9 @@ struct tt_ctx {
     DevBuf<double> ppart;               // persistent solver partial sums
     DevBuf<c64> pU;                     // persistent solver column outputs [f2][split][C][n]
     DevBuf<c64> tFa, tFb, tGr;          // persistent solver transform tiles
+    DevBuf<c32> tFAm, tFBm;             // persistent solver matrix-core operand fragments (8 bytes each)
     int tile_S = 0, tile_elem = 0;      // split and element size the tiles were built for
+    int tile_mf = -1;                   // column-transform mode the fragments were built for
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     DevBuf<double> part;                // per-block partial sums
     DevBuf<double> scal;                // solver scalars (see cg.hip)

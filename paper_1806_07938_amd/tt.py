@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtt.so")
 
 TT_OK, TT_INVALID_ARG, TT_HIP_ERROR, TT_OUT_OF_MEMORY, TT_NOT_CONVERGED, TT_BREAKDOWN, TT_NOT_READY = range(7)
-PREC_F32, PREC_F64 = 0, 1
+PREC_F32, PREC_F64, PREC_F16, PREC_BF16 = 0, 1, 2, 3
 SOLVER_PERSISTENT, SOLVER_KERNELS = 0, 1
 MODEL_HUDGIN, MODEL_FRIED = 0, 1
 

@@ -100,6 +100,37 @@ def test_c2_solve(c2, c2_oracle, solver):
     assert abs(res - info.rel_residual) <= 1e-8
 
 
+@pytest.mark.parametrize("precision", [2, 3])
+def test_c2_low_precision_status_is_honest(c2, c2_oracle, precision):
+    # FP16 / BF16 column transforms: TT_OK only with the oracle's FP64 residual
+    # at or under tol; otherwise TT_NOT_CONVERGED reporting the returned
+    # iterate's residual
+    import torch
+    from paper_1806_07938_amd.tt import TT_NOT_CONVERGED
+    wl, ctx, k = c2
+    s = W.turbulent_slopes(wl, seed=7)[0].astype(np.float32)
+    zeta, phi, info = ctx.solve(torch.tensor(s, device=torch_dev()), tol=1e-6, precision=precision,
+                                allow=(0, TT_NOT_CONVERGED))
+    z = zeta.cpu().numpy()
+    assert np.all(np.isfinite(z))
+    s64 = s.astype(np.float64)
+    res = np.linalg.norm(s64 - c2_oracle(z)) / np.linalg.norm(s64)
+    say("c2 precision", precision, "status", info.status, "iterations", info.iterations, "lib relres",
+        info.rel_residual, "oracle relres", res)
+    # norm-wise FP64 rounding bound of s - A z (||A|| by power iteration)
+    v = np.random.default_rng(0).standard_normal(z.size)
+    for _ in range(30):
+        v = c2_oracle(v)
+        nrm = np.linalg.norm(v)
+        v /= nrm
+    scale = (1.01 * nrm * np.linalg.norm(z) + np.linalg.norm(s64)) / np.linalg.norm(s64)
+    assert abs(res - info.rel_residual) <= 1e-11 * scale
+    if info.status == 0:
+        assert res <= 1.01e-6
+    else:
+        assert info.status == TT_NOT_CONVERGED
+
+
 def test_c2_projection(c2):
     import torch
     from oracle.projection import phi_paper_fft, xi_prime_tables
