@@ -79,8 +79,9 @@ struct PArgs {
 // its XCD, the L1 being write-through); thread 0 of every block then
 // increments its group counter.  The last arriver of a group issues one agent
 // release fence (write-back of that L2) and increments the top counter; every
-// block polls the top counter with relaxed loads (2 s wall-clock limit, abort
-// word) and finishes with an agent acquire fence.  One L2 write-back per XCD
+// block polls the top counter with relaxed loads (2 s wall-clock limit and the
+// abort word, both checked every 64th poll) and finishes with an agent acquire
+// fence.  One L2 write-back per XCD
 // instead of one per block.  Counters grow monotonically within a launch
 // (reset before it).  A stale read would show up as a failed FP64 true-residual
 // check after the launch, never as a silently accepted result.
@@ -104,15 +105,19 @@ __device__ bool grid_sync(unsigned* bar, unsigned nwg, unsigned& epoch, int* s_f
         }
         int ok = 1;
         const unsigned long long t0 = wall_clock64();
+        unsigned spins = 0;
+        // one load per poll; the abort word and the time limit every 64th poll
         while (__hip_atomic_load(top, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch * ng) {
-            if (__hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                ok = 0;
-                break;
-            }
-            if (wall_clock64() - t0 > SPIN_TICKS) {
-                __hip_atomic_store(abort_w, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = 0;
-                break;
+            if ((++spins & 63u) == 0u) {
+                if (__hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                    ok = 0;
+                    break;
+                }
+                if (wall_clock64() - t0 > SPIN_TICKS) {
+                    __hip_atomic_store(abort_w, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
             }
             __builtin_amdgcn_s_sleep(1);
         }
