@@ -19,8 +19,11 @@ the paper it follows.  Modules:
   toeplitz    the 2RBT matrix-vector product by circulant embedding, step by
               step (§2.E: shuffle, FFT, element-wise product, inverse FFT,
               reshuffle; fused over blocks as in the Sigma_ss zeta equation)
-  solve       Cholesky solve of (Sigma_ss + Sigma_eta) zeta = s and plain CG
-              (§2.C, §2.G)
+  solve       Cholesky solve of (Sigma_ss + Sigma_eta) zeta = s, plain CG and
+              preconditioned CG (§2.C, §2.G)
+  precond     block-circulant preconditioner: the positive part of the
+              per-frequency embedded spectra plus sigma^2, inverted (§2.E
+              embedding; preconditioning is left open in §2.G)
   projection  the LGS phase-slope product through per-layer grids with
               bilinear interpolation (§2.D "Phase-Slope Covariance Matrix",
               §2.E LGS equation), plus the exact dense form for comparison
