@@ -4,16 +4,19 @@ relative residual 1e-6, on one MI355X.
 
 One step = one frame through the whole hot path: CG solve of
 (Sigma_ss + Sigma_eta) zeta = s with the fused 2RBT products (FP32, with
-FP64 residual replacement certifying the tolerance) followed by the LGS
+FP64 residual replacement certifying the tolerance), preconditioned by the
+block-circulant inverse of the embedding (default; --preconditioner none for
+plain CG, which is also reported on the same line), followed by the LGS
 projection phi = W_phi Sigma_phi_s zeta.  Kernel generation and spectra
 (set-up, done once per atmosphere) are timed separately.  Inputs: 20 seeded
 frames of slopes measured through von Karman layers, resident in HBM before
 the timed region.
 
 Prints one JSON line.  The roofline object is for the dominant kernel, the
-persistent CG kernel: algorithmic bytes per iteration (packed FP32 spectra +
-slopes in and out) times iterations per launch, over the launch duration
-measured with HIP events on the library's stream.  The cpu_baseline object
+persistent CG kernel: algorithmic bytes per iteration (packed FP32 slope
+spectra, plus the preconditioner spectra when preconditioned, + slopes in and
+out) times iterations per launch, over the launch duration measured with HIP
+events on the library's stream.  The cpu_baseline object
 times the FP64 oracle (CG with its step-by-step 2RBT product) on one frame.
 """
 import argparse
@@ -42,6 +45,7 @@ def parse():
                     help="timed form (the FP16 / BF16 column-transform forms are reported under variants)")
     ap.add_argument("--solver", choices=["persistent", "kernels"], default="persistent")
     ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--preconditioner", choices=["circulant", "none"], default="circulant")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the FP64 / kernel-solver side numbers")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -50,11 +54,11 @@ def parse():
     return ap.parse_args()
 
 
-def traffic_record():
+def traffic_record(pc):
     """HBM traffic of the persistent kernel measured with rocprofv3 counters
     (profiles/*_traffic.md), valid only while the kernel source is unchanged."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_cg_persistent_f32_c2_L148_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"k_cg_persistent_{'pcg' if pc else 'cg'}_f32_c2_L148_traffic.md")
     src = os.path.join(ROOT, "paper_1806_07938_amd", "csrc", "persistent.hip")
     try:
         rec = {}
@@ -98,8 +102,8 @@ def main():
     import torch
     import workloads as W
     from paper_1806_07938_amd import Context, system_from
-    from paper_1806_07938_amd.tt import (PREC_BF16, PREC_F16, PREC_F32, PREC_F64, SOLVER_KERNELS,
-                                         SOLVER_PERSISTENT, TT_NOT_CONVERGED)
+    from paper_1806_07938_amd.tt import (PRECOND_CIRCULANT, PRECOND_NONE, PREC_BF16, PREC_F16, PREC_F32, PREC_F64,
+                                         SOLVER_KERNELS, SOLVER_PERSISTENT, TT_NOT_CONVERGED)
 
     dev = torch.device("cuda:0")
     if args.copy_calibration:
@@ -125,10 +129,18 @@ def main():
     phi = torch.empty(info["n_vphi"], dtype=torch.float32, device=dev)
     prec = PREC_F32 if args.precision == "f32" else PREC_F64
     solver = SOLVER_PERSISTENT if args.solver == "persistent" else SOLVER_KERNELS
+    pc = PRECOND_CIRCULANT if (args.preconditioner == "circulant" and solver == SOLVER_PERSISTENT) else PRECOND_NONE
 
-    def run(k, prec=prec, solver=solver, allow=(0,)):
+    def run(k, prec=prec, solver=solver, allow=(0,), pc=pc):
         return ctx.solve(S[k % args.frames], zeta=zeta, phi=phi, tol=args.tol, precision=prec, solver=solver,
-                         allow=allow)[2]
+                         allow=allow, preconditioner=pc)[2]
+
+    t0 = time.perf_counter()
+    if pc:   # the preconditioner spectra are built once per system, before the timed solves
+        ctx.solve(S[0], zeta=zeta, phi=phi, tol=args.tol, precision=prec, max_iter=0, preconditioner=pc,
+                  allow=(0, TT_NOT_CONVERGED))
+    torch.cuda.synchronize()
+    pc_setup_ms = (time.perf_counter() - t0) * 1e3
 
     for k in range(args.warmup):
         run(k)
@@ -149,19 +161,22 @@ def main():
 
     spectra = info["spectra_bytes_f32"] if prec == PREC_F32 else info["spectra_bytes_f64"]
     elem = 4 if prec == PREC_F32 else 8
-    bytes_iter = spectra + 2 * wl.n_slopes * elem
+    C = 2 * wl.n_gs
+    pc_spectra = args.pad * (args.pad // 2 + 1) * C * C * elem if pc else 0   # general Hermitian packing
+    bytes_iter = spectra + pc_spectra + 2 * wl.n_slopes * elem
     roofline = None
     if solver == SOLVER_PERSISTENT and kms.sum() > 0:
         avg_launch_ms = kms.sum() / launches.sum()
         bytes_launch = bytes_iter * iters.sum() / launches.sum()
         achieved = bytes_launch / (avg_launch_ms * 1e-3) / 1e9
-        tpi = traffic_record() if (prec == PREC_F32 and args.pad == 148) else None
+        tpi = traffic_record(pc) if (prec == PREC_F32 and args.pad == 148) else None
         traffic = round(tpi * iters.sum() / launches.sum()) if tpi else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
-                    "kernel": ("k_cg_persistent<float, true, 1> (FP32 column transforms on the matrix cores)"
-                               if prec == PREC_F32 else "k_cg_persistent<double, true, 0>"),
+                    "kernel": (f"k_cg_persistent<float, true, 1, {'true' if pc else 'false'}> (FP32 column "
+                               "transforms on the matrix cores)" if prec == PREC_F32 else
+                               f"k_cg_persistent<double, true, 0, {'true' if pc else 'false'}>"),
                     "avg_launch_ms": round(avg_launch_ms, 4), "bytes_per_iteration": int(bytes_iter),
                     "iterations_per_launch": round(float(iters.sum() / launches.sum()), 1)}
 
@@ -172,16 +187,19 @@ def main():
         "dtype": "f32" if prec == PREC_F32 else "f64", "data": "synthetic",
         "config": {"workload": (f"39 m pupil, 28% obstruction, 74x74 SH (3972 valid/WFS), 6 LGS at 90 km on a 60 "
                                 f"arcsec ring, 35 layers 30 m-26.5 km, r0 0.157 m, L0 25 m, sigma^2 0.1 rad^2, "
-                                f"L={args.pad}, on-axis target; plain CG to rel. residual {args.tol:g}"),
+                                f"L={args.pad}, on-axis target; "
+                                + ("CG preconditioned by the block-circulant inverse" if pc else "plain CG")
+                                + f" to rel. residual {args.tol:g}"),
                    "n": wl.n, "n_gs": wl.n_gs, "n_layer": wl.n_layer, "n_slopes": wl.n_slopes, "pad_L": args.pad,
-                   "solver": args.solver, "precision": args.precision + ("+f64 residual replacement"
-                                                                          if prec == PREC_F32 else ""),
+                   "solver": args.solver, "preconditioner": "circulant" if pc else "none",
+                   "precision": args.precision + ("+f64 residual replacement" if prec == PREC_F32 else ""),
                    "frames": args.frames},
         "valid": bool(ok),
         "iterations_mean": round(float(iters.mean()), 1),
         "refinements_mean": round(float(np.mean([i.refinements for i in infos])), 2),
         "rel_residual_max": relres,
         "setup_ms": round(setup_ms, 1),
+        "preconditioner_setup_ms": round(pc_setup_ms, 1) if pc else None,
         "roofline": roofline,
     }
     if not args.no_variants:
@@ -190,16 +208,20 @@ def main():
         # phase, and the FP16 / BF16 column-transform forms (which may stop
         # short of the tolerance: status and the FP64 residual reached are
         # reported per frame)
-        for name, p, sv in (("f64_persistent", PREC_F64, SOLVER_PERSISTENT), ("f32_kernels", PREC_F32, SOLVER_KERNELS),
-                            ("f16_persistent", PREC_F16, SOLVER_PERSISTENT),
-                            ("bf16_persistent", PREC_BF16, SOLVER_PERSISTENT)):
-            if p == prec and sv == solver:
+        for name, p, sv, vpc in (("f32_persistent_plain_cg", PREC_F32, SOLVER_PERSISTENT, PRECOND_NONE),
+                                 ("f32_persistent_pcg", PREC_F32, SOLVER_PERSISTENT, PRECOND_CIRCULANT),
+                                 ("f64_persistent_plain_cg", PREC_F64, SOLVER_PERSISTENT, PRECOND_NONE),
+                                 ("f64_persistent_pcg", PREC_F64, SOLVER_PERSISTENT, PRECOND_CIRCULANT),
+                                 ("f32_kernels_plain_cg", PREC_F32, SOLVER_KERNELS, PRECOND_NONE),
+                                 ("f16_persistent_plain_cg", PREC_F16, SOLVER_PERSISTENT, PRECOND_NONE),
+                                 ("bf16_persistent_plain_cg", PREC_BF16, SOLVER_PERSISTENT, PRECOND_NONE)):
+            if p == prec and sv == solver and vpc == pc:
                 continue
             allow = (0, TT_NOT_CONVERGED)
-            run(0, p, sv, allow)
+            run(0, p, sv, allow, vpc)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            ii = [run(k, p, sv, allow) for k in range(3)]
+            ii = [run(k, p, sv, allow, vpc) for k in range(3)]
             torch.cuda.synchronize()
             side[name] = {"ms_per_solve": round((time.perf_counter() - t0) * 1e3 / 3, 3),
                           "iterations_mean": round(float(np.mean([i.iterations for i in ii])), 1),

@@ -84,6 +84,21 @@ typedef enum {
 } tt_solver_kind;
 
 typedef enum {
+    TT_PRECOND_NONE = 0,      /* plain CG (§2.G) */
+    TT_PRECOND_CIRCULANT = 1  /* CG preconditioned by the block-circulant inverse: the
+                                 restriction to the valid subapertures of
+                                 F^-1 (M_+(f) + sigma^2 I)^-1 F, with M(f) the per-frequency
+                                 matrix of the embedded slope spectra of the product (§2.E),
+                                 M_+ its positive part and sigma^2 the mean noise variance.
+                                 Symmetric positive definite; built once per system (FP64,
+                                 on the host) at the first solve that asks for it.  The
+                                 paper leaves preconditioning open (§2.G).
+                                 TT_SOLVER_PERSISTENT with TT_PREC_F32 or TT_PREC_F64 only,
+                                 and a block's grid rows must fit its threads:
+                                 n * ceil(2 n_gs n / compute units) <= 512. */
+} tt_preconditioner;
+
+typedef enum {
     TT_MODEL_HUDGIN = 0,     /* App. A.2 Hudgin-like two-point slopes */
     TT_MODEL_FRIED = 1       /* App. A.3 Fried four-corner slopes */
 } tt_gradient_model;
@@ -128,6 +143,7 @@ typedef struct {
     double refine_drop;           /* TT_PREC_F32: FP64 residual replacement when the
                                      recursive residual fell by this factor since the
                                      last one (0 -> 1e-3) */
+    int preconditioner;           /* tt_preconditioner (0: none) */
 } tt_solve_opts;
 
 typedef struct {

@@ -117,6 +117,7 @@ tt_status set_system_impl(tt_ctx* c, const tt_kernels* k, const double* noise_va
     c->ready = false;
     c->proj.on = false;
     c->tile_S = 0;
+    c->pc_ready = false;
     c->n = k->n;
     c->G = k->n_gs;
     c->C = 2 * k->n_gs;
@@ -184,6 +185,7 @@ tt_status solve_impl(tt_ctx* c, const float* s, const double* x0, double* zeta, 
     o.precision = TT_PREC_F32;
     o.solver = TT_SOLVER_PERSISTENT;
     o.refine_drop = 1e-3;
+    o.preconditioner = TT_PRECOND_NONE;
     if (opts) o = *opts;
     TT_REQUIRE(std::isfinite(o.tol) && o.tol >= 0, "tol must be >= 0");
     TT_REQUIRE(o.max_iter >= 0, "max_iter must be >= 0");
@@ -194,6 +196,11 @@ tt_status solve_impl(tt_ctx* c, const float* s, const double* x0, double* zeta, 
                "TT_PREC_F16 / TT_PREC_BF16 need TT_SOLVER_PERSISTENT");
     TT_REQUIRE(o.solver == TT_SOLVER_PERSISTENT || o.solver == TT_SOLVER_KERNELS, "unknown solver");
     TT_REQUIRE(std::isfinite(o.refine_drop) && o.refine_drop >= 0 && o.refine_drop < 1, "refine_drop in [0, 1)");
+    TT_REQUIRE(o.preconditioner == TT_PRECOND_NONE || o.preconditioner == TT_PRECOND_CIRCULANT,
+               "unknown preconditioner");
+    TT_REQUIRE(o.preconditioner == TT_PRECOND_NONE ||
+                   (o.solver == TT_SOLVER_PERSISTENT && (o.precision == TT_PREC_F32 || o.precision == TT_PREC_F64)),
+               "TT_PRECOND_CIRCULANT needs TT_SOLVER_PERSISTENT with TT_PREC_F32 or TT_PREC_F64");
     TT_CHECK(use_device(c->device));
     tt_solve_info inf{};
     if (o.solver == TT_SOLVER_PERSISTENT)

@@ -55,6 +55,7 @@ struct PArgs {
     double gprev, aprev, gmax;
     const int* vmap;
     const R* M;              // packed spectra [f2][f1][3G^2]
+    const R* Mi;             // preconditioner spectra [f2][f1][C^2] (general Hermitian packing), or null
     const cplx<R>* Fa;       // [S][n][Lrm]  exp(-2 pi i f1 a / L), f1 = f1a(part) + j
     const cplx<R>* Fb;       // [S][Lrm][n]  the same values, a fastest
     const cplx<R>* Gr;       // [Lh][n]      exp(+2 pi i f2 b / L)
@@ -65,9 +66,9 @@ struct PArgs {
     double* part;            // [2][nwg][4]: partial r.r, sigma^2 r.r, r.C r (Parseval)
     int vreg;                // CG vectors held in registers (rows per block * n <= threads)
     int rbv;                 // rows per block at a time
-    const uint2* FAm;        // [S][MTf][TKf][64] forward column-transform operand fragments (MF > 0)
-    const uint2* FBm;        // [S][MTi][TKi][64] inverse column-transform operand fragments (MF > 0)
-    int MTf, TKf, MTi, TKi;  // fragment tiles and K steps of the two column transforms
+    const uint2* FAm;        // [S][TKf][4][Lrm] forward column-transform operand fragments (MF > 0)
+    const uint2* FBm;        // [S][TKi][4][n]   inverse column-transform operand fragments (MF > 0)
+    int MTf, TKf, MTi, TKi;  // output row tiles and K steps of the two column transforms
     CgScalars* S_;
     PScalars* P;
     unsigned* bar;           // barrier words: [0] top counter, [16] abort, [32 + 32 g] group counters
@@ -168,7 +169,7 @@ struct Tiles {
     const uint2* FAm;     // matrix-core column transforms: this block's fragments
     const uint2* FBm;
     const cplx<R>* Gr;
-    const R* Ms;       // resident: [slot][Lrm]; else null
+    R* Ms;             // resident: [slot][Lrm]; else null
     const R* Mg;       // global: M + f2 L P (used when Ms is null)
     cplx<R>* work;
 };
@@ -199,6 +200,7 @@ template <typename R>
 struct Lane {
     long gi;   // slope index, or -1 (no point / invalid subaperture)
     R x, r, p, s, nz;
+    R u;       // preconditioned residual P r (preconditioned solver)
 };
 
 // Us[k][f2] = sum over f1 ranges of the column-phase outputs of row k
@@ -320,6 +322,77 @@ __device__ void row_phase_reg(const PArgs<R>& a, const Tiles<R>& t, Lane<R>& v, 
     }
 }
 
+// Preconditioned solver, row phases (CG vectors in registers).  The
+// iteration is the single-reduction form of preconditioned CG:
+//   u_i = P r_i,  w_i = A u_i,  gamma_i = r_i.u_i,  delta_i = u_i.w_i,
+//   beta_i = gamma_i / gamma_{i-1},  alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1}),
+//   p_i = u_i + beta_i p_{i-1},  s_i = w_i + beta_i s_{i-1},
+//   x_{i+1} = x_i + alpha_i p_i,  r_{i+1} = r_i - alpha_i s_i,
+// with four phases per iteration: row (update, forward transform of r), column
+// with the preconditioner spectra (partial gamma by Parseval), row (u = P r,
+// partial sigma^2 u.u, forward transform of u), column with the slope spectra
+// (partial u.C u by Parseval).
+//
+// Update phase: w = A u from the gathered column outputs (Us), vector updates,
+// forward row transform of the new residual; partial r.r in slot 0.
+template <typename R>
+__device__ void row_pc_update(const PArgs<R>& a, const Tiles<R>& t, Lane<R>& v, int nrk, R alpha, R beta, int par,
+                              double* red) {
+    const int n = a.n, Lh = a.Lh, L = a.L;
+    cplx<R>* Us = t.work;   // filled by gather_u before the call
+    R* xs = reinterpret_cast<R*>(Us + a.rbv * Lh);
+    __syncthreads();
+    double g = 0.0;
+    if ((int)threadIdx.x < nrk * n) {
+        const int k = threadIdx.x / n, b = threadIdx.x % n;
+        R rn = 0;
+        if (v.gi >= 0) {
+            const R inv = R(1) / (R(L) * R(L));
+            const R wv = inv_row(Us + k * Lh, t.Gr, n, b, L, Lh) * inv + v.nz * v.u;
+            v.p = v.u + beta * v.p;
+            v.s = wv + beta * v.s;
+            v.x += alpha * v.p;
+            v.r = v.r - alpha * v.s;
+            rn = v.r;
+            g = (double)rn * (double)rn;
+        }
+        xs[k * n + b] = rn;
+    }
+    __syncthreads();
+    fwd_rows(a, t.Gr, xs, blockIdx.x * a.rbv, 1, nrk);
+    const D3 tot = block_sum3(D3{g, 0.0, 0.0}, red);
+    if (threadIdx.x == 0) a.part[((long)par * a.nwg + blockIdx.x) * 4 + 0] = tot.a;
+}
+
+// Preconditioner phase: u = P r from the column outputs of the preconditioner
+// spectra (no noise term: it is inside P), forward row transform of u; partial
+// sigma^2 u.u in slot 1.
+template <typename R>
+__device__ void row_pc_precond(const PArgs<R>& a, const Tiles<R>& t, Lane<R>& v, int nrk, int par, double* red) {
+    const int n = a.n, Lh = a.Lh, L = a.L;
+    cplx<R>* Us = t.work;
+    R* xs = reinterpret_cast<R*>(Us + a.rbv * Lh);
+    __syncthreads();
+    gather_u(a, Us, blockIdx.x * a.rbv, 1, nrk);
+    __syncthreads();
+    double sg = 0.0;
+    if ((int)threadIdx.x < nrk * n) {
+        const int k = threadIdx.x / n, b = threadIdx.x % n;
+        R un = 0;
+        if (v.gi >= 0) {
+            const R inv = R(1) / (R(L) * R(L));
+            un = inv_row(Us + k * Lh, t.Gr, n, b, L, Lh) * inv;
+            sg = (double)v.nz * (double)un * (double)un;
+        }
+        v.u = un;
+        xs[k * n + b] = un;
+    }
+    __syncthreads();
+    fwd_rows(a, t.Gr, xs, blockIdx.x * a.rbv, 1, nrk);
+    const D3 tot = block_sum3(D3{sg, 0.0, 0.0}, red);
+    if (threadIdx.x == 0) a.part[((long)par * a.nwg + blockIdx.x) * 4 + 1] = tot.a;
+}
+
 // Row phase with the CG vectors in global memory (systems with more rows per block).
 template <typename R>
 __device__ void row_phase_mem(const PArgs<R>& a, const Tiles<R>& t, bool update, R alpha, R beta, int par,
@@ -391,10 +464,10 @@ typedef short i16x4 __attribute__((ext_vector_type(4)));
 //   MF = 2, 3, FP16 / BF16 operands, v_mfma_f32_16x16x16{f16,bf16_1k}: lane
 //       supplies the 4 K values (8t + 2kq, e), (8t + 2kq + 1, e), e = 0, 1.
 // The result element v of lane l is row 4 kq + v, column lc of the tile.
-// The constant operand (A, A') is precomputed in exactly this lane order
-// (uint2 per lane per step: one complex FP32, or four 16-bit values), zero
-// outside the transform, so that a wave reads 64 consecutive 8-byte words per
-// step.  FP16 / BF16 data operands are multiplied by sc, a power of two that
+// The constant operand (A, A') is precomputed per K step in this lane order
+// (uint2 per lane per step: one complex FP32, or four 16-bit values) as
+// [t][kq][row], zero outside the transform, rows past the last output row not
+// stored; a wave reads 4 runs of 16 consecutive 8-byte words per step.  FP16 / BF16 data operands are multiplied by sc, a power of two that
 // brings the block's largest magnitude to [2^13, 2^14); results are multiplied
 // by 1/sc, both exact.
 __device__ inline unsigned short bf16_bits(float x) {
@@ -461,8 +534,8 @@ __device__ inline void col_load(const cplx<float>* src, int t, int kq, int kmax,
 // (all loads of a group issued before its products, on two accumulators) and
 // a remainder of single steps.  INV selects the inverse transform.
 template <int MF, bool INV>
-__device__ void col_mf(const uint2* FR, const cplx<float>* src, int srcstride, int kmax, float* dst, int dststride,
-                       int rmax, int C, int MT, int TK, float sc) {
+__device__ void col_mf(const uint2* FR, int rowsA, const cplx<float>* src, int srcstride, int kmax, float* dst,
+                       int dststride, int rmax, int C, int MT, int TK, float sc) {
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, kq = l >> 4, lc = l & 15;
     const int NT = (2 * C + 15) / 16;
     const float isc = 1.0f / sc;
@@ -471,7 +544,11 @@ __device__ void col_mf(const uint2* FR, const cplx<float>* src, int srcstride, i
         const int c = nt * 8 + (lc >> 1), f = lc & 1;
         const bool cv = c < C;
         const cplx<float>* sp = src + (cv ? c : 0) * srcstride;
-        const uint2* fr = FR + (long)mt * TK * 64 + l;
+        // constant operand: [t][kq][row] words, rows >= rowsA are zero (not stored)
+        const int arow = mt * 16 + lc;
+        const bool aok = arow < rowsA;
+        const uint2* fr = FR + kq * rowsA + (aok ? arow : 0);
+        const int ts = 4 * rowsA;
         f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
         int t = 0;
         for (; t + 4 <= TK; t += 4) {
@@ -479,7 +556,8 @@ __device__ void col_mf(const uint2* FR, const cplx<float>* src, int srcstride, i
             cplx<float> w0[4], w1[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                av[u] = fr[(t + u) * 64];
+                av[u] = fr[(t + u) * ts];
+                if (!aok) av[u] = uint2{0u, 0u};
                 col_load<MF>(sp, t + u, kq, kmax, cv, w0[u], w1[u]);
             }
 #pragma unroll
@@ -491,7 +569,9 @@ __device__ void col_mf(const uint2* FR, const cplx<float>* src, int srcstride, i
         for (; t < TK; ++t) {
             cplx<float> w0, w1;
             col_load<MF>(sp, t, kq, kmax, cv, w0, w1);
-            acc0 = col_step<MF, INV>(fr[t * 64], w0, w1, f, sc, acc0);
+            uint2 av = fr[t * ts];
+            if (!aok) av = uint2{0u, 0u};
+            acc0 = col_step<MF, INV>(av, w0, w1, f, sc, acc0);
         }
         if (cv)
             for (int v = 0; v < 4; ++v) {
@@ -506,14 +586,14 @@ __device__ void col_mf(const uint2* FR, const cplx<float>* src, int srcstride, i
 template <int MF>
 __device__ inline void col_fwd_mf(const uint2* FA, const cplx<float>* Tc, cplx<float>* Xh, int n, int C, int Lr,
                                   int Lrm, int MT, int TK, float sc) {
-    col_mf<MF, false>(FA, Tc, n, n, reinterpret_cast<float*>(Xh), Lrm, Lr, C, MT, TK, sc);
+    col_mf<MF, false>(FA, Lrm, Tc, n, n, reinterpret_cast<float*>(Xh), Lrm, Lr, C, MT, TK, sc);
 }
 
 // inverse (partial over this f1 range): Uo[p][a] = sum_j Yh[p][j] conj F[f1a+j][a], a < n
 template <int MF>
 __device__ inline void col_inv_mf(const uint2* FB, const cplx<float>* Yh, cplx<float>* Uo, int n, int C, int Lr,
                                   int Lrm, int MT, int TK, float sc) {
-    col_mf<MF, true>(FB, Yh, Lrm, Lr, reinterpret_cast<float*>(Uo), n, n, C, MT, TK, sc);
+    col_mf<MF, true>(FB, n, Yh, Lrm, Lr, reinterpret_cast<float*>(Uo), n, n, C, MT, TK, sc);
 }
 
 // largest |value| over the block, as float bits, accumulated into *slot
@@ -526,10 +606,29 @@ __device__ inline void block_max_bits(float m, int* slot) {
     if ((threadIdx.x & 63) == 0) atomicMax(slot, b);
 }
 
+// General Hermitian per-frequency matrix (preconditioner spectra, C^2 reals
+// per frequency: slot a = Re H[a][a]; for a < b, slots C + 2k, C + 2k + 1 =
+// Re, Im H[a][b] with k = a C - a(a+1)/2 + b - a - 1) at local frequency j.
+template <typename R>
+__device__ inline cplx<R> hval(const R* Hs, const R* Hg, int a, int b, int j, int C, int Lrm) {
+    const int C2 = C * C;
+    auto val = [&](int slot) { return Hs ? Hs[slot * Lrm + j] : Hg[(long)j * C2 + slot]; };
+    if (a == b) return cplx<R>{val(a), R(0)};
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    const int k = lo * C - lo * (lo + 1) / 2 + (hi - lo - 1);
+    const R im = val(C + 2 * k + 1);
+    return cplx<R>{val(C + 2 * k), a < b ? im : -im};
+}
+
 // MF: column transforms on the VALU (0) or on the matrix cores with FP32 (1),
-// FP16 (2) or BF16 (3) operands and FP32 accumulation.
-template <typename R, int MF>
-__device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, int par, double* red, int* s_mx) {
+// FP16 (2) or BF16 (3) operands and FP32 accumulation.  GEN: the products use
+// the general Hermitian spectra gsrc (preconditioner) instead of the packed
+// slope spectra.  gsrc: global spectra of this phase, [f2][f1][reals]; when
+// stage is set they are first copied to the block's LDS spectra region (in the
+// same loop as the T loads); slot: partial-sum slot of the Parseval term.
+template <typename R, int MF, bool GEN>
+__device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, int par, double* red, int* s_mx, const R* gsrc,
+                          bool stage, int slot) {
     const int n = a.n, L = a.L, C = a.C, G = a.G, S = a.S, Lrm = a.Lrm;
     double accd = 0.0;
     if (blockIdx.x < a.Lh * S) {
@@ -541,6 +640,8 @@ __device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, int par, double*
         cplx<R>* Yh = Xh + C * Lrm;    // [C][Lrm]
         if (MF >= 2 && threadIdx.x == 0) s_mx[0] = s_mx[1] = 0;
         __syncthreads();
+        const int Pn = GEN ? C * C : 3 * G * G;
+        const R* gcol = gsrc + ((long)f2 * L + f1a) * Pn;   // this block's spectra, [j][reals]
         {
             R m = 0;
             for (int i = threadIdx.x; i < C * n; i += PT) {
@@ -548,6 +649,8 @@ __device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, int par, double*
                 Tc[i] = q;
                 if constexpr (MF >= 2) m = fmaxf(m, fmaxf(fabsf(q.x), fabsf(q.y)));
             }
+            if (stage)
+                for (int i = threadIdx.x; i < Pn * Lr; i += PT) t.Ms[(i % Pn) * Lrm + i / Pn] = gcol[i];
             if constexpr (MF >= 2) block_max_bits(m, s_mx);
         }
         __syncthreads();
@@ -592,6 +695,18 @@ __device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, int par, double*
         for (int i = threadIdx.x; i < G * Lr; i += PT) {
             const int g = i / Lr, j = i % Lr;
             R y0r = 0, y0i = 0, y1r = 0, y1i = 0;
+            if constexpr (GEN) {
+                const R* Hs = t.Ms;
+                const R* Hg = gcol;
+                for (int b = 0; b < C; ++b) {
+                    const cplx<R> xb = Xh[b * Lrm + j];
+                    const cplx<R> h0 = hval(Hs, Hg, 2 * g, b, j, C, Lrm), h1 = hval(Hs, Hg, 2 * g + 1, b, j, C, Lrm);
+                    y0r += h0.x * xb.x - h0.y * xb.y;
+                    y0i += h0.x * xb.y + h0.y * xb.x;
+                    y1r += h1.x * xb.x - h1.y * xb.y;
+                    y1i += h1.x * xb.y + h1.y * xb.x;
+                }
+            } else
             for (int h = 0; h < G; ++h) {
                 cplx<R> m3[3];
                 mblock(t, g, h, j, G, Lrm, f1a, m3);
@@ -646,10 +761,11 @@ __device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, int par, double*
         }
     }
     const D3 tot = block_sum3(D3{accd, 0.0, 0.0}, red);
-    if (threadIdx.x == 0) a.part[((long)par * a.nwg + blockIdx.x) * 4 + 2] = tot.a / ((double)a.L * (double)a.L);
+    if (threadIdx.x == 0) a.part[((long)par * a.nwg + blockIdx.x) * 4 + slot] = tot.a / ((double)a.L * (double)a.L);
 }
 
-template <typename R, bool RES, int MF>
+// PC: preconditioned CG (four phases per iteration, see row_pc_update).
+template <typename R, bool RES, int MF, bool PC>
 __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
     extern __shared__ __align__(16) char smem_raw[];
     __shared__ double red[3 * PT / 64];
@@ -659,7 +775,7 @@ __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
     const bool colunit = blockIdx.x < Lh * S;
     const int f2 = colunit ? blockIdx.x / S : 0, part = colunit ? blockIdx.x % S : 0;
     const int f1a = (int)((long)part * L / S), f1b = (int)((long)(part + 1) * L / S);
-    const long fragA = (long)a.MTf * a.TKf * 64, fragB = (long)a.MTi * a.TKi * 64;
+    const long fragA = (long)a.TKf * 4 * a.Lrm, fragB = (long)a.TKi * 4 * a.n;
     Tiles<R> t;
     t.Mg = a.M + (long)f2 * L * P;
     t.Fa = t.Fb = nullptr;
@@ -693,14 +809,17 @@ __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
         R* Ms = reinterpret_cast<R*>(Gr + Lh * n);
         for (int i = threadIdx.x; i < Lh * n; i += PT) Gr[i] = a.Gr[i];
         const int Lr = f1b - f1a;
-        if (colunit)
+        if (colunit && !PC)   // resident for the launch (the preconditioned solver stages per phase)
             for (int i = threadIdx.x; i < P * Lr; i += PT) {
                 const int slot = i / Lr, j = i % Lr;
                 Ms[slot * Lrm + j] = t.Mg[(long)(f1a + j) * P + slot];
             }
         t.Gr = Gr;
         t.Ms = Ms;
-        t.work = reinterpret_cast<cplx<R>*>(Ms + P * Lrm);
+        // spectra region: the slope spectra, or (preconditioned) whichever spectra
+        // the current column phase staged, the larger general packing included
+        const int Preg = PC ? (P > a.C * a.C ? P : a.C * a.C) : P;
+        t.work = reinterpret_cast<cplx<R>*>(Ms + (((long)Preg * Lrm + 3) & ~3L));   // 16-byte aligned
         __syncthreads();
     } else {
         if constexpr (MF > 0) {
@@ -715,7 +834,7 @@ __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
         t.work = reinterpret_cast<cplx<R>*>(smem_raw);
     }
     // lanes of the register-resident CG vectors
-    Lane<R> v{-1, 0, 0, 0, 0, 0};
+    Lane<R> v{-1, 0, 0, 0, 0, 0, 0};
     int nrk = 0;
     if (a.vreg) {
         // a block owns the consecutive rows blockIdx.x * rbv + k, k < nrk
@@ -741,7 +860,15 @@ __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
     if (a.vreg) row_phase_reg<R>(a, t, v, nrk, false, R(0), R(0), it & 1, red);
     else row_phase_mem<R>(a, t, false, R(0), R(0), it & 1, red);
     if (!grid_sync(a.bar, a.nwg, epoch, &s_flag)) return;
-    col_phase<R, MF>(a, t, it & 1, red, s_mx);
+    if constexpr (PC) {
+        col_phase<R, MF, true>(a, t, it & 1, red, s_mx, a.Mi, RES, 3);
+        if (!grid_sync(a.bar, a.nwg, epoch, &s_flag)) return;
+        row_pc_precond<R>(a, t, v, nrk, it & 1, red);
+        if (!grid_sync(a.bar, a.nwg, epoch, &s_flag)) return;
+        col_phase<R, MF, false>(a, t, it & 1, red, s_mx, a.M, RES, 2);
+    } else {
+        col_phase<R, MF, false>(a, t, it & 1, red, s_mx, a.M, false, 2);
+    }
     if (!grid_sync(a.bar, a.nwg, epoch, &s_flag)) return;
     double gprev = a.gprev, aprev = a.aprev;
     bool first = a.first != 0;
@@ -754,33 +881,35 @@ __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
         if (a.nwg <= PT) {
             if ((int)threadIdx.x < a.nwg) {
                 const double* q = a.part + ((long)par * a.nwg + threadIdx.x) * 4;
-                pv = D3{q[0], q[1], q[2]};
+                pv = PC ? D3{q[0], q[1] + q[2], q[3]} : D3{q[0], q[1], q[2]};
             }
         } else {
             for (int i = threadIdx.x; i < a.nwg; i += PT) {
                 const double* q = a.part + ((long)par * a.nwg + i) * 4;
                 pv.a += q[0];
-                pv.b += q[1];
-                pv.c += q[2];
+                pv.b += PC ? q[1] + q[2] : q[1];
+                pv.c += PC ? q[3] : q[2];
             }
         }
         if (a.vreg) gather_u(a, t.work, blockIdx.x * a.rbv, 1, nrk);
         const D3 tot = block_sum3(pv, red);
+        // rr: r.r (stopping rule); CG: gm = r.r, dl = r.A r;  PCG: gm = r.P r, dl = u.A u
         const double g = tot.a;
-        const double dl = tot.c + tot.b;
+        const double gm = PC ? tot.c : tot.a;
+        const double dl = PC ? tot.b : tot.c + tot.b;
         int st = ST_RUN;
         double alpha = 0.0, beta = 0.0;
-        if (!isfinite(g) || !isfinite(dl)) st = ST_BREAK;
+        if (!isfinite(g) || !isfinite(dl) || !isfinite(gm)) st = ST_BREAK;
         else if (g <= tol2) st = ST_CONV;
         else if (drop2 > 0.0 && g < drop2 * a.gmax) st = ST_REFINE;
         else if (it >= a.max_iter) st = ST_CAP;
         if (st == ST_RUN) {
             if (first) {
                 beta = 0.0;
-                alpha = g / dl;
+                alpha = gm / dl;
             } else {
-                beta = g / gprev;
-                alpha = g / (dl - beta * g / aprev);
+                beta = gm / gprev;
+                alpha = gm / (dl - beta * gm / aprev);
             }
             if (!(alpha > 0.0) || !isfinite(alpha)) st = ST_BREAK;
         }
@@ -794,7 +923,7 @@ __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 a.P->gamma_prev = gprev;
                 a.P->alpha_prev = aprev;
-                a.P->gamma = g;
+                a.P->gamma = gm;
                 a.P->delta = dl;
                 a.P->first = first ? 1 : 0;
                 a.S_->state = st;
@@ -803,23 +932,35 @@ __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
             }
             return;
         }
-        if (a.vreg) row_phase_reg<R>(a, t, v, nrk, true, (R)alpha, (R)beta, (it + 1) & 1, red);
-        else row_phase_mem<R>(a, t, true, (R)alpha, (R)beta, (it + 1) & 1, red);
-        gprev = g;
+        if constexpr (PC) {
+            row_pc_update<R>(a, t, v, nrk, (R)alpha, (R)beta, (it + 1) & 1, red);
+        } else {
+            if (a.vreg) row_phase_reg<R>(a, t, v, nrk, true, (R)alpha, (R)beta, (it + 1) & 1, red);
+            else row_phase_mem<R>(a, t, true, (R)alpha, (R)beta, (it + 1) & 1, red);
+        }
+        gprev = gm;
         aprev = alpha;
         first = false;
         ++it;
         if (!grid_sync(a.bar, a.nwg, epoch, &s_flag)) return;
-        col_phase<R, MF>(a, t, it & 1, red, s_mx);
+        if constexpr (PC) {
+            col_phase<R, MF, true>(a, t, it & 1, red, s_mx, a.Mi, RES, 3);
+            if (!grid_sync(a.bar, a.nwg, epoch, &s_flag)) return;
+            row_pc_precond<R>(a, t, v, nrk, it & 1, red);
+            if (!grid_sync(a.bar, a.nwg, epoch, &s_flag)) return;
+            col_phase<R, MF, false>(a, t, it & 1, red, s_mx, a.M, RES, 2);
+        } else {
+            col_phase<R, MF, false>(a, t, it & 1, red, s_mx, a.M, false, 2);
+        }
         if (!grid_sync(a.bar, a.nwg, epoch, &s_flag)) return;
     }
 }
 
 // Fragment tiles and K steps of the matrix-core column transforms (MF > 0).
 struct FragShape {
-    int MTf = 0, TKf = 0, MTi = 0, TKi = 0;
-    long a_words() const { return (long)MTf * TKf * 64; }
-    long b_words() const { return (long)MTi * TKi * 64; }
+    int MTf = 0, TKf = 0, MTi = 0, TKi = 0, rowsA = 0, rowsB = 0;
+    long a_words() const { return (long)TKf * 4 * rowsA; }
+    long b_words() const { return (long)TKi * 4 * rowsB; }
 };
 
 FragShape frag_shape(int MF, int n, int Lrm) {
@@ -830,12 +971,14 @@ FragShape frag_shape(int MF, int n, int Lrm) {
     f.TKf = (n + kstep - 1) / kstep;
     f.MTi = (n + 15) / 16;
     f.TKi = (Lrm + kstep - 1) / kstep;
+    f.rowsA = Lrm;   // forward: output rows j < Lrm
+    f.rowsB = n;     // inverse: output rows a < n
     return f;
 }
 
 // LDS bytes: resident tiles (if RES) + work region (max of column and row needs)
 template <typename R>
-size_t lds_bytes(const tt_ctx& c, int Lrm, int rbv, bool res, int MF) {
+size_t lds_bytes(const tt_ctx& c, int Lrm, int rbv, bool res, int MF, bool pc) {
     const size_t cs = sizeof(cplx<R>);
     const size_t colw = cs * ((size_t)c.C * c.n + 2ull * c.C * Lrm);
     const size_t roww = cs * (size_t)rbv * c.Lh + sizeof(R) * (size_t)rbv * c.n;
@@ -843,7 +986,8 @@ size_t lds_bytes(const tt_ctx& c, int Lrm, int rbv, bool res, int MF) {
     if (res) {
         const FragShape fs = frag_shape(MF, c.n, Lrm);
         b += MF > 0 ? 8 * (size_t)(fs.a_words() + fs.b_words()) : cs * 2ull * c.n * Lrm;
-        b += cs * (size_t)c.Lh * c.n + sizeof(R) * (size_t)packed_reals(c.G) * Lrm;
+        const size_t reals = pc ? std::max((size_t)packed_reals(c.G), (size_t)c.C * c.C) : (size_t)packed_reals(c.G);
+        b += cs * (size_t)c.Lh * c.n + sizeof(R) * ((reals * Lrm + 3) & ~(size_t)3);
     }
     return b;
 }
@@ -905,13 +1049,12 @@ void build_frags(int MF, int n, int L, int S, int Lrm, const std::vector<double>
             }
         };
         for (int pass = 0; pass < 2; ++pass) {
-            const int MT = pass == 0 ? fs.MTf : fs.MTi, TK = pass == 0 ? fs.TKf : fs.TKi;
-            uint2* out = (pass == 0 ? FA.data() : FB.data()) + (size_t)part * MT * TK * 64;
-            for (int mt = 0; mt < MT; ++mt)
-                for (int t = 0; t < TK; ++t)
-                    for (int l = 0; l < 64; ++l) {
-                        const int kq = l >> 4, lc = l & 15, row = mt * 16 + lc;
-                        uint2& w = out[((size_t)mt * TK + t) * 64 + l];
+            const int rows = pass == 0 ? fs.rowsA : fs.rowsB, TK = pass == 0 ? fs.TKf : fs.TKi;
+            uint2* out = (pass == 0 ? FA.data() : FB.data()) + (size_t)part * TK * 4 * rows;
+            for (int t = 0; t < TK; ++t)
+                for (int kq = 0; kq < 4; ++kq)
+                    for (int row = 0; row < rows; ++row) {
+                        uint2& w = out[((size_t)t * 4 + kq) * rows + row];
                         if (MF == 1) {
                             const int k = 4 * t + kq;
                             if (pass == 0) F(row, k, &w.x, &w.y);   // j = row, a = k
@@ -981,12 +1124,12 @@ tt_status build_tiles(tt_ctx& c, int S, int Lrm, int MF) {
     return TT_OK;
 }
 
-template <typename R, bool RES, int MF>
+template <typename R, bool RES, int MF, bool PC>
 tt_status launch(tt_ctx& c, PArgs<R>& a, size_t lds, float* ms) {
     TT_HIP(hipMemsetAsync(c.bar.p, 0, c.bar.n * sizeof(unsigned), c.stream));
     void* args[] = {&a};
     TT_HIP(hipEventRecord(c.ev0, c.stream));
-    TT_HIP(hipLaunchCooperativeKernel((const void*)k_cg_persistent<R, RES, MF>, dim3(a.nwg), dim3(PT), args,
+    TT_HIP(hipLaunchCooperativeKernel((const void*)k_cg_persistent<R, RES, MF, PC>, dim3(a.nwg), dim3(PT), args,
                                       (unsigned)lds, c.stream));
     TT_HIP(hipEventRecord(c.ev1, c.stream));
     TT_HIP(hipEventSynchronize(c.ev1));
@@ -1004,14 +1147,14 @@ tt_status launch(tt_ctx& c, PArgs<R>& a, size_t lds, float* ms) {
 // residual norms (an inexact operator), not on non-finite data
 inline bool finite_breakdown(const CgScalars& h) { return std::isfinite(h.rr[h.iter & 1]) && std::isfinite(h.rr_true); }
 
-template <typename R, bool RES, int MF>
+template <typename R, bool RES, int MF, bool PC>
 tt_status run_persistent(tt_ctx& c, const float* s, double* zeta, const tt_solve_opts& o, tt_solve_info& info,
                          PArgs<R>& a, size_t lds, CgScalars& h) {
     const bool f32 = sizeof(R) == 4;
-    TT_HIP(hipFuncSetAttribute((const void*)k_cg_persistent<R, RES, MF>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    TT_HIP(hipFuncSetAttribute((const void*)k_cg_persistent<R, RES, MF, PC>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     int per_cu = 0;
-    TT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_cg_persistent<R, RES, MF>, PT, lds));
+    TT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_cg_persistent<R, RES, MF, PC>, PT, lds));
     if (per_cu < 1) {
         tt_set_error("persistent solver does not fit on a compute unit");
         return TT_INVALID_ARG;
@@ -1027,7 +1170,7 @@ tt_status run_persistent(tt_ctx& c, const float* s, double* zeta, const tt_solve
         a.aprev = aprev;
         a.gmax = gmax;
         float ms = 0.f;
-        TT_CHECK((launch<R, RES, MF>(c, a, lds, &ms)));
+        TT_CHECK((launch<R, RES, MF, PC>(c, a, lds, &ms)));
         info.kernel_ms += ms;
         info.kernel_launches++;
         TT_HIP(hipMemcpy(&h, cg_scalars(c), sizeof(h), hipMemcpyDeviceToHost));
@@ -1085,17 +1228,19 @@ tt_status run_persistent(tt_ctx& c, const float* s, double* zeta, const tt_solve
     return cg_finish(c, s, zeta, f32, have_true, info, code);
 }
 
-template <typename R, int MF>
+template <typename R, int MF, bool PC>
 tt_status run_mode(tt_ctx& c, const float* s, double* zeta, const tt_solve_opts& o, tt_solve_info& info,
                    PArgs<R>& a, size_t lds, bool res, CgScalars& h) {
-    if (res) return run_persistent<R, true, MF>(c, s, zeta, o, info, a, lds, h);
-    return run_persistent<R, false, MF>(c, s, zeta, o, info, a, lds, h);
+    if (res) return run_persistent<R, true, MF, PC>(c, s, zeta, o, info, a, lds, h);
+    return run_persistent<R, false, MF, PC>(c, s, zeta, o, info, a, lds, h);
 }
 
-// MF: column-transform mode (0 VALU, 1 FP32, 2 FP16, 3 BF16 matrix cores)
+// MF: column-transform mode (0 VALU, 1 FP32, 2 FP16, 3 BF16 matrix cores);
+// pc: block-circulant preconditioner (Mi: its spectra)
 template <typename R>
 tt_status solve_persistent_t(tt_ctx& c, const float* s, const double* x0, double* zeta, const tt_solve_opts& o,
-                             tt_solve_info& info, R* x, R* r, R* p, R* sv, const R* M, const R* noise, int MF) {
+                             tt_solve_info& info, R* x, R* r, R* p, R* sv, const R* M, const R* noise, int MF,
+                             bool pc, const R* Mi) {
     const bool f32 = sizeof(R) == 4;
     info = tt_solve_info{};
     TT_CHECK(cg_setup(c, s, x0, o, f32));
@@ -1117,8 +1262,12 @@ tt_status solve_persistent_t(tt_ctx& c, const float* s, const double* x0, double
     const int rows_per_block = (c.C * c.n + nwg - 1) / nwg;
     const bool vreg = rows_per_block * c.n <= PT;
     const int rbv = vreg ? rows_per_block : std::max(1, std::min(4, PT / std::max(c.n, 1)));
-    const bool res = lds_bytes<R>(c, Lrm, rbv, true, MF) <= lim;
-    const size_t lds = lds_bytes<R>(c, Lrm, rbv, res, MF);
+    if (pc && !vreg) {
+        tt_set_error("preconditioned persistent solver: a block's grid rows must fit its threads (n * ceil(2 n_gs n / CUs) <= 512)");
+        return TT_INVALID_ARG;
+    }
+    const bool res = lds_bytes<R>(c, Lrm, rbv, true, MF, pc) <= lim;
+    const size_t lds = lds_bytes<R>(c, Lrm, rbv, res, MF, pc);
     if (lds > lim) {
         tt_set_error("persistent solver: system too large for LDS");
         return TT_INVALID_ARG;
@@ -1148,6 +1297,7 @@ tt_status solve_persistent_t(tt_ctx& c, const float* s, const double* x0, double
     a.max_iter = o.max_iter;
     a.vmap = c.vmap.p;
     a.M = M;
+    a.Mi = Mi;
     a.Fa = reinterpret_cast<const cplx<R>*>(c.tFa.p);
     a.Fb = reinterpret_cast<const cplx<R>*>(c.tFb.p);
     a.Gr = reinterpret_cast<const cplx<R>*>(c.tGr.p);
@@ -1172,14 +1322,16 @@ tt_status solve_persistent_t(tt_ctx& c, const float* s, const double* x0, double
     a.P = p_scalars(c);
     a.bar = c.bar.p;
     if constexpr (sizeof(R) == 4) {
+        if (pc) return run_mode<R, 1, true>(c, s, zeta, o, info, a, lds, res, h);
         switch (MF) {
-            case 1: return run_mode<R, 1>(c, s, zeta, o, info, a, lds, res, h);
-            case 2: return run_mode<R, 2>(c, s, zeta, o, info, a, lds, res, h);
-            case 3: return run_mode<R, 3>(c, s, zeta, o, info, a, lds, res, h);
-            default: break;
+            case 2: return run_mode<R, 2, false>(c, s, zeta, o, info, a, lds, res, h);
+            case 3: return run_mode<R, 3, false>(c, s, zeta, o, info, a, lds, res, h);
+            default: return run_mode<R, 1, false>(c, s, zeta, o, info, a, lds, res, h);
         }
+    } else {
+        if (pc) return run_mode<R, 0, true>(c, s, zeta, o, info, a, lds, res, h);
+        return run_mode<R, 0, false>(c, s, zeta, o, info, a, lds, res, h);
     }
-    return run_mode<R, 0>(c, s, zeta, o, info, a, lds, res, h);
 }
 
 }  // namespace
@@ -1190,12 +1342,14 @@ tt_status solve_persistent(tt_ctx& c, const float* s, const double* x0, double* 
         TT_HIP(hipEventCreate(&c.ev0));
         TT_HIP(hipEventCreate(&c.ev1));
     }
+    const bool pc = o.preconditioner == TT_PRECOND_CIRCULANT;
+    if (pc) TT_CHECK(precond_build(c));
     if (o.precision == TT_PREC_F64)
         return solve_persistent_t<double>(c, s, x0, zeta, o, info, c.x64.p, c.r64.p, c.p64.p, c.q64.p, c.M64.p,
-                                          c.noise64.p, 0);
+                                          c.noise64.p, 0, pc, c.Minv64.p);
     // FP32 vectors and products; the column transforms on the matrix cores
     // with FP32, FP16 or BF16 operands
     const int MF = o.precision == TT_PREC_F16 ? 2 : o.precision == TT_PREC_BF16 ? 3 : 1;
     return solve_persistent_t<float>(c, s, x0, zeta, o, info, c.x32.p, c.r32.p, c.p32.p, c.q32.p, c.M32.p,
-                                     c.noise32.p, MF);
+                                     c.noise32.p, MF, pc, c.Minv32.p);
 }

@@ -153,6 +153,9 @@ struct tt_ctx {
     int tile_S = 0, tile_elem = 0;      // split and element size the tiles were built for
     int tile_mf = -1;                   // column-transform mode the fragments were built for
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    DevBuf<float> Minv32;               // circulant preconditioner spectra [Lh][L][C^2] (general Hermitian packing)
+    DevBuf<double> Minv64;
+    bool pc_ready = false;              // Minv built for the current system
     DevBuf<double> part;                // per-block partial sums
     DevBuf<double> scal;                // solver scalars (see cg.hip)
     DevBuf<unsigned int> bar;           // grid barrier counters
@@ -190,6 +193,10 @@ tt_status solve_kernels(tt_ctx& c, const float* s, const double* x0, double* zet
                         const tt_solve_opts& o, tt_solve_info& info);
 tt_status solve_persistent(tt_ctx& c, const float* s, const double* x0, double* zeta,
                            const tt_solve_opts& o, tt_solve_info& info);
+
+// precond.hip
+tt_status precond_build(tt_ctx& c);   // Minv32 / Minv64 of the current system (once per system)
+double precond_noise(const tt_ctx& c);
 
 // project.hip
 tt_status projection_setup(tt_ctx& c, const tt_target* t);

@@ -100,6 +100,27 @@ def test_c2_solve(c2, c2_oracle, solver):
     assert abs(res - info.rel_residual) <= 1e-8
 
 
+def test_c2_pcg_solve(c2, c2_oracle):
+    # block-circulant preconditioner at the full size: the oracle's FP64
+    # residual at or under 1e-6, in far fewer iterations than plain CG
+    import torch
+    from paper_1806_07938_amd.tt import PRECOND_CIRCULANT
+    wl, ctx, k = c2
+    s = W.turbulent_slopes(wl, seed=7)[0].astype(np.float32)
+    dev = torch_dev()
+    zeta, phi, info = ctx.solve(torch.tensor(s, device=dev), tol=1e-6, preconditioner=PRECOND_CIRCULANT)
+    _, _, info_cg = ctx.solve(torch.tensor(s, device=dev), tol=1e-6)
+    z = zeta.cpu().numpy()
+    s64 = s.astype(np.float64)
+    res = np.linalg.norm(s64 - c2_oracle(z)) / np.linalg.norm(s64)
+    say("c2 pcg iterations", info.iterations, "refinements", info.refinements, "cg iterations", info_cg.iterations,
+        "oracle relres", res, "kernel ms", info.kernel_ms, "cg kernel ms", info_cg.kernel_ms)
+    assert info.status == 0
+    assert res <= 1.01e-6
+    assert abs(res - info.rel_residual) <= 1e-8
+    assert info.iterations < 0.5 * info_cg.iterations
+
+
 @pytest.mark.parametrize("precision", [2, 3])
 def test_c2_low_precision_status_is_honest(c2, c2_oracle, precision):
     # FP16 / BF16 column transforms: TT_OK only with the oracle's FP64 residual
