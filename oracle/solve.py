@@ -15,6 +15,22 @@
       z = P r;  alpha = r.z / p.Ap;  x += alpha p;  r -= alpha Ap;
       z' = P r';  beta = r'.z' / r.z;  p = z' + beta p,
   with the same stopping rule on the unpreconditioned residual.
+* minres: the minimum-residual method for symmetric matrices, the solver the
+  paper uses for its Toeplitz system (§2.G; its experiments run it because CG
+  stalls on the mode-removed, noiseless system).  Lanczos three-term
+  recurrence with the Givens QR of the tridiagonal matrix, as in Paige and
+  Saunders (SIAM J. Numer. Anal. 12, 1975):
+      q = A v_k - alpha_k v_k - beta_k v_{k-1},  alpha_k = v_k.A v_k,
+      beta_{k+1} = ||q||,  v_{k+1} = q / beta_{k+1};
+      delta2_k = c_{k-1} delta1_k + s_{k-1} alpha_k,
+      gamma1_k = s_{k-1} delta1_k - c_{k-1} alpha_k,
+      eps_{k+1} = s_{k-1} beta_{k+1},  delta1_{k+1} = -c_{k-1} beta_{k+1},
+      gamma2_k = hypot(gamma1_k, beta_{k+1}),  c_k = gamma1_k / gamma2_k,
+      s_k = beta_{k+1} / gamma2_k,  tau_k = c_k phi_{k-1},  phi_k = s_k phi_{k-1},
+      d_k = (v_k - delta2_k d_{k-1} - eps_k d_{k-2}) / gamma2_k,  x_k = x_{k-1} + tau_k d_k,
+  starting from c_0 = -1, s_0 = 0, delta1_1 = eps_1 = 0, phi_0 = beta_1 =
+  ||s - A x0||; phi_k is the residual norm of x_k, stopping at
+  phi_k <= tol ||s||_2.
 """
 import numpy as np
 import scipy.linalg
@@ -77,4 +93,48 @@ def pcg(apply_A, apply_P, s, tol=1e-6, maxiter=10000, x0=None, history=False):
         rz = rz_new
         it += 1
         hist.append(float(np.linalg.norm(r)) / bnorm)
+    return (x, it, hist) if history else (x, it)
+
+
+def minres(apply_A, s, tol=1e-6, maxiter=10000, x0=None, history=False):
+    s = np.asarray(s, dtype=np.float64)
+    x = np.zeros_like(s) if x0 is None else np.array(x0, dtype=np.float64)
+    r = s - apply_A(x) if x0 is not None else s.copy()
+    bnorm = float(np.sqrt(s @ s))
+    beta = float(np.linalg.norm(r))
+    hist = [beta / bnorm if bnorm > 0 else 0.0]
+    if bnorm == 0.0 or beta <= tol * bnorm:
+        return (x, 0, hist) if history else (x, 0)
+    v_prev = np.zeros_like(s)
+    v = r / beta
+    d_prev = np.zeros_like(s)
+    d_prev2 = np.zeros_like(s)
+    c, sn = -1.0, 0.0
+    delta1, eps = 0.0, 0.0
+    phi = beta
+    it = 0
+    while it < maxiter:
+        q = apply_A(v)
+        alpha = float(v @ q)
+        q = q - alpha * v - beta * v_prev
+        beta_next = float(np.linalg.norm(q))
+        # Givens QR of the new column of the tridiagonal matrix
+        delta2 = c * delta1 + sn * alpha
+        gamma1 = sn * delta1 - c * alpha
+        eps_next = sn * beta_next
+        delta1_next = -c * beta_next
+        gamma2 = float(np.hypot(gamma1, beta_next))
+        c, sn = gamma1 / gamma2, beta_next / gamma2
+        tau = c * phi
+        phi = sn * phi
+        d = (v - delta2 * d_prev - eps * d_prev2) / gamma2
+        x = x + tau * d
+        it += 1
+        hist.append(abs(phi) / bnorm)
+        if abs(phi) <= tol * bnorm or beta_next == 0.0:
+            break
+        d_prev2, d_prev = d_prev, d
+        v_prev, v = v, q / beta_next
+        beta = beta_next
+        delta1, eps = delta1_next, eps_next
     return (x, it, hist) if history else (x, it)

@@ -51,3 +51,54 @@ def test_cg_warm_start_at_solution_does_nothing():
     z = S.cholesky_solve(A, s)
     x, it = S.cg(lambda v: A @ v, s, tol=1e-8, x0=z)
     assert it == 0
+
+
+# --- MINRES (§2.G, the paper's Toeplitz solver) ---------------------------------
+
+def test_minres_matches_cholesky_c1():
+    from oracle.solve import minres
+    wl = W.c1()
+    A = C.system_matrix(wl)
+    s = W.turbulent_slopes(wl)[0]
+    x, k, hist = minres(lambda v: A @ v, s, tol=1e-10, history=True)
+    zref = S.cholesky_solve(A, s)
+    assert np.linalg.norm(s - A @ x) <= 1.0001e-10 * np.linalg.norm(s)
+    assert np.linalg.norm(x - zref) <= 1e-6 * np.linalg.norm(zref)
+    # the QR estimate is the true residual norm, and it never increases
+    assert abs(hist[-1] - np.linalg.norm(s - A @ x) / np.linalg.norm(s)) <= 1e-3 * hist[-1]
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(hist, hist[1:]))
+
+
+def test_minres_finite_termination_distinct_eigenvalues():
+    from oracle.solve import minres
+    rng = np.random.default_rng(3)
+    Q, _ = np.linalg.qr(rng.standard_normal((40, 40)))
+    lam = np.repeat([0.5, 1.0, 3.0, 7.0, 20.0], 8)
+    A = (Q * lam) @ Q.T
+    b = rng.standard_normal(40)
+    x, k = minres(lambda v: A @ v, b, tol=1e-10)
+    assert k <= 5     # five distinct eigenvalues: the Krylov space is exhausted after five steps
+    assert np.linalg.norm(A @ x - b) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_minres_symmetric_indefinite():
+    # where CG's energy norm does not exist MINRES still solves (the reason the paper uses it)
+    from oracle.solve import minres
+    rng = np.random.default_rng(5)
+    Q, _ = np.linalg.qr(rng.standard_normal((60, 60)))
+    lam = np.concatenate([-np.linspace(1, 5, 20), np.linspace(0.5, 9, 40)])
+    A = (Q * lam) @ Q.T
+    b = rng.standard_normal(60)
+    x, k = minres(lambda v: A @ v, b, tol=1e-10, maxiter=500)
+    assert np.linalg.norm(x - np.linalg.solve(A, b)) <= 1e-8 * np.linalg.norm(x)
+
+
+def test_minres_equals_cg_iterate_count_order_on_spd():
+    # on an SPD system MINRES and CG need iteration counts of the same order
+    from oracle.solve import minres
+    wl = W.c1()
+    A = C.system_matrix(wl)
+    s = W.turbulent_slopes(wl)[0]
+    _, kcg = S.cg(lambda v: A @ v, s, tol=1e-8)
+    _, kmr = minres(lambda v: A @ v, s, tol=1e-8)
+    assert 0.5 * kcg <= kmr <= 1.5 * kcg
