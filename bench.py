@@ -102,8 +102,9 @@ def main():
     import torch
     import workloads as W
     from paper_1806_07938_amd import Context, system_from
-    from paper_1806_07938_amd.tt import (PRECOND_CIRCULANT, PRECOND_NONE, PREC_BF16, PREC_F16, PREC_F32, PREC_F64,
-                                         SOLVER_KERNELS, SOLVER_PERSISTENT, TT_NOT_CONVERGED)
+    from paper_1806_07938_amd.tt import (METHOD_CG, METHOD_MINRES, PRECOND_CIRCULANT, PRECOND_NONE, PREC_BF16,
+                                         PREC_F16, PREC_F32, PREC_F64, SOLVER_KERNELS, SOLVER_PERSISTENT,
+                                         TT_NOT_CONVERGED)
 
     dev = torch.device("cuda:0")
     if args.copy_calibration:
@@ -131,9 +132,9 @@ def main():
     solver = SOLVER_PERSISTENT if args.solver == "persistent" else SOLVER_KERNELS
     pc = PRECOND_CIRCULANT if (args.preconditioner == "circulant" and solver == SOLVER_PERSISTENT) else PRECOND_NONE
 
-    def run(k, prec=prec, solver=solver, allow=(0,), pc=pc):
+    def run(k, prec=prec, solver=solver, allow=(0,), pc=pc, method=METHOD_CG):
         return ctx.solve(S[k % args.frames], zeta=zeta, phi=phi, tol=args.tol, precision=prec, solver=solver,
-                         allow=allow, preconditioner=pc)[2]
+                         allow=allow, preconditioner=pc, method=method)[2]
 
     t0 = time.perf_counter()
     if pc:   # the preconditioner spectra are built once per system, before the timed solves
@@ -208,20 +209,23 @@ def main():
         # phase, and the FP16 / BF16 column-transform forms (which may stop
         # short of the tolerance: status and the FP64 residual reached are
         # reported per frame)
-        for name, p, sv, vpc in (("f32_persistent_plain_cg", PREC_F32, SOLVER_PERSISTENT, PRECOND_NONE),
-                                 ("f32_persistent_pcg", PREC_F32, SOLVER_PERSISTENT, PRECOND_CIRCULANT),
-                                 ("f64_persistent_plain_cg", PREC_F64, SOLVER_PERSISTENT, PRECOND_NONE),
-                                 ("f64_persistent_pcg", PREC_F64, SOLVER_PERSISTENT, PRECOND_CIRCULANT),
-                                 ("f32_kernels_plain_cg", PREC_F32, SOLVER_KERNELS, PRECOND_NONE),
-                                 ("f16_persistent_plain_cg", PREC_F16, SOLVER_PERSISTENT, PRECOND_NONE),
-                                 ("bf16_persistent_plain_cg", PREC_BF16, SOLVER_PERSISTENT, PRECOND_NONE)):
-            if p == prec and sv == solver and vpc == pc:
+        CG, MR = METHOD_CG, METHOD_MINRES
+        for name, p, sv, vpc, mth in (("f32_persistent_plain_cg", PREC_F32, SOLVER_PERSISTENT, PRECOND_NONE, CG),
+                                      ("f32_persistent_pcg", PREC_F32, SOLVER_PERSISTENT, PRECOND_CIRCULANT, CG),
+                                      ("f32_persistent_minres", PREC_F32, SOLVER_PERSISTENT, PRECOND_NONE, MR),
+                                      ("f64_persistent_plain_cg", PREC_F64, SOLVER_PERSISTENT, PRECOND_NONE, CG),
+                                      ("f64_persistent_pcg", PREC_F64, SOLVER_PERSISTENT, PRECOND_CIRCULANT, CG),
+                                      ("f64_persistent_minres", PREC_F64, SOLVER_PERSISTENT, PRECOND_NONE, MR),
+                                      ("f32_kernels_plain_cg", PREC_F32, SOLVER_KERNELS, PRECOND_NONE, CG),
+                                      ("f16_persistent_plain_cg", PREC_F16, SOLVER_PERSISTENT, PRECOND_NONE, CG),
+                                      ("bf16_persistent_plain_cg", PREC_BF16, SOLVER_PERSISTENT, PRECOND_NONE, CG)):
+            if p == prec and sv == solver and vpc == pc and mth == CG:
                 continue
             allow = (0, TT_NOT_CONVERGED)
-            run(0, p, sv, allow, vpc)
+            run(0, p, sv, allow, vpc, mth)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            ii = [run(k, p, sv, allow, vpc) for k in range(3)]
+            ii = [run(k, p, sv, allow, vpc, mth) for k in range(3)]
             torch.cuda.synchronize()
             side[name] = {"ms_per_solve": round((time.perf_counter() - t0) * 1e3 / 3, 3),
                           "iterations_mean": round(float(np.mean([i.iterations for i in ii])), 1),

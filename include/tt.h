@@ -84,6 +84,16 @@ typedef enum {
 } tt_solver_kind;
 
 typedef enum {
+    TT_METHOD_CG = 0,         /* conjugate gradients (§2.G) */
+    TT_METHOD_MINRES = 1      /* minimum residual (Paige-Saunders Lanczos + Givens QR), the
+                                 paper's solver for its Toeplitz system (§2.G); stops on the
+                                 QR residual estimate, certified like CG by the FP64 true
+                                 residual.  TT_SOLVER_PERSISTENT with TT_PREC_F32 or
+                                 TT_PREC_F64, no preconditioner, and a block's grid rows
+                                 must fit its threads (as TT_PRECOND_CIRCULANT). */
+} tt_method;
+
+typedef enum {
     TT_PRECOND_NONE = 0,      /* plain CG (§2.G) */
     TT_PRECOND_CIRCULANT = 1  /* CG preconditioned by the block-circulant inverse: the
                                  restriction to the valid subapertures of
@@ -144,6 +154,7 @@ typedef struct {
                                      recursive residual fell by this factor since the
                                      last one (0 -> 1e-3) */
     int preconditioner;           /* tt_preconditioner (0: none) */
+    int method;                   /* tt_method (0: CG) */
 } tt_solve_opts;
 
 typedef struct {

@@ -186,6 +186,7 @@ tt_status solve_impl(tt_ctx* c, const float* s, const double* x0, double* zeta, 
     o.solver = TT_SOLVER_PERSISTENT;
     o.refine_drop = 1e-3;
     o.preconditioner = TT_PRECOND_NONE;
+    o.method = TT_METHOD_CG;
     if (opts) o = *opts;
     TT_REQUIRE(std::isfinite(o.tol) && o.tol >= 0, "tol must be >= 0");
     TT_REQUIRE(o.max_iter >= 0, "max_iter must be >= 0");
@@ -201,6 +202,11 @@ tt_status solve_impl(tt_ctx* c, const float* s, const double* x0, double* zeta, 
     TT_REQUIRE(o.preconditioner == TT_PRECOND_NONE ||
                    (o.solver == TT_SOLVER_PERSISTENT && (o.precision == TT_PREC_F32 || o.precision == TT_PREC_F64)),
                "TT_PRECOND_CIRCULANT needs TT_SOLVER_PERSISTENT with TT_PREC_F32 or TT_PREC_F64");
+    TT_REQUIRE(o.method == TT_METHOD_CG || o.method == TT_METHOD_MINRES, "unknown method");
+    TT_REQUIRE(o.method == TT_METHOD_CG ||
+                   (o.solver == TT_SOLVER_PERSISTENT && o.preconditioner == TT_PRECOND_NONE &&
+                    (o.precision == TT_PREC_F32 || o.precision == TT_PREC_F64)),
+               "TT_METHOD_MINRES needs TT_SOLVER_PERSISTENT, TT_PREC_F32 or TT_PREC_F64 and no preconditioner");
     TT_CHECK(use_device(c->device));
     tt_solve_info inf{};
     if (o.solver == TT_SOLVER_PERSISTENT)

@@ -46,6 +46,7 @@
 namespace {
 
 constexpr int PT = 512;                                  // threads per block
+enum { K_CG = 0, K_PCG = 1, K_MINRES = 2 };              // iteration of the persistent kernel
 constexpr unsigned long long SPIN_TICKS = 200000000ull;  // 2 s of the 100 MHz wall clock
 
 template <typename R>
@@ -391,6 +392,63 @@ __device__ void row_pc_precond(const PArgs<R>& a, const Tiles<R>& t, Lane<R>& v,
     fwd_rows(a, t.Gr, xs, blockIdx.x * a.rbv, 1, nrk);
     const D3 tot = block_sum3(D3{sg, 0.0, 0.0}, red);
     if (threadIdx.x == 0) a.part[((long)par * a.nwg + blockIdx.x) * 4 + 1] = tot.a;
+}
+
+// MINRES (Paige-Saunders; the paper's solver for its Toeplitz system, §2.G),
+// CG vectors in registers with the lane fields read as
+//   r: q_j = beta_j v_j, the Lanczos vector before normalisation,
+//   p: v_{j-1},  s: d_{j-2},  u: d_{j-3}  (direction vectors of the solution).
+// At the top of iteration j the partial sums give beta_j = ||q_j|| and
+// alpha_j = v_j.A v_j = q_j.A q_j / beta_j^2, and the Givens QR step j-1 of
+// the tridiagonal matrix (scalars identical in every block) gives tau, delta2,
+// eps, gamma2 and the residual norm phi_{j-1}.  This row phase then applies
+// the solution update of step j-1 (qr set), normalises v_j, forms
+// A v_j = (C q_j + sigma^2 q_j) / beta_j from the gathered column outputs, and
+// the next Lanczos vector q_{j+1} = A v_j - alpha_j v_j - beta_j v_{j-1};
+// partial ||q||^2 and sigma^2 ||q||^2 in slots 0 and 1 (the CG layout), and the
+// forward row transform of q_{j+1} for the column phase's q.C q.
+template <typename R>
+__device__ inline void mr_update(Lane<R>& v, bool qr, R tau, R delta2, R eps, R igamma2) {
+    if (qr) {
+        const R d = (v.p - delta2 * v.s - eps * v.u) * igamma2;
+        v.x += tau * d;
+        v.u = v.s;
+        v.s = d;
+    }
+}
+
+template <typename R>
+__device__ void row_mr(const PArgs<R>& a, const Tiles<R>& t, Lane<R>& v, int nrk, bool qr, R tau, R delta2, R eps,
+                       R igamma2, R alpha, R beta, int par, double* red) {
+    const int n = a.n, Lh = a.Lh, L = a.L;
+    cplx<R>* Us = t.work;   // filled by gather_u before the call
+    R* xs = reinterpret_cast<R*>(Us + a.rbv * Lh);
+    __syncthreads();
+    double g = 0.0, sg = 0.0;
+    if ((int)threadIdx.x < nrk * n) {
+        const int k = threadIdx.x / n, b = threadIdx.x % n;
+        R qn = 0;
+        if (v.gi >= 0) {
+            mr_update(v, qr, tau, delta2, eps, igamma2);
+            const R ib = R(1) / beta;
+            const R inv = R(1) / (R(L) * R(L));
+            const R vj = v.r * ib;
+            const R avj = (inv_row(Us + k * Lh, t.Gr, n, b, L, Lh) * inv + v.nz * v.r) * ib;
+            qn = avj - alpha * vj - beta * v.p;
+            v.p = vj;
+            v.r = qn;
+            g = (double)qn * (double)qn;
+            sg = (double)v.nz * g;
+        }
+        xs[k * n + b] = qn;
+    }
+    __syncthreads();
+    fwd_rows(a, t.Gr, xs, blockIdx.x * a.rbv, 1, nrk);
+    const D3 tot = block_sum3(D3{g, sg, 0.0}, red);
+    if (threadIdx.x == 0) {
+        a.part[((long)par * a.nwg + blockIdx.x) * 4 + 0] = tot.a;
+        a.part[((long)par * a.nwg + blockIdx.x) * 4 + 1] = tot.b;
+    }
 }
 
 // Row phase with the CG vectors in global memory (systems with more rows per block).
@@ -764,9 +822,12 @@ __device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, int par, double*
     if (threadIdx.x == 0) a.part[((long)par * a.nwg + blockIdx.x) * 4 + slot] = tot.a / ((double)a.L * (double)a.L);
 }
 
-// PC: preconditioned CG (four phases per iteration, see row_pc_update).
-template <typename R, bool RES, int MF, bool PC>
+// KIND: K_CG, K_PCG (preconditioned CG, four phases per iteration, see
+// row_pc_update) or K_MINRES (see row_mr).
+template <typename R, bool RES, int MF, int KIND>
 __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
+    constexpr bool PC = KIND == K_PCG;
+    constexpr bool MR = KIND == K_MINRES;
     extern __shared__ __align__(16) char smem_raw[];
     __shared__ double red[3 * PT / 64];
     __shared__ int s_flag;
@@ -873,6 +934,9 @@ __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
     double gprev = a.gprev, aprev = a.aprev;
     bool first = a.first != 0;
     const double tol2 = a.S_->tol2, drop2 = a.S_->drop2;
+    // MINRES: Givens QR state (every launch starts a fresh Lanczos process)
+    double mr_c = -1.0, mr_s = 0.0, mr_d1 = 0.0, mr_eps = 0.0, mr_phi = 0.0, mr_alpha = 0.0;
+    int mr_k = 0;   // Lanczos vectors normalised so far in this launch
     while (true) {
         const int par = it & 1;
         // The loads of the partial sums and of this block's column-phase outputs
@@ -899,11 +963,45 @@ __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
         const double dl = PC ? tot.b : tot.c + tot.b;
         int st = ST_RUN;
         double alpha = 0.0, beta = 0.0;
+        // MINRES scalars of this iteration (see row_mr)
+        bool mr_qr = false;
+        double mr_tau = 0.0, mr_delta2 = 0.0, mr_epsk = 0.0, mr_ig = 0.0, mr_rr = 0.0;
+        if constexpr (MR) {
+            beta = sqrt(g);          // beta_j = ||q_j||
+            alpha = dl / g;          // alpha_j = q_j.A q_j / ||q_j||^2
+            mr_qr = mr_k >= 1;
+            bool bad = !isfinite(g) || !isfinite(dl);
+            if (mr_qr) {             // Givens QR step j-1: alpha_{j-1} = mr_alpha, beta_j
+                mr_delta2 = mr_c * mr_d1 + mr_s * mr_alpha;
+                const double gamma1 = mr_s * mr_d1 - mr_c * mr_alpha;
+                const double eps_next = mr_s * beta, d1_next = -mr_c * beta;
+                const double gamma2 = sqrt(gamma1 * gamma1 + beta * beta);
+                bad = bad || !(gamma2 > 0.0);
+                mr_epsk = mr_eps;
+                mr_c = gamma1 / gamma2;
+                mr_s = beta / gamma2;
+                mr_tau = mr_c * mr_phi;
+                mr_phi = mr_s * mr_phi;
+                mr_ig = 1.0 / gamma2;
+                mr_eps = eps_next;
+                mr_d1 = d1_next;
+            } else {
+                mr_phi = beta;       // phi_0 = beta_1 = ||r||
+            }
+            mr_alpha = alpha;
+            mr_rr = mr_phi * mr_phi; // residual norm^2 of the current iterate
+            if (bad || !isfinite(mr_rr)) st = ST_BREAK;
+            else if (mr_rr <= tol2) st = ST_CONV;
+            else if (drop2 > 0.0 && mr_rr < drop2 * a.gmax) st = ST_REFINE;
+            else if (it >= a.max_iter) st = ST_CAP;
+            else if (!(g > 0.0)) st = ST_BREAK;
+        } else {
         if (!isfinite(g) || !isfinite(dl) || !isfinite(gm)) st = ST_BREAK;
         else if (g <= tol2) st = ST_CONV;
         else if (drop2 > 0.0 && g < drop2 * a.gmax) st = ST_REFINE;
         else if (it >= a.max_iter) st = ST_CAP;
-        if (st == ST_RUN) {
+        }
+        if (!MR && st == ST_RUN) {
             if (first) {
                 beta = 0.0;
                 alpha = gm / dl;
@@ -914,6 +1012,9 @@ __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
             if (!(alpha > 0.0) || !isfinite(alpha)) st = ST_BREAK;
         }
         if (st != ST_RUN) {
+            // MINRES: the solution update of the QR step just taken
+            if (MR && a.vreg && v.gi >= 0 && st != ST_BREAK)
+                mr_update(v, mr_qr, (R)mr_tau, (R)mr_delta2, (R)mr_epsk, (R)mr_ig);
             if (a.vreg && v.gi >= 0) {
                 a.x[v.gi] = v.x;
                 a.r[v.gi] = v.r;
@@ -928,12 +1029,16 @@ __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
                 a.P->first = first ? 1 : 0;
                 a.S_->state = st;
                 a.S_->iter = it;
-                a.S_->rr[it & 1] = g;
+                a.S_->rr[it & 1] = MR ? mr_rr : g;
             }
             return;
         }
         if constexpr (PC) {
             row_pc_update<R>(a, t, v, nrk, (R)alpha, (R)beta, (it + 1) & 1, red);
+        } else if constexpr (MR) {
+            row_mr<R>(a, t, v, nrk, mr_qr, (R)mr_tau, (R)mr_delta2, (R)mr_epsk, (R)mr_ig, (R)alpha, (R)beta,
+                      (it + 1) & 1, red);
+            ++mr_k;
         } else {
             if (a.vreg) row_phase_reg<R>(a, t, v, nrk, true, (R)alpha, (R)beta, (it + 1) & 1, red);
             else row_phase_mem<R>(a, t, true, (R)alpha, (R)beta, (it + 1) & 1, red);
@@ -1124,12 +1229,12 @@ tt_status build_tiles(tt_ctx& c, int S, int Lrm, int MF) {
     return TT_OK;
 }
 
-template <typename R, bool RES, int MF, bool PC>
+template <typename R, bool RES, int MF, int KIND>
 tt_status launch(tt_ctx& c, PArgs<R>& a, size_t lds, float* ms) {
     TT_HIP(hipMemsetAsync(c.bar.p, 0, c.bar.n * sizeof(unsigned), c.stream));
     void* args[] = {&a};
     TT_HIP(hipEventRecord(c.ev0, c.stream));
-    TT_HIP(hipLaunchCooperativeKernel((const void*)k_cg_persistent<R, RES, MF, PC>, dim3(a.nwg), dim3(PT), args,
+    TT_HIP(hipLaunchCooperativeKernel((const void*)k_cg_persistent<R, RES, MF, KIND>, dim3(a.nwg), dim3(PT), args,
                                       (unsigned)lds, c.stream));
     TT_HIP(hipEventRecord(c.ev1, c.stream));
     TT_HIP(hipEventSynchronize(c.ev1));
@@ -1147,14 +1252,14 @@ tt_status launch(tt_ctx& c, PArgs<R>& a, size_t lds, float* ms) {
 // residual norms (an inexact operator), not on non-finite data
 inline bool finite_breakdown(const CgScalars& h) { return std::isfinite(h.rr[h.iter & 1]) && std::isfinite(h.rr_true); }
 
-template <typename R, bool RES, int MF, bool PC>
+template <typename R, bool RES, int MF, int KIND>
 tt_status run_persistent(tt_ctx& c, const float* s, double* zeta, const tt_solve_opts& o, tt_solve_info& info,
                          PArgs<R>& a, size_t lds, CgScalars& h) {
     const bool f32 = sizeof(R) == 4;
-    TT_HIP(hipFuncSetAttribute((const void*)k_cg_persistent<R, RES, MF, PC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    TT_HIP(hipFuncSetAttribute((const void*)k_cg_persistent<R, RES, MF, KIND>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     int per_cu = 0;
-    TT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_cg_persistent<R, RES, MF, PC>, PT, lds));
+    TT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_cg_persistent<R, RES, MF, KIND>, PT, lds));
     if (per_cu < 1) {
         tt_set_error("persistent solver does not fit on a compute unit");
         return TT_INVALID_ARG;
@@ -1170,7 +1275,7 @@ tt_status run_persistent(tt_ctx& c, const float* s, double* zeta, const tt_solve
         a.aprev = aprev;
         a.gmax = gmax;
         float ms = 0.f;
-        TT_CHECK((launch<R, RES, MF, PC>(c, a, lds, &ms)));
+        TT_CHECK((launch<R, RES, MF, KIND>(c, a, lds, &ms)));
         info.kernel_ms += ms;
         info.kernel_launches++;
         TT_HIP(hipMemcpy(&h, cg_scalars(c), sizeof(h), hipMemcpyDeviceToHost));
@@ -1228,19 +1333,20 @@ tt_status run_persistent(tt_ctx& c, const float* s, double* zeta, const tt_solve
     return cg_finish(c, s, zeta, f32, have_true, info, code);
 }
 
-template <typename R, int MF, bool PC>
+template <typename R, int MF, int KIND>
 tt_status run_mode(tt_ctx& c, const float* s, double* zeta, const tt_solve_opts& o, tt_solve_info& info,
                    PArgs<R>& a, size_t lds, bool res, CgScalars& h) {
-    if (res) return run_persistent<R, true, MF, PC>(c, s, zeta, o, info, a, lds, h);
-    return run_persistent<R, false, MF, PC>(c, s, zeta, o, info, a, lds, h);
+    if (res) return run_persistent<R, true, MF, KIND>(c, s, zeta, o, info, a, lds, h);
+    return run_persistent<R, false, MF, KIND>(c, s, zeta, o, info, a, lds, h);
 }
 
 // MF: column-transform mode (0 VALU, 1 FP32, 2 FP16, 3 BF16 matrix cores);
-// pc: block-circulant preconditioner (Mi: its spectra)
+// kind: K_CG, K_PCG (block-circulant preconditioner, Mi: its spectra), K_MINRES
 template <typename R>
 tt_status solve_persistent_t(tt_ctx& c, const float* s, const double* x0, double* zeta, const tt_solve_opts& o,
                              tt_solve_info& info, R* x, R* r, R* p, R* sv, const R* M, const R* noise, int MF,
-                             bool pc, const R* Mi) {
+                             int kind, const R* Mi) {
+    const bool pc = kind == K_PCG;
     const bool f32 = sizeof(R) == 4;
     info = tt_solve_info{};
     TT_CHECK(cg_setup(c, s, x0, o, f32));
@@ -1262,8 +1368,8 @@ tt_status solve_persistent_t(tt_ctx& c, const float* s, const double* x0, double
     const int rows_per_block = (c.C * c.n + nwg - 1) / nwg;
     const bool vreg = rows_per_block * c.n <= PT;
     const int rbv = vreg ? rows_per_block : std::max(1, std::min(4, PT / std::max(c.n, 1)));
-    if (pc && !vreg) {
-        tt_set_error("preconditioned persistent solver: a block's grid rows must fit its threads (n * ceil(2 n_gs n / CUs) <= 512)");
+    if (kind != K_CG && !vreg) {
+        tt_set_error("preconditioned CG / MINRES: a block's grid rows must fit its threads (n * ceil(2 n_gs n / CUs) <= 512)");
         return TT_INVALID_ARG;
     }
     const bool res = lds_bytes<R>(c, Lrm, rbv, true, MF, pc) <= lim;
@@ -1322,15 +1428,17 @@ tt_status solve_persistent_t(tt_ctx& c, const float* s, const double* x0, double
     a.P = p_scalars(c);
     a.bar = c.bar.p;
     if constexpr (sizeof(R) == 4) {
-        if (pc) return run_mode<R, 1, true>(c, s, zeta, o, info, a, lds, res, h);
+        if (pc) return run_mode<R, 1, K_PCG>(c, s, zeta, o, info, a, lds, res, h);
+        if (kind == K_MINRES) return run_mode<R, 1, K_MINRES>(c, s, zeta, o, info, a, lds, res, h);
         switch (MF) {
-            case 2: return run_mode<R, 2, false>(c, s, zeta, o, info, a, lds, res, h);
-            case 3: return run_mode<R, 3, false>(c, s, zeta, o, info, a, lds, res, h);
-            default: return run_mode<R, 1, false>(c, s, zeta, o, info, a, lds, res, h);
+            case 2: return run_mode<R, 2, K_CG>(c, s, zeta, o, info, a, lds, res, h);
+            case 3: return run_mode<R, 3, K_CG>(c, s, zeta, o, info, a, lds, res, h);
+            default: return run_mode<R, 1, K_CG>(c, s, zeta, o, info, a, lds, res, h);
         }
     } else {
-        if (pc) return run_mode<R, 0, true>(c, s, zeta, o, info, a, lds, res, h);
-        return run_mode<R, 0, false>(c, s, zeta, o, info, a, lds, res, h);
+        if (pc) return run_mode<R, 0, K_PCG>(c, s, zeta, o, info, a, lds, res, h);
+        if (kind == K_MINRES) return run_mode<R, 0, K_MINRES>(c, s, zeta, o, info, a, lds, res, h);
+        return run_mode<R, 0, K_CG>(c, s, zeta, o, info, a, lds, res, h);
     }
 }
 
@@ -1344,12 +1452,13 @@ tt_status solve_persistent(tt_ctx& c, const float* s, const double* x0, double* 
     }
     const bool pc = o.preconditioner == TT_PRECOND_CIRCULANT;
     if (pc) TT_CHECK(precond_build(c));
+    const int kind = o.method == TT_METHOD_MINRES ? K_MINRES : pc ? K_PCG : K_CG;
     if (o.precision == TT_PREC_F64)
         return solve_persistent_t<double>(c, s, x0, zeta, o, info, c.x64.p, c.r64.p, c.p64.p, c.q64.p, c.M64.p,
-                                          c.noise64.p, 0, pc, c.Minv64.p);
+                                          c.noise64.p, 0, kind, c.Minv64.p);
     // FP32 vectors and products; the column transforms on the matrix cores
     // with FP32, FP16 or BF16 operands
     const int MF = o.precision == TT_PREC_F16 ? 2 : o.precision == TT_PREC_BF16 ? 3 : 1;
     return solve_persistent_t<float>(c, s, x0, zeta, o, info, c.x32.p, c.r32.p, c.p32.p, c.q32.p, c.M32.p,
-                                     c.noise32.p, MF, pc, c.Minv32.p);
+                                     c.noise32.p, MF, kind, c.Minv32.p);
 }

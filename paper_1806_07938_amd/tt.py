@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libtt.so")
 TT_OK, TT_INVALID_ARG, TT_HIP_ERROR, TT_OUT_OF_MEMORY, TT_NOT_CONVERGED, TT_BREAKDOWN, TT_NOT_READY = range(7)
 PREC_F32, PREC_F64, PREC_F16, PREC_BF16 = 0, 1, 2, 3
 PRECOND_NONE, PRECOND_CIRCULANT = 0, 1
+METHOD_CG, METHOD_MINRES = 0, 1
 SOLVER_PERSISTENT, SOLVER_KERNELS = 0, 1
 MODEL_HUDGIN, MODEL_FRIED = 0, 1
 
@@ -56,7 +57,7 @@ class _Target(C.Structure):
 
 class _SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("precision", C.c_int), ("solver", C.c_int),
-                ("refine_drop", C.c_double), ("preconditioner", C.c_int)]
+                ("refine_drop", C.c_double), ("preconditioner", C.c_int), ("method", C.c_int)]
 
 
 class _SolveInfo(C.Structure):
@@ -241,7 +242,8 @@ class Context:
 
     def solve(self, s, x0=None, zeta=None, phi=None, project: bool = True, tol: float = 1e-6,
               max_iter: int = 20000, precision: int = PREC_F32, solver: int = SOLVER_PERSISTENT,
-              refine_drop: float = 1e-3, preconditioner: int = PRECOND_NONE, allow=(TT_OK,)):
+              refine_drop: float = 1e-3, preconditioner: int = PRECOND_NONE, method: int = METHOD_CG,
+              allow=(TT_OK,)):
         """Solve for zeta (float64) and, if a target is set and project, phi (float32)."""
         import torch
         n = self.info["n_slopes"]
@@ -255,7 +257,7 @@ class Context:
         else:
             phi = None
         opts = _SolveOpts(float(tol), int(max_iter), int(precision), int(solver), float(refine_drop),
-                          int(preconditioner))
+                          int(preconditioner), int(method))
         inf = _SolveInfo()
         px0 = _dptr(x0, torch.float64, n) if x0 is not None else None
         st = load().tt_solve_frame(self._h, _dptr(s, torch.float32, n), px0, _dptr(zeta, torch.float64, n),

@@ -121,6 +121,23 @@ def test_c2_pcg_solve(c2, c2_oracle):
     assert info.iterations < 0.5 * info_cg.iterations
 
 
+def test_c2_minres_solve(c2, c2_oracle):
+    # the paper's solver at the full size: the oracle's FP64 residual at or under 1e-6
+    import torch
+    from paper_1806_07938_amd.tt import METHOD_MINRES
+    wl, ctx, k = c2
+    s = W.turbulent_slopes(wl, seed=7)[0].astype(np.float32)
+    zeta, phi, info = ctx.solve(torch.tensor(s, device=torch_dev()), tol=1e-6, method=METHOD_MINRES)
+    z = zeta.cpu().numpy()
+    s64 = s.astype(np.float64)
+    res = np.linalg.norm(s64 - c2_oracle(z)) / np.linalg.norm(s64)
+    say("c2 minres iterations", info.iterations, "refinements", info.refinements, "oracle relres", res,
+        "kernel ms", info.kernel_ms)
+    assert info.status == 0
+    assert res <= 1.01e-6
+    assert abs(res - info.rel_residual) <= 1e-8
+
+
 @pytest.mark.parametrize("precision", [2, 3])
 def test_c2_low_precision_status_is_honest(c2, c2_oracle, precision):
     # FP16 / BF16 column transforms: TT_OK only with the oracle's FP64 residual

@@ -1,0 +1,90 @@
+"""GPU parity of the persistent MINRES (TT_METHOD_MINRES, the paper's solver
+for its Toeplitz system, §2.G) against the oracle's MINRES, through the C ABI.
+
+* Early iterates: max_iter = k returns the k-th MINRES iterate; in FP64 it
+  equals the oracle's (Lanczos + Givens QR in the same order of steps) to
+  1e-10 for k = 1, 2, 3, 5 (k = 1 is the residual-minimising multiple of s).
+* Full solves reach the Cholesky solution (FP64 true residual at or under
+  tol, recomputed with the oracle's dense matrix; solution to 1e-5) in as many
+  iterations as the oracle's MINRES (FP64: within 5 %).
+* Argument errors for the combinations MINRES does not support."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_helpers import make_system, say, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = [dict(n=5, n_gs=2, lgs=True, n_layer=3, seed=4, pad_L=12),
+         dict(n=7, n_gs=4, lgs=True, n_layer=2, seed=5, pad_L=16)]
+
+
+def _wl(case):
+    return W.tiny(**case) if isinstance(case, dict) else case()
+
+
+@pytest.mark.parametrize("case", CASES + [W.c1], ids=lambda c: str(c) if isinstance(c, dict) else "c1")
+def test_early_iterates_match_oracle(case):
+    import torch
+    from oracle.covariance import system_matrix
+    from oracle.solve import minres
+    from paper_1806_07938_amd.tt import METHOD_MINRES, TT_NOT_CONVERGED
+    wl = _wl(case)
+    ctx, k = make_system(wl, target=False)
+    s = W.turbulent_slopes(wl)[0].astype(np.float32)
+    A = system_matrix(wl)
+    st = torch.tensor(s, device=torch_dev())
+    for it in (1, 2, 3, 5):
+        z, _, info = ctx.solve(st, tol=1e-14, max_iter=it, precision=1, method=METHOD_MINRES,
+                               allow=(0, TT_NOT_CONVERGED))
+        xr, kr = minres(lambda v: A @ v, s.astype(np.float64), tol=1e-14, maxiter=it)
+        d = np.linalg.norm(z.cpu().numpy() - xr) / np.linalg.norm(xr)
+        say("minres", wl.name, "iterations", it, info.iterations, "difference", d)
+        assert info.iterations == it == kr
+        assert d < 1e-10
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+@pytest.mark.parametrize("case", CASES + [W.c1], ids=lambda c: str(c) if isinstance(c, dict) else "c1")
+def test_minres_solve_matches_cholesky(case, precision):
+    import torch
+    from oracle.covariance import system_matrix
+    from oracle.solve import cholesky_solve, minres
+    from paper_1806_07938_amd.tt import METHOD_MINRES
+    wl = _wl(case)
+    ctx, k = make_system(wl, target=True)
+    s = W.turbulent_slopes(wl)[0].astype(np.float32)
+    s64 = s.astype(np.float64)
+    A = system_matrix(wl)
+    tol = 1e-10 if precision == 1 else 1e-8
+    z, phi, info = ctx.solve(torch.tensor(s, device=torch_dev()), tol=tol, precision=precision, method=METHOD_MINRES)
+    zz = z.cpu().numpy()
+    res = np.linalg.norm(s64 - A @ zz) / np.linalg.norm(s64)
+    _, kr = minres(lambda v: A @ v, s64, tol=tol)
+    say("minres", wl.name, "precision", precision, "iterations", info.iterations, "oracle", kr, "refinements",
+        info.refinements, "residual", res)
+    assert info.status == 0
+    assert res <= 1.01 * tol
+    assert abs(info.rel_residual - res) <= 1e-3 * tol
+    assert np.linalg.norm(zz - cholesky_solve(A, s64)) <= 1e-5 * np.linalg.norm(zz)
+    if precision == 1:
+        assert abs(info.iterations - kr) <= max(2, 0.05 * kr)
+    else:
+        assert info.iterations <= 1.5 * kr + 10 * info.refinements
+
+
+def test_minres_argument_errors():
+    import torch
+    from paper_1806_07938_amd import TTError
+    from paper_1806_07938_amd.tt import METHOD_MINRES, PRECOND_CIRCULANT, TT_INVALID_ARG
+    wl = W.c1()
+    ctx, k = make_system(wl, target=False)
+    s = torch.zeros(wl.n_slopes, dtype=torch.float32, device=torch_dev())
+    for kw in (dict(solver=1), dict(precision=2), dict(preconditioner=PRECOND_CIRCULANT)):
+        with pytest.raises(TTError) as e:
+            ctx.solve(s, method=METHOD_MINRES, **kw)
+        assert e.value.status == TT_INVALID_ARG
+    with pytest.raises(TTError) as e:
+        ctx.solve(s, method=9)
+    assert e.value.status == TT_INVALID_ARG
