@@ -153,11 +153,26 @@ def slope_covariance(wl):
     return S
 
 
-def system_matrix(wl, noise_var=None):
-    """A = W_s (Sigma_ss + Sigma_eta) W_s^T with Sigma_eta = sigma^2 I (§2.C, §2.F)."""
+def noise_covariance(wl, noise_var=None, noise_xy=None):
+    """Sigma_eta on the valid slopes (§2.C; §2.F elongated LGS spots): the
+    per-slope variances on the diagonal (a scalar sigma^2 or one per slope),
+    and with noise_xy (n_gs, n_vs) the x-y covariance of each subaperture in
+    each sensor, which makes Sigma_eta 2x2 block diagonal."""
     nv = wl.noise_var if noise_var is None else noise_var
-    S = slope_covariance(wl)
-    return S + nv * np.eye(S.shape[0])
+    N = wl.n_slopes
+    E = np.diag(np.broadcast_to(np.asarray(nv, dtype=np.float64), (N,)).copy())
+    if noise_xy is not None:
+        nvs = N // (2 * wl.n_gs)
+        for g in range(wl.n_gs):
+            for v in range(nvs):
+                i, j = 2 * g * nvs + v, (2 * g + 1) * nvs + v
+                E[i, j] = E[j, i] = noise_xy[g, v]
+    return E
+
+
+def system_matrix(wl, noise_var=None, noise_xy=None):
+    """A = W_s (Sigma_ss + Sigma_eta) W_s^T (§2.C, §2.F)."""
+    return slope_covariance(wl) + noise_covariance(wl, noise_var, noise_xy)
 
 
 def slope_covariance_rows(wl, rows):

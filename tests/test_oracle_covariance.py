@@ -199,3 +199,46 @@ def test_fried_has_an_invisible_waffle_mode():
             sx[a, b] = 0.5 * (pa - pb - pc + pd)
             sy[a, b] = 0.5 * (pa + pb - pc - pd)
     assert np.abs(sx).max() == 0 and np.abs(sy).max() == 0
+
+
+# --- elongated-spot noise (§2.F) ----------------------------------------------
+
+def test_noise_covariance_structure():
+    wl = W.tiny(n=4, n_gs=2, seed=3)
+    var, cxy = W.elongated_noise(wl)
+    E = C.noise_covariance(wl, var, cxy)
+    nvs = wl.n_slopes // (2 * wl.n_gs)
+    assert np.array_equal(E, E.T)
+    assert np.allclose(np.diag(E), var)
+    off = E - np.diag(np.diag(E))
+    for i, j in zip(*np.nonzero(off)):
+        # only the x and y slopes of one subaperture of one sensor are coupled
+        assert i // (2 * nvs) == j // (2 * nvs) and i % nvs == j % nvs and i != j
+    assert np.linalg.eigvalsh(E).min() > 0
+    assert np.array_equal(C.noise_covariance(wl, var, None), np.diag(var))
+
+
+def test_elongated_noise_principal_axes_radial():
+    wl = W.c1()
+    var, cxy = W.elongated_noise(wl)
+    n, d = wl.n, wl.d
+    idx = np.flatnonzero(wl.valid.ravel())
+    cx = (idx % n - (n - 1) / 2.0) * d
+    cy = (idx // n - (n - 1) / 2.0) * d
+    v = var.reshape(wl.n_gs, 2, -1)
+    for g in range(wl.n_gs):
+        for t in range(idx.size):
+            B = np.array([[v[g, 0, t], cxy[g, t]], [cxy[g, t], v[g, 1, t]]])
+            lam, U = np.linalg.eigh(B)
+            assert abs(lam[0] - wl.noise_var) <= 1e-12           # across the radial direction: sigma^2
+            radial = np.array([cx[t], cy[t]]) / np.hypot(cx[t], cy[t])
+            assert abs(abs(U[:, 1] @ radial) - 1.0) <= 1e-9       # the larger axis is radial
+
+
+def test_correlated_noise_sample_covariance():
+    wl = W.tiny(n=3, n_gs=1, seed=2, mask="full")
+    var, cxy = W.elongated_noise(wl, elongation=4.0)
+    E = C.noise_covariance(wl, var, cxy)
+    X = np.array([W.correlated_noise(var, cxy, seed=k) for k in range(20000)])
+    emp = X.T @ X / X.shape[0]
+    assert np.abs(emp - E).max() <= 0.05 * np.abs(E).max()

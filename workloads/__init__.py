@@ -235,3 +235,51 @@ def turbulent_slopes(wl: Workload, seed: int = SEED, frames: int = 1,
             v = v + math.sqrt(wl.noise_var) * rng.standard_normal(v.size)
         out[f] = v
     return out
+
+
+# ----------------------------------------------------------------------------
+# elongated-spot noise
+# ----------------------------------------------------------------------------
+def elongated_noise(wl: Workload, elongation: float = 3.0, seed: int = SEED):
+    """Slope noise of elongated LGS spots (§2.F): per valid subaperture a 2x2
+    x-y noise covariance with principal axes along and across the radial
+    direction from the pupil centre (laser launched on axis), variance
+    sigma^2 (1 + e (rho / R)^2) along it and sigma^2 across it, e = elongation
+    times a seeded per-sensor factor in [0.8, 1.2].  Returns (var, cov_xy):
+    var (n_slopes,) in the slope-vector layout, cov_xy (n_gs, n_vs)."""
+    rng = np.random.default_rng(seed)
+    n, d = wl.n, wl.d
+    idx = np.flatnonzero(wl.valid.ravel())
+    ii, jj = idx // n, idx % n
+    cx = (jj - (n - 1) / 2.0) * d
+    cy = (ii - (n - 1) / 2.0) * d
+    rho2 = (cx ** 2 + cy ** 2) / (wl.D / 2.0) ** 2
+    th = np.arctan2(cy, cx)
+    var = np.zeros((wl.n_gs, 2, idx.size))
+    cov = np.zeros((wl.n_gs, idx.size))
+    for g in range(wl.n_gs):
+        e = elongation * (0.8 + 0.4 * rng.random())
+        par = wl.noise_var * (1.0 + e * rho2)
+        per = np.full(idx.size, wl.noise_var)
+        c, s = np.cos(th), np.sin(th)
+        var[g, 0] = par * c * c + per * s * s
+        var[g, 1] = par * s * s + per * c * c
+        cov[g] = (par - per) * s * c
+    return var.reshape(-1), cov
+
+
+def correlated_noise(var: np.ndarray, cov_xy: np.ndarray, seed: int = SEED) -> np.ndarray:
+    """One seeded sample of slope noise with the given per-slope variances and
+    x-y covariances (same layouts as elongated_noise)."""
+    rng = np.random.default_rng(seed)
+    G, nv = cov_xy.shape
+    v = var.reshape(G, 2, nv)
+    # 2x2 Cholesky per subaperture
+    l11 = np.sqrt(v[:, 0])
+    l21 = cov_xy / l11
+    l22 = np.sqrt(v[:, 1] - l21 ** 2)
+    z = rng.standard_normal((2, G, nv))
+    out = np.zeros((G, 2, nv))
+    out[:, 0] = l11 * z[0]
+    out[:, 1] = l21 * z[0] + l22 * z[1]
+    return out.reshape(-1)
