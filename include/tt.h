@@ -214,6 +214,19 @@ tt_status tt_set_system(tt_ctx* ctx, const tt_kernels* k, const double* noise_va
                         double noise_scalar, const tt_target* target);
 tt_status tt_get_system_info(const tt_ctx* ctx, tt_system_info* out);
 
+/* Elongated LGS spots (§2.F): make Sigma_eta 2x2 block diagonal by giving the
+ * covariance of the x and y slope noise of every valid subaperture of every
+ * sensor.  cov_xy: host array of n_gs * n_vs doubles, index g * n_vs + v
+ * (v: valid subaperture in row-major order), copied; NULL removes the blocks.
+ * Every block [[var_x, cov], [cov, var_y]] (variances from tt_set_system) must
+ * be positive definite, else TT_INVALID_ARG and nothing changes.  Applies to
+ * every later product and solve of the context until the next tt_set_system
+ * (which removes the blocks).  The block-circulant preconditioner keeps using
+ * the mean variance.  Persistent solvers need a block's grid rows to fit its
+ * threads (as TT_PRECOND_CIRCULANT); TT_PRECOND_CIRCULANT with the blocks needs
+ * TT_PREC_F32.  Synchronous. */
+tt_status tt_set_noise_xy(tt_ctx* ctx, const double* cov_xy);
+
 /* y = W_s (Sigma_ss + Sigma_eta) W_s^T x, once, by the fused 2RBT product of
  * §2.E (rows a3-a7).  d_x, d_y: n_slopes elements; they must not overlap. */
 tt_status tt_matvec(tt_ctx* ctx, const float* d_x, float* d_y);

@@ -118,6 +118,7 @@ tt_status set_system_impl(tt_ctx* c, const tt_kernels* k, const double* noise_va
     c->proj.on = false;
     c->tile_S = 0;
     c->pc_ready = false;
+    c->has_nxy = false;
     c->n = k->n;
     c->G = k->n_gs;
     c->C = 2 * k->n_gs;
@@ -259,6 +260,32 @@ tt_status tt_kernels_copy(const tt_kernels* k, double* host_out, size_t count) {
 tt_status tt_set_system(tt_ctx* ctx, const tt_kernels* k, const double* noise_var, double noise_scalar,
                         const tt_target* target) {
     TT_GUARD(set_system_impl(ctx, k, noise_var, noise_scalar, target));
+}
+
+tt_status tt_set_noise_xy(tt_ctx* c, const double* cov_xy) {
+    TT_REQUIRE(c, "NULL context");
+    if (!c->ready) {
+        tt_set_error("tt_set_noise_xy: no system set");
+        return TT_NOT_READY;
+    }
+    TT_CHECK(use_device(c->device));
+    if (!cov_xy) {
+        c->has_nxy = false;
+        return TT_OK;
+    }
+    const size_t m = (size_t)c->G * c->n_vs;
+    for (size_t i = 0; i < m; ++i) {
+        const size_t g = i / c->n_vs, v = i % c->n_vs;
+        const double vx = c->host_noise[(2 * g) * c->n_vs + v], vy = c->host_noise[(2 * g + 1) * c->n_vs + v];
+        TT_REQUIRE(std::isfinite(cov_xy[i]) && vx > 0 && vy > 0 && cov_xy[i] * cov_xy[i] < vx * vy,
+                   "every 2x2 noise block must be positive definite");
+    }
+    std::vector<float> c32(cov_xy, cov_xy + m);
+    TT_CHECK(c->nxy64.upload(cov_xy, m, c->stream));
+    TT_CHECK(c->nxy32.upload(c32.data(), m, c->stream));
+    TT_HIP(hipStreamSynchronize(c->stream));
+    c->has_nxy = true;
+    return TT_OK;
 }
 
 tt_status tt_get_system_info(const tt_ctx* c, tt_system_info* out) {

@@ -14,7 +14,8 @@
 //             U[f2][p][a]  = sum_{f1<L} Y[p][f1] exp(+2 pi i f1 a / L), a < n  (F^-1 along y, S2 rows)
 //   row_inv : y_p[a][b]    = L^-2 sum_{f2} w(f2) Re(U[f2][p][a] exp(+2 pi i f2 b / L)),
 //             w = 1 for f2 = 0 and f2 = L/2, else 2 (real output)               (F^-1 along x, S2, W_s)
-//             out = y + sigma^2 x
+//             out = y + sigma^2 x (+ the x-y noise covariance times the other
+//             slope of the subaperture when Sigma_eta has 2x2 blocks, §2.F)
 //
 // Inputs are only nonzero on the n x n top-left corner of the L x L embedding
 // and only that corner of the output is read (pruned transforms).
@@ -125,8 +126,8 @@ __global__ void k_col_pass(const cplx<R>* __restrict__ T, const R* __restrict__ 
 
 template <typename R>
 __global__ void k_row_inv(const cplx<R>* __restrict__ U, const cplx<R>* __restrict__ tw, const int* __restrict__ vmap,
-                          const R* __restrict__ x, const R* __restrict__ noise, R* __restrict__ y,
-                          double* __restrict__ part, int n, int C, int L, int Lh, int n_vs) {
+                          const R* __restrict__ x, const R* __restrict__ noise, const R* __restrict__ nxy,
+                          R* __restrict__ y, double* __restrict__ part, int n, int C, int L, int Lh, int n_vs) {
     __shared__ cplx<R> Us[513];
     __shared__ cplx<R> tws[1024];
     __shared__ double red[256];
@@ -152,7 +153,9 @@ __global__ void k_row_inv(const cplx<R>* __restrict__ U, const cplx<R>* __restri
             if (m >= L) m -= L;
         }
         const long i = (long)c * n_vs + v;
-        const R out = s * inv + noise[i] * x[i];
+        R out = s * inv + noise[i] * x[i];
+        // 2x2 noise blocks: x-y covariance of this subaperture times the other slope
+        if (nxy) out += nxy[(long)(c >> 1) * n_vs + v] * x[(long)(c ^ 1) * n_vs + v];
         y[i] = out;
         acc_dot += (double)x[i] * (double)out;
     }
@@ -173,7 +176,7 @@ size_t col_pass_lds(const tt_ctx& c, size_t elem) { return elem * ((size_t)c.L +
 
 template <typename R>
 tt_status matvec_t(tt_ctx& c, const R* x, R* y, double* part, const R* M, const cplx<R>* tw, cplx<R>* T,
-                   cplx<R>* U, const R* noise) {
+                   cplx<R>* U, const R* noise, const R* nxy) {
     const int rows = c.C * c.n;
     hipLaunchKernelGGL(k_row_fwd<R>, dim3(rows), dim3(128), 0, c.stream, x, c.vmap.p, tw, T, c.n, c.C, c.L, c.Lh,
                        c.n_vs);
@@ -181,8 +184,8 @@ tt_status matvec_t(tt_ctx& c, const R* x, R* y, double* part, const R* M, const 
     const size_t lds = col_pass_lds(c, sizeof(cplx<R>));
     hipLaunchKernelGGL(k_col_pass<R>, dim3(c.Lh), dim3(256), lds, c.stream, T, M, tw, U, c.n, c.G, c.L, c.Lh);
     TT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_row_inv<R>, dim3(rows), dim3(128), 0, c.stream, U, tw, c.vmap.p, x, noise, y, part, c.n,
-                       c.C, c.L, c.Lh, c.n_vs);
+    hipLaunchKernelGGL(k_row_inv<R>, dim3(rows), dim3(128), 0, c.stream, U, tw, c.vmap.p, x, noise, nxy, y, part,
+                       c.n, c.C, c.L, c.Lh, c.n_vs);
     TT_HIP(hipGetLastError());
     return TT_OK;
 }
@@ -202,11 +205,13 @@ tt_status matvec_prepare(tt_ctx& c) {
 }
 
 tt_status matvec_f32(tt_ctx& c, const float* x, float* y, double* part) {
-    return matvec_t<float>(c, x, y, part, c.M32.p, c.tw32.p, c.T32.p, c.U32.p, c.noise32.p);
+    return matvec_t<float>(c, x, y, part, c.M32.p, c.tw32.p, c.T32.p, c.U32.p, c.noise32.p,
+                           c.has_nxy ? c.nxy32.p : nullptr);
 }
 
 tt_status matvec_f64(tt_ctx& c, const double* x, double* y, double* part) {
-    return matvec_t<double>(c, x, y, part, c.M64.p, c.tw64.p, c.T64.p, c.U64.p, c.noise64.p);
+    return matvec_t<double>(c, x, y, part, c.M64.p, c.tw64.p, c.T64.p, c.U64.p, c.noise64.p,
+                            c.has_nxy ? c.nxy64.p : nullptr);
 }
 
 // exported for the projection: forward row pass of float data with another padding

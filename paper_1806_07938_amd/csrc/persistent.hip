@@ -61,6 +61,7 @@ struct PArgs {
     const cplx<R>* Fb;       // [S][Lrm][n]  the same values, a fastest
     const cplx<R>* Gr;       // [Lh][n]      exp(+2 pi i f2 b / L)
     const R* noise;
+    const R* nxy;            // x-y noise covariance [g][v] (2x2 noise blocks, §2.F), or null
     R *x, *r, *p, *s;
     cplx<R>* T;              // [f2][c][a]
     cplx<R>* U;              // [f2][part][c][a]
@@ -202,7 +203,46 @@ struct Lane {
     long gi;   // slope index, or -1 (no point / invalid subaperture)
     R x, r, p, s, nz;
     R u;       // preconditioned residual P r (preconditioned solver)
+    R nxy;     // x-y noise covariance of this subaperture (0 without 2x2 noise blocks)
 };
+
+// Grid row index -> (channel c, subaperture row a): row = c n + a, or, with
+// 2x2 noise blocks (pair set), row = (g n + a) 2 + p with c = 2 g + p, so that
+// with an even number of rows per block both slopes of a subaperture are in
+// the same block.
+__device__ inline void row_ca(int row, int n, bool pair, int& c, int& ra) {
+    if (!pair) {
+        c = row / n;
+        ra = row - c * n;
+        return;
+    }
+    const int g = row / (2 * n), rem = row - g * 2 * n;
+    ra = rem >> 1;
+    c = 2 * g + (rem & 1);
+}
+
+// The same vector value of the other slope (x <-> y) of this lane's
+// subaperture, through a block exchange buffer: lanes (k, b) and (k ^ 1, b).
+template <typename R>
+__device__ inline R partner_value(R mine, int nrk, int n) {
+    __shared__ R xch[PT];
+    if ((int)threadIdx.x < nrk * n) xch[threadIdx.x] = mine;
+    __syncthreads();
+    R other = 0;
+    if ((int)threadIdx.x < nrk * n) {
+        const int k = threadIdx.x / n, b = threadIdx.x % n;
+        if ((k ^ 1) < nrk) other = xch[(k ^ 1) * n + b];
+    }
+    __syncthreads();
+    return other;
+}
+
+// x-y noise part of w.Sigma_eta w for this lane's value w: nxy w w_partner.
+template <typename R>
+__device__ inline double xy_noise_term(const Lane<R>& v, R w, int nrk, int n) {
+    const R wp = partner_value(v.gi >= 0 ? w : R(0), nrk, n);
+    return v.gi >= 0 ? (double)v.nxy * (double)w * (double)wp : 0.0;
+}
 
 // Us[k][f2] = sum over f1 ranges of the column-phase outputs of row k
 template <typename R>
@@ -211,7 +251,8 @@ __device__ void gather_u(const PArgs<R>& a, cplx<R>* Us, int base, int stride, i
     for (int i = threadIdx.x; i < nrk * Lh; i += PT) {
         const int k = i / Lh, f2 = i % Lh;
         const int row = base + k * stride;
-        const int c = row / n, ra = row % n;
+        int c, ra;
+        row_ca(row, n, a.nxy != nullptr, c, ra);
         const cplx<R>* u = a.U + ((long)f2 * S * C + c) * n + ra;
         // the first (up to) four ranges loaded together, then summed in order
         cplx<R> q[4];
@@ -267,7 +308,8 @@ __device__ void fwd_rows(const PArgs<R>& a, const cplx<R>* Gr, const R* xs, int 
     for (int i = threadIdx.x; i < nrk * Lh; i += PT) {
         const int k = i / Lh, f2 = i % Lh;
         const int row = base + k * stride;
-        const int c = row / n, ra = row % n;
+        int c, ra;
+        row_ca(row, n, a.nxy != nullptr, c, ra);
         const R* xr = xs + k * n;
         const cplx<R>* g = Gr + f2 * n;
         R r0 = 0, i0 = 0, r1 = 0, i1 = 0;
@@ -296,13 +338,16 @@ __device__ void row_phase_reg(const PArgs<R>& a, const Tiles<R>& t, Lane<R>& v, 
     R* xs = reinterpret_cast<R*>(Us + a.rbv * Lh);
     __syncthreads();
     double g = 0.0, sg = 0.0;
+    // 2x2 noise blocks: the other slope's residual for the noise term of A r
+    R rp = 0;
+    if (update && a.nxy) rp = partner_value(v.gi >= 0 ? v.r : R(0), nrk, n);
+    R rn = 0;
     if ((int)threadIdx.x < nrk * n) {
         const int k = threadIdx.x / n, b = threadIdx.x % n;
-        R rn = 0;
         if (v.gi >= 0) {
             if (update) {
                 const R inv = R(1) / (R(L) * R(L));
-                const R wv = inv_row(Us + k * Lh, t.Gr, n, b, L, Lh) * inv + v.nz * v.r;
+                const R wv = inv_row(Us + k * Lh, t.Gr, n, b, L, Lh) * inv + v.nz * v.r + v.nxy * rp;
                 v.p = v.r + beta * v.p;
                 v.s = wv + beta * v.s;
                 v.x += alpha * v.p;
@@ -315,6 +360,7 @@ __device__ void row_phase_reg(const PArgs<R>& a, const Tiles<R>& t, Lane<R>& v, 
         xs[k * n + b] = rn;
     }
     __syncthreads();
+    if (a.nxy) sg += xy_noise_term(v, rn, nrk, n);
     fwd_rows(a, t.Gr, xs, blockIdx.x * a.rbv, 1, nrk);
     const D3 tot = block_sum3(D3{g, sg, 0.0}, red);
     if (threadIdx.x == 0) {
@@ -344,12 +390,14 @@ __device__ void row_pc_update(const PArgs<R>& a, const Tiles<R>& t, Lane<R>& v, 
     R* xs = reinterpret_cast<R*>(Us + a.rbv * Lh);
     __syncthreads();
     double g = 0.0;
+    R up = 0;   // 2x2 noise blocks: the other slope's u
+    if (a.nxy) up = partner_value(v.u, nrk, n);
     if ((int)threadIdx.x < nrk * n) {
         const int k = threadIdx.x / n, b = threadIdx.x % n;
         R rn = 0;
         if (v.gi >= 0) {
             const R inv = R(1) / (R(L) * R(L));
-            const R wv = inv_row(Us + k * Lh, t.Gr, n, b, L, Lh) * inv + v.nz * v.u;
+            const R wv = inv_row(Us + k * Lh, t.Gr, n, b, L, Lh) * inv + v.nz * v.u + v.nxy * up;
             v.p = v.u + beta * v.p;
             v.s = wv + beta * v.s;
             v.x += alpha * v.p;
@@ -377,9 +425,9 @@ __device__ void row_pc_precond(const PArgs<R>& a, const Tiles<R>& t, Lane<R>& v,
     gather_u(a, Us, blockIdx.x * a.rbv, 1, nrk);
     __syncthreads();
     double sg = 0.0;
+    R un = 0;
     if ((int)threadIdx.x < nrk * n) {
         const int k = threadIdx.x / n, b = threadIdx.x % n;
-        R un = 0;
         if (v.gi >= 0) {
             const R inv = R(1) / (R(L) * R(L));
             un = inv_row(Us + k * Lh, t.Gr, n, b, L, Lh) * inv;
@@ -389,6 +437,7 @@ __device__ void row_pc_precond(const PArgs<R>& a, const Tiles<R>& t, Lane<R>& v,
         xs[k * n + b] = un;
     }
     __syncthreads();
+    if (a.nxy) sg += xy_noise_term(v, un, nrk, n);
     fwd_rows(a, t.Gr, xs, blockIdx.x * a.rbv, 1, nrk);
     const D3 tot = block_sum3(D3{sg, 0.0, 0.0}, red);
     if (threadIdx.x == 0) a.part[((long)par * a.nwg + blockIdx.x) * 4 + 1] = tot.a;
@@ -425,15 +474,17 @@ __device__ void row_mr(const PArgs<R>& a, const Tiles<R>& t, Lane<R>& v, int nrk
     R* xs = reinterpret_cast<R*>(Us + a.rbv * Lh);
     __syncthreads();
     double g = 0.0, sg = 0.0;
+    R qp = 0;   // 2x2 noise blocks: the other slope's q
+    if (a.nxy) qp = partner_value(v.gi >= 0 ? v.r : R(0), nrk, n);
+    R qn = 0;
     if ((int)threadIdx.x < nrk * n) {
         const int k = threadIdx.x / n, b = threadIdx.x % n;
-        R qn = 0;
         if (v.gi >= 0) {
             mr_update(v, qr, tau, delta2, eps, igamma2);
             const R ib = R(1) / beta;
             const R inv = R(1) / (R(L) * R(L));
             const R vj = v.r * ib;
-            const R avj = (inv_row(Us + k * Lh, t.Gr, n, b, L, Lh) * inv + v.nz * v.r) * ib;
+            const R avj = (inv_row(Us + k * Lh, t.Gr, n, b, L, Lh) * inv + v.nz * v.r + v.nxy * qp) * ib;
             qn = avj - alpha * vj - beta * v.p;
             v.p = vj;
             v.r = qn;
@@ -443,6 +494,7 @@ __device__ void row_mr(const PArgs<R>& a, const Tiles<R>& t, Lane<R>& v, int nrk
         xs[k * n + b] = qn;
     }
     __syncthreads();
+    if (a.nxy) sg += xy_noise_term(v, qn, nrk, n);
     fwd_rows(a, t.Gr, xs, blockIdx.x * a.rbv, 1, nrk);
     const D3 tot = block_sum3(D3{g, sg, 0.0}, red);
     if (threadIdx.x == 0) {
@@ -470,7 +522,8 @@ __device__ void row_phase_mem(const PArgs<R>& a, const Tiles<R>& t, bool update,
         for (int i = threadIdx.x; i < nrk * n; i += PT) {
             const int k = i / n, b = i % n;
             const int row = base + k * a.nwg;
-            const int c = row / n, ra = row % n;
+            int c, ra;
+            row_ca(row, n, a.nxy != nullptr, c, ra);
             const int vv = a.vmap[ra * n + b];
             R rn = 0;
             if (vv >= 0) {
@@ -828,6 +881,9 @@ template <typename R, bool RES, int MF, int KIND>
 __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
     constexpr bool PC = KIND == K_PCG;
     constexpr bool MR = KIND == K_MINRES;
+    // The FP64 preconditioned kernel is built without the 2x2 noise blocks (the
+    // present gfx950 compiler rejects that instantiation; the host refuses it).
+    if constexpr (PC && sizeof(R) == 8) a.nxy = nullptr;
     extern __shared__ __align__(16) char smem_raw[];
     __shared__ double red[3 * PT / 64];
     __shared__ int s_flag;
@@ -895,7 +951,7 @@ __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
         t.work = reinterpret_cast<cplx<R>*>(smem_raw);
     }
     // lanes of the register-resident CG vectors
-    Lane<R> v{-1, 0, 0, 0, 0, 0, 0};
+    Lane<R> v{-1, 0, 0, 0, 0, 0, 0, 0};
     int nrk = 0;
     if (a.vreg) {
         // a block owns the consecutive rows blockIdx.x * rbv + k, k < nrk
@@ -904,10 +960,12 @@ __global__ void __launch_bounds__(PT) k_cg_persistent(PArgs<R> a) {
         if ((int)threadIdx.x < nrk * n) {
             const int k = threadIdx.x / n, b = threadIdx.x % n;
             const int row = blockIdx.x * a.rbv + k;
-            const int c = row / n, ra = row % n;
+            int c, ra;
+            row_ca(row, n, a.nxy != nullptr, c, ra);
             const int vv = a.vmap[ra * n + b];
             if (vv >= 0) {
                 v.gi = (long)c * a.n_vs + vv;
+                if (a.nxy) v.nxy = a.nxy[(long)(c >> 1) * a.n_vs + vv];
                 v.x = a.x[v.gi];
                 v.r = a.r[v.gi];
                 v.p = a.p[v.gi];
@@ -1366,10 +1424,18 @@ tt_status solve_persistent_t(tt_ctx& c, const float* s, const double* x0, double
     const size_t lim = 160 * 1024 - 512;   // minus the static LDS (reduction scratch and flags)
     // rows per block: all of a block's rows at once when they fit the threads
     const int rows_per_block = (c.C * c.n + nwg - 1) / nwg;
-    const bool vreg = rows_per_block * c.n <= PT;
-    const int rbv = vreg ? rows_per_block : std::max(1, std::min(4, PT / std::max(c.n, 1)));
-    if (kind != K_CG && !vreg) {
-        tt_set_error("preconditioned CG / MINRES: a block's grid rows must fit its threads (n * ceil(2 n_gs n / CUs) <= 512)");
+    // with 2x2 noise blocks, rows per block rounded up to even: the x and y rows
+    // of a subaperture row stay together
+    const int rpb2 = c.has_nxy ? (rows_per_block + 1) / 2 * 2 : rows_per_block;
+    const bool vreg = rpb2 * c.n <= PT;
+    const int rbv = vreg ? rpb2 : std::max(1, std::min(4, PT / std::max(c.n, 1)));
+    if (kind == K_PCG && c.has_nxy && !f32) {
+        tt_set_error("2x2 noise blocks with the preconditioned solver need TT_PREC_F32");
+        return TT_INVALID_ARG;
+    }
+    if ((kind != K_CG || c.has_nxy) && !vreg) {
+        tt_set_error("preconditioned CG / MINRES / 2x2 noise blocks: a block's grid rows must fit its threads "
+                     "(n * ceil(2 n_gs n / CUs), rounded up to even, <= 512)");
         return TT_INVALID_ARG;
     }
     const bool res = lds_bytes<R>(c, Lrm, rbv, true, MF, pc) <= lim;
@@ -1415,6 +1481,7 @@ tt_status solve_persistent_t(tt_ctx& c, const float* s, const double* x0, double
     a.MTi = fs.MTi;
     a.TKi = fs.TKi;
     a.noise = noise;
+    a.nxy = c.has_nxy ? reinterpret_cast<const R*>(f32 ? (const void*)c.nxy32.p : (const void*)c.nxy64.p) : nullptr;
     a.x = x;
     a.r = r;
     a.p = p;

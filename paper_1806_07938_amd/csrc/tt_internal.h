@@ -136,6 +136,9 @@ struct tt_ctx {
     DevBuf<int> vidx;         // n_vs: flat index of valid subaperture v
     DevBuf<float> noise32;    // n_slopes
     DevBuf<double> noise64;
+    DevBuf<float> nxy32;      // x-y noise covariance per sensor and valid subaperture [g][v] (§2.F), if set
+    DevBuf<double> nxy64;
+    bool has_nxy = false;
     DevBuf<c32> tw32;         // L twiddles exp(-2 pi i k / L) as (cos, sin)
     DevBuf<c64> tw64;
 

@@ -29,7 +29,7 @@ MODEL_HUDGIN, MODEL_FRIED = 0, 1
 # Every function declared in include/tt.h.
 EXPORTED = (
     "tt_create", "tt_destroy", "tt_generate_kernels", "tt_kernels_destroy", "tt_kernels_copy",
-    "tt_set_system", "tt_get_system_info", "tt_matvec", "tt_matvec_f64", "tt_solve_frame",
+    "tt_set_system", "tt_set_noise_xy", "tt_get_system_info", "tt_matvec", "tt_matvec_f64", "tt_solve_frame",
     "tt_project", "tt_status_string", "tt_last_error",
 )
 
@@ -92,6 +92,7 @@ def load(path: str = LIB_PATH):
     lib.tt_kernels_copy.argtypes = [vp, C.POINTER(C.c_double), C.c_size_t]
     lib.tt_set_system.argtypes = [vp, vp, C.POINTER(C.c_double), C.c_double, C.POINTER(_Target)]
     lib.tt_get_system_info.argtypes = [vp, C.POINTER(_SystemInfo)]
+    lib.tt_set_noise_xy.argtypes = [vp, C.POINTER(C.c_double)]
     lib.tt_matvec.argtypes = [vp, vp, vp]
     lib.tt_matvec_f64.argtypes = [vp, vp, vp]
     lib.tt_solve_frame.argtypes = [vp, vp, vp, vp, vp, C.POINTER(_SolveOpts), C.POINTER(_SolveInfo)]
@@ -217,6 +218,16 @@ class Context:
             tgt = C.byref(_Target(float(target[0]), float(target[1]), int(n_prime), int(proj_pad_L)))
         _check(load().tt_set_system(self._h, kernels._h, nv, float(noise_scalar), tgt))
         self.info = self.system_info()
+
+    def set_noise_xy(self, cov_xy=None):
+        """2x2 noise blocks (elongated LGS spots): cov_xy (n_gs, n_vs) x-y noise
+        covariances, or None to remove them."""
+        p = None
+        if cov_xy is not None:
+            arr = np.ascontiguousarray(np.asarray(cov_xy, dtype=np.float64).reshape(-1))
+            self._keep_xy = arr
+            p = arr.ctypes.data_as(C.POINTER(C.c_double))
+        _check(load().tt_set_noise_xy(self._h, p))
 
     def system_info(self) -> dict:
         s = _SystemInfo()
