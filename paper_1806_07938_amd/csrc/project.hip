@@ -11,6 +11,9 @@
 //
 // Readings: n' = ceil(n / min_k s_k) + 1 by default; grids centred on the
 // direction; standard bilinear weights, nodes outside a grid contribute zero.
+// With natural guide stars (s_k = 1 for every layer) the layer spectra are
+// summed at set-up: one inverse transform and one interpolation in all (the
+// NGS phase-slope product of §2.E).
 #include "tt_internal.h"
 #include "vk_math.h"
 
@@ -28,6 +31,24 @@ __global__ void k_pack_proj(const c64* __restrict__ S, c32* __restrict__ spec, i
     const int f2 = (int)(f / L), f1 = (int)(f % L);
     const c64 v = S[((long)tab * Lh + f2) * L + f1];
     spec[i] = c32{(float)v.x, (float)v.y};
+}
+
+// Natural guide stars: every layer uses the same grid and interpolation, so the
+// per-layer spectra are summed over layers (the NGS phase-slope product of
+// §2.E: one inverse transform instead of one per layer).
+__global__ void k_pack_proj_sum(const c64* __restrict__ S, c32* __restrict__ spec, int K, int C, int L, int Lh) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;   // i = f * C + q, f = f2 * L + f1
+    if (i >= (long)L * Lh * C) return;
+    const int q = (int)(i % C);
+    const long f = i / C;
+    const int f2 = (int)(f / L), f1 = (int)(f % L);
+    double re = 0.0, im = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const c64 v = S[(((long)k * C + q) * Lh + f2) * L + f1];
+        re += v.x;
+        im += v.y;
+    }
+    spec[i] = c32{(float)re, (float)im};
 }
 
 __global__ void k_d2f(const double* __restrict__ a, float* __restrict__ b, long n) {
@@ -155,6 +176,8 @@ tt_status projection_setup(tt_ctx& c, const tt_target* t) {
     TT_REQUIRE(std::isfinite(t->beta_x) && std::isfinite(t->beta_y), "non-finite target direction");
     double smin = 1.0;
     std::vector<double> sk(c.n_layer, 1.0);
+    // natural guide stars: all layers share one grid; their spectra are summed
+    const bool ngs_sum = !c.lgs;
     if (c.lgs)
         for (int k = 0; k < c.n_layer; ++k) {
             sk[k] = 1.0 - c.h[k] / c.h_lgs;
@@ -170,7 +193,7 @@ tt_status projection_setup(tt_ctx& c, const tt_target* t) {
     }
     TT_REQUIRE(L >= np + c.n - 1 && L <= 1024, "projection pad_L must be in [n'+n-1, 1024]");
     TT_REQUIRE(L / 2 + 1 <= 513 && c.n <= 512, "projection too large");
-    const size_t lds = proj_col_lds(L, c.C, c.n, c.n_layer);
+    const size_t lds = proj_col_lds(L, c.C, c.n, ngs_sum ? 1 : c.n_layer);
     if (lds > 160 * 1024) {
         tt_set_error("projection needs " + std::to_string(lds) + " bytes of LDS per column (> 160 KiB)");
         return TT_INVALID_ARG;
@@ -180,7 +203,7 @@ tt_status projection_setup(tt_ctx& c, const tt_target* t) {
     P.np = np;
     P.Lp = L;
     P.Lph = L / 2 + 1;
-    P.n_layer = c.n_layer;
+    P.n_layer = ngs_sum ? 1 : c.n_layer;
     const int K = c.n_layer, C = c.C;
     const int m = np + c.n - 1;
     // phase-slope tables (FP64) and their spectra
@@ -190,9 +213,14 @@ tt_status projection_setup(tt_ctx& c, const tt_target* t) {
     DevBuf<c64> S;
     TT_CHECK(table_spectra(tab.p, (long)K * C, m, np - 1, L, S, c.stream));
     tab.release();
-    const long nspec = (long)L * P.Lph * K * C;
+    const long nspec = (long)L * P.Lph * P.n_layer * C;
     TT_CHECK(P.spec.alloc(nspec));
-    hipLaunchKernelGGL(k_pack_proj, dim3(cdiv(nspec, 256)), dim3(256), 0, c.stream, S.p, P.spec.p, K * C, L, P.Lph);
+    if (ngs_sum)
+        hipLaunchKernelGGL(k_pack_proj_sum, dim3(cdiv(nspec, 256)), dim3(256), 0, c.stream, S.p, P.spec.p, K, C, L,
+                           P.Lph);
+    else
+        hipLaunchKernelGGL(k_pack_proj, dim3(cdiv(nspec, 256)), dim3(256), 0, c.stream, S.p, P.spec.p, K * C, L,
+                           P.Lph);
     TT_HIP(hipGetLastError());
     TT_HIP(hipStreamSynchronize(c.stream));
     S.release();
@@ -212,9 +240,10 @@ tt_status projection_setup(tt_ctx& c, const tt_target* t) {
     P.n_vphi = (int)vphi.size();
     TT_CHECK(P.vphi.upload(vphi.data(), vphi.size(), c.stream));
     TT_CHECK(c.proj.T.alloc((size_t)P.Lph * C * n));
-    TT_CHECK(c.proj.Xw.alloc((size_t)P.Lph * K * np));
-    TT_CHECK(c.proj.layer_out.alloc((size_t)K * np * np));
+    TT_CHECK(c.proj.Xw.alloc((size_t)P.Lph * P.n_layer * np));
+    TT_CHECK(c.proj.layer_out.alloc((size_t)P.n_layer * np * np));
     TT_CHECK(build_twiddles(L, P.twp, nullptr, c.stream));
+    if (ngs_sum) sk.assign(1, 1.0);
     TT_CHECK(P.sk.upload(sk.data(), sk.size(), c.stream));
     TT_CHECK(P.z32.alloc(c.n_slopes));
     TT_HIP(hipFuncSetAttribute((const void*)k_proj_col, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));

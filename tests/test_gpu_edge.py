@@ -215,3 +215,23 @@ def test_two_systems_and_repeated_solves():
         z2, _, _ = ctx.solve(torch.tensor(s, device=dev), tol=1e-9)
         assert np.linalg.norm(z1.cpu().numpy() - zref) / np.linalg.norm(zref) < 1e-5
         assert np.array_equal(z1.cpu().numpy(), z2.cpu().numpy())
+
+
+@pytest.mark.parametrize("n_prime", [0, 13])
+def test_ngs_projection_layers_summed(n_prime):
+    # natural guide stars: the library sums the layer spectra (one inverse
+    # transform); the oracle keeps one product per layer.  Default grid
+    # (n' = n + 1, identity interpolation) and a larger grid (interpolated).
+    import torch
+    from oracle.projection import phi_exact, phi_paper_dense
+    wl = W.tiny(n=6, n_gs=3, lgs=False, n_layer=4, seed=9, pad_L=11)
+    wl.target = (4 * W.ARCSEC, 2 * W.ARCSEC)
+    ctx, k = make_system(wl, target=True, n_prime=n_prime)
+    z = np.random.default_rng(7).standard_normal(wl.n_slopes)
+    phi = ctx.project(torch.tensor(z, device=torch_dev())).cpu().numpy()
+    z32 = z.astype(np.float32).astype(np.float64)
+    ref = phi_paper_dense(wl, z32, n_prime=(n_prime or None))
+    say("ngs projection n'", ctx.info["n_prime"], "difference", np.linalg.norm(phi - ref) / np.linalg.norm(ref))
+    assert np.linalg.norm(phi - ref) / np.linalg.norm(ref) < 1e-5
+    if n_prime == 0:
+        assert np.linalg.norm(ref - phi_exact(wl, z32)) / np.linalg.norm(ref) < 1e-10
