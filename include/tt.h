@@ -227,6 +227,18 @@ tt_status tt_get_system_info(const tt_ctx* ctx, tt_system_info* out);
  * TT_PREC_F32.  Synchronous. */
 tt_status tt_set_noise_xy(tt_ctx* ctx, const double* cov_xy);
 
+/* Low-order mode removal (§2.F "Mode removal"): with on != 0 the products and
+ * solves use M_s W_s in place of W_s, M_s = block diagonal of the per-sensor
+ * projectors I - Z Z^+ removing tip, tilt and focus (Hudgin slopes of the
+ * phase modes x, y, x^2 + y^2 on the valid subapertures), i.e. the system
+ * (M_s W_s)(Sigma_ss + Sigma_eta)(M_s W_s)^T zeta = M_s s with zeta in the
+ * range of M_s (rel_residual is relative to ||M_s s||), and the projection
+ * applies M_phi (the same modes at the valid phase points) to
+ * W_phi Sigma_phi_s M_s zeta.  tt_matvec / tt_matvec_f64 then apply
+ * M_s A M_s.  Solves need TT_SOLVER_KERNELS.  Cleared by tt_set_system;
+ * on = 0 removes it.  Synchronous. */
+tt_status tt_set_mode_removal(tt_ctx* ctx, int on);
+
 /* y = W_s (Sigma_ss + Sigma_eta) W_s^T x, once, by the fused 2RBT product of
  * §2.E (rows a3-a7).  d_x, d_y: n_slopes elements; they must not overlap. */
 tt_status tt_matvec(tt_ctx* ctx, const float* d_x, float* d_y);

@@ -119,6 +119,7 @@ tt_status set_system_impl(tt_ctx* c, const tt_kernels* k, const double* noise_va
     c->tile_S = 0;
     c->pc_ready = false;
     c->has_nxy = false;
+    c->modes = false;
     c->n = k->n;
     c->G = k->n_gs;
     c->C = 2 * k->n_gs;
@@ -208,12 +209,21 @@ tt_status solve_impl(tt_ctx* c, const float* s, const double* x0, double* zeta, 
                    (o.solver == TT_SOLVER_PERSISTENT && o.preconditioner == TT_PRECOND_NONE &&
                     (o.precision == TT_PREC_F32 || o.precision == TT_PREC_F64)),
                "TT_METHOD_MINRES needs TT_SOLVER_PERSISTENT, TT_PREC_F32 or TT_PREC_F64 and no preconditioner");
+    TT_REQUIRE(!c->modes || o.solver == TT_SOLVER_KERNELS, "mode removal needs TT_SOLVER_KERNELS");
     TT_CHECK(use_device(c->device));
     tt_solve_info inf{};
+
     if (o.solver == TT_SOLVER_PERSISTENT)
         TT_CHECK(solve_persistent(*c, s, x0, zeta, o, inf));
     else
         TT_CHECK(solve_kernels(*c, s, x0, zeta, o, inf));
+    // mode removal: (M_s W_s)(Sigma_ss + Sigma_eta)(M_s W_s)^T zeta = M_s s with the
+    // product projected on both sides (matvec.hip) and every residual projected
+    // (cg.hip); the solution is projected at the end
+    if (c->modes) {
+        TT_CHECK(modes_project_f64(*c, zeta));
+        TT_HIP(hipStreamSynchronize(c->stream));
+    }
     if (phi) {
         TT_CHECK(projection_apply(*c, zeta, phi));
         TT_HIP(hipStreamSynchronize(c->stream));
@@ -285,6 +295,24 @@ tt_status tt_set_noise_xy(tt_ctx* c, const double* cov_xy) {
     TT_CHECK(c->nxy32.upload(c32.data(), m, c->stream));
     TT_HIP(hipStreamSynchronize(c->stream));
     c->has_nxy = true;
+    return TT_OK;
+}
+
+tt_status tt_set_mode_removal(tt_ctx* c, int on) {
+    TT_REQUIRE(c, "NULL context");
+    if (!c->ready) {
+        tt_set_error("tt_set_mode_removal: no system set");
+        return TT_NOT_READY;
+    }
+    TT_CHECK(use_device(c->device));
+    if (!on) {
+        c->modes = false;
+        return TT_OK;
+    }
+    TT_CHECK(modes_setup(*c));
+    TT_CHECK(c->mtmp32.alloc(c->n_slopes));
+    TT_CHECK(c->mtmp64.alloc(c->n_slopes));
+    c->modes = true;
     return TT_OK;
 }
 

@@ -197,6 +197,8 @@ tt_status true_residual(tt_ctx& c, const float* s, CgScalars* S) {
     const long n = c.n_slopes;
     TT_CHECK(matvec_f64(c, c.x64.p, c.aux64.p, nullptr));
     hipLaunchKernelGGL(k_resid, dim3(vec_blocks(n)), dim3(NT), 0, c.stream, s, c.aux64.p, c.r64.p, n);
+    // mode removal: the residual of the mode-removed system is M (s - M A M x)
+    if (c.modes) TT_CHECK(modes_project_f64(c, c.r64.p));
     hipLaunchKernelGGL((k_dot_partial<double, double>), dim3(vec_blocks(n)), dim3(NT), 0, c.stream, c.r64.p,
                        c.r64.p, n, c.part.p);
     hipLaunchKernelGGL(k_set_true, dim3(1), dim3(NT), 0, c.stream, c.part.p, (int)vec_blocks(n), S);
@@ -232,7 +234,15 @@ tt_status cg_setup(tt_ctx& c, const float* s, const double* x0, const tt_solve_o
     const unsigned nb = vec_blocks(n);
     double* part_s = c.part.p;
     double* part_r = c.part.p + 1024;
-    hipLaunchKernelGGL((k_dot_partial<float, float>), dim3(nb), dim3(NT), 0, c.stream, s, s, n, part_s);
+    if (c.modes) {
+        // ||M s||^2 in FP64 (the norm of the mode-removed right-hand side)
+        hipLaunchKernelGGL(k_copy_f2d, dim3(nb), dim3(NT), 0, c.stream, s, c.aux64.p, n);
+        TT_CHECK(modes_project_f64(c, c.aux64.p));
+        hipLaunchKernelGGL((k_dot_partial<double, double>), dim3(nb), dim3(NT), 0, c.stream, c.aux64.p, c.aux64.p,
+                           n, part_s);
+    } else {
+        hipLaunchKernelGGL((k_dot_partial<float, float>), dim3(nb), dim3(NT), 0, c.stream, s, s, n, part_s);
+    }
     if (x0) {
         hipLaunchKernelGGL(k_copy<double>, dim3(nb), dim3(NT), 0, c.stream, x0, c.x64.p, n);
         TT_CHECK(matvec_f64(c, c.x64.p, c.aux64.p, nullptr));
@@ -241,6 +251,7 @@ tt_status cg_setup(tt_ctx& c, const float* s, const double* x0, const tt_solve_o
         hipLaunchKernelGGL(k_fill<double>, dim3(nb), dim3(NT), 0, c.stream, c.x64.p, 0.0, n);
         hipLaunchKernelGGL(k_copy_f2d, dim3(nb), dim3(NT), 0, c.stream, s, c.r64.p, n);
     }
+    if (c.modes) TT_CHECK(modes_project_f64(c, c.r64.p));   // residual in the range of M
     hipLaunchKernelGGL((k_dot_partial<double, double>), dim3(nb), dim3(NT), 0, c.stream, c.r64.p, c.r64.p, n,
                        part_r);
     const double drop = f32 ? (o.refine_drop > 0 ? o.refine_drop : 1e-3) : 0.0;

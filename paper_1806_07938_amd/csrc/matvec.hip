@@ -175,9 +175,26 @@ namespace {
 size_t col_pass_lds(const tt_ctx& c, size_t elem) { return elem * ((size_t)c.L + (size_t)c.C * c.n + 2ull * c.C * c.L); }
 
 template <typename R>
+__global__ void k_copy_vec(const R* __restrict__ a, R* __restrict__ b, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) b[i] = a[i];
+}
+
+tt_status mode_project(tt_ctx& c, float* v) { return modes_project_f32(c, v); }
+tt_status mode_project(tt_ctx& c, double* v) { return modes_project_f64(c, v); }
+
+// With mode removal (§2.F) the product is M A M x: the input is projected into
+// tmp first (the partial dot products are then (M x).A(M x) = x.(M A M x)) and
+// the output after.
+template <typename R>
 tt_status matvec_t(tt_ctx& c, const R* x, R* y, double* part, const R* M, const cplx<R>* tw, cplx<R>* T,
-                   cplx<R>* U, const R* noise, const R* nxy) {
+                   cplx<R>* U, const R* noise, const R* nxy, R* tmp) {
     const int rows = c.C * c.n;
+    if (c.modes) {
+        hipLaunchKernelGGL(k_copy_vec<R>, dim3(cdiv(c.n_slopes, 256)), dim3(256), 0, c.stream, x, tmp,
+                           (long)c.n_slopes);
+        TT_CHECK(mode_project(c, tmp));
+        x = tmp;
+    }
     hipLaunchKernelGGL(k_row_fwd<R>, dim3(rows), dim3(128), 0, c.stream, x, c.vmap.p, tw, T, c.n, c.C, c.L, c.Lh,
                        c.n_vs);
     TT_HIP(hipGetLastError());
@@ -187,6 +204,7 @@ tt_status matvec_t(tt_ctx& c, const R* x, R* y, double* part, const R* M, const 
     hipLaunchKernelGGL(k_row_inv<R>, dim3(rows), dim3(128), 0, c.stream, U, tw, c.vmap.p, x, noise, nxy, y, part,
                        c.n, c.C, c.L, c.Lh, c.n_vs);
     TT_HIP(hipGetLastError());
+    if (c.modes) TT_CHECK(mode_project(c, y));
     return TT_OK;
 }
 
@@ -206,12 +224,12 @@ tt_status matvec_prepare(tt_ctx& c) {
 
 tt_status matvec_f32(tt_ctx& c, const float* x, float* y, double* part) {
     return matvec_t<float>(c, x, y, part, c.M32.p, c.tw32.p, c.T32.p, c.U32.p, c.noise32.p,
-                           c.has_nxy ? c.nxy32.p : nullptr);
+                           c.has_nxy ? c.nxy32.p : nullptr, c.mtmp32.p);
 }
 
 tt_status matvec_f64(tt_ctx& c, const double* x, double* y, double* part) {
     return matvec_t<double>(c, x, y, part, c.M64.p, c.tw64.p, c.T64.p, c.U64.p, c.noise64.p,
-                            c.has_nxy ? c.nxy64.p : nullptr);
+                            c.has_nxy ? c.nxy64.p : nullptr, c.mtmp64.p);
 }
 
 // exported for the projection: forward row pass of float data with another padding

@@ -258,6 +258,7 @@ tt_status projection_apply(tt_ctx& c, const double* zeta, float* phi) {
     hipLaunchKernelGGL(k_d2f, dim3(cdiv(c.n_slopes, 256)), dim3(256), 0, c.stream, zeta, P.z32.p,
                        (long)c.n_slopes);
     TT_HIP(hipGetLastError());
+    if (c.modes) TT_CHECK(modes_project_f32(c, P.z32.p));   // zeta_MW = M_s zeta_W (§2.F)
     TT_CHECK(row_fwd_f32(P.z32.p, c.vmap.p, P.twp.p, P.T.p, n, C, P.Lp, c.n_vs, c.stream));
     const size_t lds = proj_col_lds(P.Lp, C, n, K);
     hipLaunchKernelGGL(k_proj_col, dim3(P.Lph), dim3(256), lds, c.stream, P.T.p, P.spec.p, P.twp.p, P.Xw.p, n, C, K,
@@ -269,5 +270,6 @@ tt_status projection_apply(tt_ctx& c, const double* zeta, float* phi) {
     hipLaunchKernelGGL(k_interp, dim3(cdiv(P.n_vphi, 128)), dim3(128), 0, c.stream, P.layer_out.p, P.vphi.p,
                        P.sk.p, phi, P.n_vphi, n, P.np, K, c.d);
     TT_HIP(hipGetLastError());
+    if (c.modes) TT_CHECK(modes_project_phase(c, phi));      // M_phi (§2.F)
     return TT_OK;
 }

@@ -139,6 +139,13 @@ struct tt_ctx {
     DevBuf<float> nxy32;      // x-y noise covariance per sensor and valid subaperture [g][v] (§2.F), if set
     DevBuf<double> nxy64;
     bool has_nxy = false;
+    bool modes = false;       // tip/tilt/focus removal (§2.F), see modes.hip
+    DevBuf<float> mode_pos;   // (x, y) of the valid subapertures, units of d
+    std::vector<double> mode_ginv;         // (Z^T Z)^-1 of one sensor's slope modes
+    DevBuf<float> mode_phase_pos;          // (x, y) of the valid phase points
+    std::vector<double> mode_phase_ginv;   // (Z^T Z)^-1 of the phase modes (empty: no target)
+    DevBuf<float> mtmp32;     // projected input of the product with mode removal
+    DevBuf<double> mtmp64;
     DevBuf<c32> tw32;         // L twiddles exp(-2 pi i k / L) as (cos, sin)
     DevBuf<c64> tw64;
 
@@ -200,6 +207,12 @@ tt_status solve_persistent(tt_ctx& c, const float* s, const double* x0, double* 
 // precond.hip
 tt_status precond_build(tt_ctx& c);   // Minv32 / Minv64 of the current system (once per system)
 double precond_noise(const tt_ctx& c);
+
+// modes.hip
+tt_status modes_setup(tt_ctx& c);
+tt_status modes_project_f32(tt_ctx& c, float* v);
+tt_status modes_project_f64(tt_ctx& c, double* v);
+tt_status modes_project_phase(tt_ctx& c, float* phi);
 
 // project.hip
 tt_status projection_setup(tt_ctx& c, const tt_target* t);

@@ -29,7 +29,7 @@ MODEL_HUDGIN, MODEL_FRIED = 0, 1
 # Every function declared in include/tt.h.
 EXPORTED = (
     "tt_create", "tt_destroy", "tt_generate_kernels", "tt_kernels_destroy", "tt_kernels_copy",
-    "tt_set_system", "tt_set_noise_xy", "tt_get_system_info", "tt_matvec", "tt_matvec_f64", "tt_solve_frame",
+    "tt_set_system", "tt_set_noise_xy", "tt_set_mode_removal", "tt_get_system_info", "tt_matvec", "tt_matvec_f64", "tt_solve_frame",
     "tt_project", "tt_status_string", "tt_last_error",
 )
 
@@ -93,6 +93,7 @@ def load(path: str = LIB_PATH):
     lib.tt_set_system.argtypes = [vp, vp, C.POINTER(C.c_double), C.c_double, C.POINTER(_Target)]
     lib.tt_get_system_info.argtypes = [vp, C.POINTER(_SystemInfo)]
     lib.tt_set_noise_xy.argtypes = [vp, C.POINTER(C.c_double)]
+    lib.tt_set_mode_removal.argtypes = [vp, C.c_int]
     lib.tt_matvec.argtypes = [vp, vp, vp]
     lib.tt_matvec_f64.argtypes = [vp, vp, vp]
     lib.tt_solve_frame.argtypes = [vp, vp, vp, vp, vp, C.POINTER(_SolveOpts), C.POINTER(_SolveInfo)]
@@ -228,6 +229,10 @@ class Context:
             self._keep_xy = arr
             p = arr.ctypes.data_as(C.POINTER(C.c_double))
         _check(load().tt_set_noise_xy(self._h, p))
+
+    def set_mode_removal(self, on: bool = True):
+        """Tip/tilt/focus removal M_s (and M_phi on the projection), §2.F."""
+        _check(load().tt_set_mode_removal(self._h, 1 if on else 0))
 
     def system_info(self) -> dict:
         s = _SystemInfo()
