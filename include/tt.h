@@ -256,6 +256,18 @@ tt_status tt_solve_frame(tt_ctx* ctx, const float* d_s, const double* d_x0,
                          double* d_zeta, float* d_phi, const tt_solve_opts* opts,
                          tt_solve_info* info);
 
+/* A batch of frames, each on its own configured context (systems may differ
+ * in size and geometry; contexts must not repeat).  For i < count, frame i is
+ * tt_solve_frame(systems[i], d_s[i], d_x0 ? d_x0[i] : NULL, d_zeta[i],
+ * d_phi ? d_phi[i] : NULL, opts, infos ? &infos[i] : NULL), in order, one
+ * after another (each solve occupies the whole device).  Returns TT_OK when
+ * every frame did, else the first non-OK status in the order TT_BREAKDOWN,
+ * TT_NOT_CONVERGED (all frames are still attempted and infos filled), or the
+ * first argument / runtime error (later frames are then not attempted). */
+tt_status tt_solve_batch(tt_ctx* const* systems, int count, const float* const* d_s,
+                         const double* const* d_x0, double* const* d_zeta, float* const* d_phi,
+                         const tt_solve_opts* opts, tt_solve_info* infos);
+
 /* phi = W_phi sum_k I'_k S2 F^-1 { sum_q Xi'~_{q,k} . F[S1 zeta_q] } (row a9,
  * §2.E LGS phase-slope equation with a common n').  d_zeta: n_slopes doubles
  * (rounded to FP32 for the products), d_phi: n_vphi floats.  Requires a target. */

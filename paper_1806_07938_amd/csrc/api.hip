@@ -236,6 +236,23 @@ tt_status solve_impl(tt_ctx* c, const float* s, const double* x0, double* zeta, 
 
 void tt_set_error(const std::string& msg) { g_last_error = msg; }
 
+static tt_status batch_impl(tt_ctx* const* systems, int count, const float* const* d_s, const double* const* d_x0,
+                         double* const* d_zeta, float* const* d_phi, const tt_solve_opts* opts, tt_solve_info* infos) {
+    TT_REQUIRE(count >= 0, "count must be >= 0");
+    TT_REQUIRE(count == 0 || (systems && d_s && d_zeta), "NULL argument");
+    for (int i = 0; i < count; ++i)
+        for (int j = 0; j < i; ++j) TT_REQUIRE(systems[i] != systems[j], "a context appears twice in the batch");
+    bool breakdown = false, notconv = false;
+    for (int i = 0; i < count; ++i) {
+        const tt_status st = solve_impl(systems[i], d_s[i], d_x0 ? d_x0[i] : nullptr, d_zeta[i],
+                                        d_phi ? d_phi[i] : nullptr, opts, infos ? &infos[i] : nullptr);
+        if (st == TT_BREAKDOWN) breakdown = true;
+        else if (st == TT_NOT_CONVERGED) notconv = true;
+        else if (st != TT_OK) return st;
+    }
+    return breakdown ? TT_BREAKDOWN : notconv ? TT_NOT_CONVERGED : TT_OK;
+}
+
 extern "C" {
 
 tt_status tt_create(tt_ctx** out, int device, void* stream) { TT_GUARD(create_impl(out, device, stream)); }
@@ -364,6 +381,11 @@ tt_status tt_matvec_f64(tt_ctx* c, const double* d_x, double* d_y) {
 tt_status tt_solve_frame(tt_ctx* ctx, const float* d_s, const double* d_x0, double* d_zeta, float* d_phi,
                          const tt_solve_opts* opts, tt_solve_info* info) {
     TT_GUARD(solve_impl(ctx, d_s, d_x0, d_zeta, d_phi, opts, info));
+}
+
+tt_status tt_solve_batch(tt_ctx* const* systems, int count, const float* const* d_s, const double* const* d_x0,
+                         double* const* d_zeta, float* const* d_phi, const tt_solve_opts* opts, tt_solve_info* infos) {
+    TT_GUARD(batch_impl(systems, count, d_s, d_x0, d_zeta, d_phi, opts, infos));
 }
 
 tt_status tt_project(tt_ctx* c, const double* d_zeta, float* d_phi) {

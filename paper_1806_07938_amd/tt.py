@@ -30,7 +30,7 @@ MODEL_HUDGIN, MODEL_FRIED = 0, 1
 EXPORTED = (
     "tt_create", "tt_destroy", "tt_generate_kernels", "tt_kernels_destroy", "tt_kernels_copy",
     "tt_set_system", "tt_set_noise_xy", "tt_set_mode_removal", "tt_get_system_info", "tt_matvec", "tt_matvec_f64", "tt_solve_frame",
-    "tt_project", "tt_status_string", "tt_last_error",
+    "tt_solve_batch", "tt_project", "tt_status_string", "tt_last_error",
 )
 
 
@@ -98,6 +98,8 @@ def load(path: str = LIB_PATH):
     lib.tt_matvec_f64.argtypes = [vp, vp, vp]
     lib.tt_solve_frame.argtypes = [vp, vp, vp, vp, vp, C.POINTER(_SolveOpts), C.POINTER(_SolveInfo)]
     lib.tt_project.argtypes = [vp, vp, vp]
+    lib.tt_solve_batch.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                                   C.POINTER(vp), C.POINTER(_SolveOpts), C.POINTER(_SolveInfo)]
     lib.tt_status_string.argtypes = [C.c_int]
     lib.tt_status_string.restype = C.c_char_p
     lib.tt_last_error.argtypes = []
@@ -312,3 +314,38 @@ def system_from(ctx: Context, wl, target: bool = True, pad_L: Optional[int] = No
     ctx.set_system(k, noise_scalar=wl.noise_var, target=(tuple(wl.target) if target else None),
                    n_prime=n_prime, proj_pad_L=proj_pad_L)
     return k
+
+
+def solve_batch(contexts, slopes, tol: float = 1e-6, max_iter: int = 20000, precision: int = PREC_F32,
+                solver: int = SOLVER_PERSISTENT, refine_drop: float = 1e-3, preconditioner: int = PRECOND_NONE,
+                method: int = METHOD_CG, allow=(TT_OK,)):
+    """tt_solve_batch: frame i (device float32 slopes) on contexts[i]; returns
+    (zetas, phis, infos, status).  phis[i] is None without a target."""
+    import torch
+    m = len(contexts)
+    assert len(slopes) == m
+    zetas, phis, sp, zp, pp = [], [], [], [], []
+    for ctx, s in zip(contexts, slopes):
+        n = ctx.info["n_slopes"]
+        z = torch.empty(n, dtype=torch.float64, device=s.device)
+        zetas.append(z)
+        sp.append(_dptr(s, torch.float32, n))
+        zp.append(_dptr(z, torch.float64, n))
+        if ctx.info["n_vphi"] > 0:
+            ph = torch.empty(ctx.info["n_vphi"], dtype=torch.float32, device=s.device)
+            phis.append(ph)
+            pp.append(_dptr(ph, torch.float32, ctx.info["n_vphi"]))
+        else:
+            phis.append(None)
+            pp.append(None)
+    arr = C.c_void_p * max(m, 1)
+    hs = arr(*[c._h for c in contexts])
+    opts = _SolveOpts(float(tol), int(max_iter), int(precision), int(solver), float(refine_drop),
+                      int(preconditioner), int(method))
+    infos = (_SolveInfo * max(m, 1))()
+    use_phi = all(p is not None for p in pp) and m > 0
+    st = load().tt_solve_batch(hs, m, arr(*sp), None, arr(*zp), arr(*pp) if use_phi else None, C.byref(opts), infos)
+    _check(st, allow=allow)
+    out = [SolveInfo(i.iterations, i.refinements, i.status, i.rel_residual, i.recursive_residual, i.kernel_ms,
+                     i.kernel_launches) for i in list(infos)[:m]]
+    return zetas, (phis if use_phi else [None] * m), out, st
