@@ -58,7 +58,7 @@ def traffic_record(pc):
     """HBM traffic of the persistent kernel measured with rocprofv3 counters
     (profiles/*_traffic.md), valid only while the kernel source is unchanged."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"k_cg_persistent_{'pcg' if pc else 'cg'}_f32_c2_L148_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"k_cg_persistent_{'pcg' if pc else 'cg'}_f32_74x74_L148_traffic.md")
     src = os.path.join(ROOT, "paper_1806_07938_amd", "csrc", "persistent.hip")
     try:
         rec = {}
@@ -97,7 +97,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md but not implemented.", file=sys.stderr)
+              "one system is not sharded across GPUs.", file=sys.stderr)
         sys.exit(2)
     import torch
     import workloads as W
@@ -114,7 +114,7 @@ def main():
             cy.copy_(cx)
         torch.cuda.synchronize()
         del cx, cy
-    wl = W.c2(pad_L=args.pad)
+    wl = W.lgs6_74x74(pad_L=args.pad)
     frames = W.turbulent_slopes(wl, frames=args.frames).astype(np.float32)
 
     ctx = Context(0)

@@ -1,38 +1,43 @@
-// Persistent CG solver (TT_SOLVER_PERSISTENT): one cooperative launch runs CG
+// Persistent solver (TT_SOLVER_PERSISTENT): one cooperative launch runs the
 // iterations until convergence, a residual-replacement point, the iteration
-// cap or a breakdown.  Rows a3-a8 of the hot path in one kernel.
+// cap or a breakdown.  Rows a3-a8 of the hot path in one kernel, for three
+// iterations (KIND):
 //
-// CG form.  The single-reduction rearrangement of CG (Chronopoulos & Gear,
-// J. Comput. Appl. Math. 25 (1989)) computes both inner products of an
-// iteration after one matrix-vector product with the residual:
-//
+// K_CG: the single-reduction rearrangement of CG (Chronopoulos & Gear,
+// J. Comput. Appl. Math. 25 (1989)), both inner products of an iteration
+// after one matrix-vector product with the residual:
 //   w_i = A r_i,  gamma_i = r_i.r_i,  delta_i = r_i.w_i,
 //   beta_i = gamma_i / gamma_{i-1} (0 at a start),
 //   alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1})  (gamma_i/delta_i at a start),
 //   p_i = r_i + beta_i p_{i-1},  s_i = w_i + beta_i s_{i-1}   (s_i = A p_i),
-//   x_{i+1} = x_i + alpha_i p_i,  r_{i+1} = r_i - alpha_i s_i.
-//
-// In exact arithmetic it produces the iterates of textbook CG (§2.G).  After an
-// FP64 residual replacement the recurrences restart (beta = 0, p = s = 0).
+//   x_{i+1} = x_i + alpha_i p_i,  r_{i+1} = r_i - alpha_i s_i;
+// in exact arithmetic the iterates of textbook CG (§2.G).
+// K_PCG: the same preconditioned by the block-circulant inverse (see
+// row_pc_update; four phases per iteration).
+// K_MINRES: Paige-Saunders MINRES (see row_mr), the paper's Toeplitz solver.
+// After an FP64 residual replacement every iteration restarts from scratch.
 //
 // The product A r is the fused 2RBT product of §2.E, split in two phases
-// separated by grid barriers (two barriers per iteration):
+// separated by grid barriers:
 //   row phase    (rows (c, a) of the n x n grids, a few consecutive rows per
-//                block): inverse row transform of the column-phase output ->
-//                w = A r (+ sigma^2 r); vector updates; forward row transform of
-//                the new residual -> T[f2][c][a]; partial r.r and sigma^2 r.r;
+//                block, one lane per grid point with the vectors in
+//                registers): inverse row transform of the gathered column-phase
+//                output -> w = A r (+ Sigma_eta r); vector updates; forward row
+//                transform of the new vector -> T[f2][c][a]; partial sums;
 //   column phase (block = one f2 column and one of S ranges of f1):
 //                forward column transform of the C channels, per-frequency
 //                Hermitian products summed over input channels, partial inverse
 //                column transform -> U[f2][part][c][a], and the partial of
 //                r.(Sigma_ss r) by Parseval: r.C r = L^-2 sum_f w(f2) Re(X~^H Y~),
 //                valid because r vanishes outside the n x n corner.
-// Each block keeps its transform tiles (its f1 range of the column DFT matrix
-// in both orientations, the row DFT matrix) and its share of the packed
-// spectra in LDS for the whole launch when they fit (FP32 at the 74x74 size),
-// so the iteration reads no spectra from memory; otherwise the same tiles are
-// read from global memory.  Loops are laid out so that consecutive lanes read
-// consecutive LDS words.
+// The column transforms are dense contractions and run on the matrix cores
+// (col_mf: FP32, or FP16 / BF16 operands for the TT_PREC_F16 / BF16 forms);
+// the FP64 form uses the VALU.  Each block keeps its transform tiles (its f1
+// range of the column DFT matrix as operand fragments, the row DFT matrix)
+// and its share of the packed spectra in LDS for the whole launch when they
+// fit, so an iteration reads no spectra from memory; the preconditioned
+// solver stages the slope or preconditioner spectra per column phase.  With
+// 2x2 noise blocks (§2.F) the x and y rows of a subaperture share a block.
 //
 // Barrier: two-level counters (per XCD, then global), see grid_sync.  Every
 // poll has a 2 s wall-clock limit and honours an abort word, so every wave

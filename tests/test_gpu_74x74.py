@@ -20,35 +20,35 @@ WORKERS = min(16, os.cpu_count() or 1)
 
 
 @pytest.fixture(scope="module")
-def c2():
-    wl = W.c2()
-    say("c2: building library system")
+def sys74():
+    wl = W.lgs6_74x74()
+    say("74x74: building library system")
     ctx, k = make_system(wl, target=True)
     return wl, ctx, k
 
 
 @pytest.fixture(scope="module")
-def c2_oracle(c2):
+def oracle74(sys74):
     from oracle.covariance import kernel_tables
     from oracle.toeplitz import ToeplitzOperator
-    wl = c2[0]
-    say("c2: oracle tables with", WORKERS, "workers")
+    wl = sys74[0]
+    say("74x74: oracle tables with", WORKERS, "workers")
     tabs = kernel_tables(wl, workers=WORKERS)
     return ToeplitzOperator(wl, tables=tabs)
 
 
-def test_c2_sizes(c2):
-    wl, ctx, k = c2
+def test_74x74_sizes(sys74):
+    wl, ctx, k = sys74
     info = ctx.info
     assert info["n_vs"] == 3972 and info["n_slopes"] == 47664
     assert info["n_prime"] == 106 and info["proj_pad_L"] == 180
     assert info["spectra_bytes_f32"] == 148 * 75 * 108 * 4
 
 
-def test_c2_tables_sampled(c2):
+def test_74x74_tables_sampled(sys74):
     from oracle.covariance import slope_pair_cov
-    wl, ctx, k = c2
-    say("c2 tables sampled")
+    wl, ctx, k = sys74
+    say("74x74 tables sampled")
     got = k.tables()
     rng = np.random.default_rng(0)
     n, m = wl.n, 2 * wl.n - 1
@@ -68,31 +68,31 @@ def test_c2_tables_sampled(c2):
     assert worst < 1e-11
 
 
-def test_c2_matvec(c2, c2_oracle):
+def test_74x74_matvec(sys74, oracle74):
     import torch
-    wl, ctx, k = c2
-    say("c2 matvec")
+    wl, ctx, k = sys74
+    say("74x74 matvec")
     dev = torch_dev()
     x = np.random.default_rng(5).standard_normal(wl.n_slopes)
-    ref = c2_oracle(x)
+    ref = oracle74(x)
     y64 = ctx.matvec_f64(torch.tensor(x, device=dev)).cpu().numpy()
     assert rel_maxabs(y64, ref) < 1e-11
     x32 = x.astype(np.float32)
     y32 = ctx.matvec(torch.tensor(x32, device=dev)).cpu().numpy()
-    assert rel_maxabs(y32, c2_oracle(x32.astype(np.float64))) < 3e-6
+    assert rel_maxabs(y32, oracle74(x32.astype(np.float64))) < 3e-6
 
 
 @pytest.mark.parametrize("solver", [0, 1])
-def test_c2_solve(c2, c2_oracle, solver):
+def test_74x74_solve(sys74, oracle74, solver):
     import torch
-    wl, ctx, k = c2
-    say("c2 solve solver", solver)
+    wl, ctx, k = sys74
+    say("74x74 solve solver", solver)
     dev = torch_dev()
     s = W.turbulent_slopes(wl, seed=7)[0].astype(np.float32)
     zeta, phi, info = ctx.solve(torch.tensor(s, device=dev), tol=1e-6, solver=solver)
     z = zeta.cpu().numpy()
     s64 = s.astype(np.float64)
-    res = np.linalg.norm(s64 - c2_oracle(z)) / np.linalg.norm(s64)
+    res = np.linalg.norm(s64 - oracle74(z)) / np.linalg.norm(s64)
     say("  iterations", info.iterations, "refinements", info.refinements, "lib relres", info.rel_residual,
         "oracle relres", res)
     assert info.status == 0
@@ -100,20 +100,20 @@ def test_c2_solve(c2, c2_oracle, solver):
     assert abs(res - info.rel_residual) <= 1e-8
 
 
-def test_c2_pcg_solve(c2, c2_oracle):
+def test_74x74_pcg_solve(sys74, oracle74):
     # block-circulant preconditioner at the full size: the oracle's FP64
     # residual at or under 1e-6, in far fewer iterations than plain CG
     import torch
     from paper_1806_07938_amd.tt import PRECOND_CIRCULANT
-    wl, ctx, k = c2
+    wl, ctx, k = sys74
     s = W.turbulent_slopes(wl, seed=7)[0].astype(np.float32)
     dev = torch_dev()
     zeta, phi, info = ctx.solve(torch.tensor(s, device=dev), tol=1e-6, preconditioner=PRECOND_CIRCULANT)
     _, _, info_cg = ctx.solve(torch.tensor(s, device=dev), tol=1e-6)
     z = zeta.cpu().numpy()
     s64 = s.astype(np.float64)
-    res = np.linalg.norm(s64 - c2_oracle(z)) / np.linalg.norm(s64)
-    say("c2 pcg iterations", info.iterations, "refinements", info.refinements, "cg iterations", info_cg.iterations,
+    res = np.linalg.norm(s64 - oracle74(z)) / np.linalg.norm(s64)
+    say("74x74 pcg iterations", info.iterations, "refinements", info.refinements, "cg iterations", info_cg.iterations,
         "oracle relres", res, "kernel ms", info.kernel_ms, "cg kernel ms", info_cg.kernel_ms)
     assert info.status == 0
     assert res <= 1.01e-6
@@ -121,17 +121,17 @@ def test_c2_pcg_solve(c2, c2_oracle):
     assert info.iterations < 0.5 * info_cg.iterations
 
 
-def test_c2_minres_solve(c2, c2_oracle):
+def test_74x74_minres_solve(sys74, oracle74):
     # the paper's solver at the full size: the oracle's FP64 residual at or under 1e-6
     import torch
     from paper_1806_07938_amd.tt import METHOD_MINRES
-    wl, ctx, k = c2
+    wl, ctx, k = sys74
     s = W.turbulent_slopes(wl, seed=7)[0].astype(np.float32)
     zeta, phi, info = ctx.solve(torch.tensor(s, device=torch_dev()), tol=1e-6, method=METHOD_MINRES)
     z = zeta.cpu().numpy()
     s64 = s.astype(np.float64)
-    res = np.linalg.norm(s64 - c2_oracle(z)) / np.linalg.norm(s64)
-    say("c2 minres iterations", info.iterations, "refinements", info.refinements, "oracle relres", res,
+    res = np.linalg.norm(s64 - oracle74(z)) / np.linalg.norm(s64)
+    say("74x74 minres iterations", info.iterations, "refinements", info.refinements, "oracle relres", res,
         "kernel ms", info.kernel_ms)
     assert info.status == 0
     assert res <= 1.01e-6
@@ -139,26 +139,26 @@ def test_c2_minres_solve(c2, c2_oracle):
 
 
 @pytest.mark.parametrize("precision", [2, 3])
-def test_c2_low_precision_status_is_honest(c2, c2_oracle, precision):
+def test_74x74_low_precision_status_is_honest(sys74, oracle74, precision):
     # FP16 / BF16 column transforms: TT_OK only with the oracle's FP64 residual
     # at or under tol; otherwise TT_NOT_CONVERGED reporting the returned
     # iterate's residual
     import torch
     from paper_1806_07938_amd.tt import TT_NOT_CONVERGED
-    wl, ctx, k = c2
+    wl, ctx, k = sys74
     s = W.turbulent_slopes(wl, seed=7)[0].astype(np.float32)
     zeta, phi, info = ctx.solve(torch.tensor(s, device=torch_dev()), tol=1e-6, precision=precision,
                                 allow=(0, TT_NOT_CONVERGED))
     z = zeta.cpu().numpy()
     assert np.all(np.isfinite(z))
     s64 = s.astype(np.float64)
-    res = np.linalg.norm(s64 - c2_oracle(z)) / np.linalg.norm(s64)
-    say("c2 precision", precision, "status", info.status, "iterations", info.iterations, "lib relres",
+    res = np.linalg.norm(s64 - oracle74(z)) / np.linalg.norm(s64)
+    say("74x74 precision", precision, "status", info.status, "iterations", info.iterations, "lib relres",
         info.rel_residual, "oracle relres", res)
     # norm-wise FP64 rounding bound of s - A z (||A|| by power iteration)
     v = np.random.default_rng(0).standard_normal(z.size)
     for _ in range(30):
-        v = c2_oracle(v)
+        v = oracle74(v)
         nrm = np.linalg.norm(v)
         v /= nrm
     scale = (1.01 * nrm * np.linalg.norm(z) + np.linalg.norm(s64)) / np.linalg.norm(s64)
@@ -169,11 +169,11 @@ def test_c2_low_precision_status_is_honest(c2, c2_oracle, precision):
         assert info.status == TT_NOT_CONVERGED
 
 
-def test_c2_projection(c2):
+def test_74x74_projection(sys74):
     import torch
     from oracle.projection import phi_paper_fft, xi_prime_tables
-    wl, ctx, k = c2
-    say("c2 projection")
+    wl, ctx, k = sys74
+    say("74x74 projection")
     dev = torch_dev()
     z = np.random.default_rng(9).standard_normal(wl.n_slopes)
     phi = ctx.project(torch.tensor(z, device=dev)).cpu().numpy()

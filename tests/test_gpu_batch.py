@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _batch():
-    wls = [W.c1(), W.tiny(n=6, n_gs=2, lgs=True, n_layer=3, seed=4, pad_L=12),
+    wls = [W.lgs3_10x10(), W.tiny(n=6, n_gs=2, lgs=True, n_layer=3, seed=4, pad_L=12),
            W.tiny(n=8, n_gs=4, lgs=False, n_layer=2, seed=6, pad_L=16)]
     systems = [make_system(wl, target=True) for wl in wls]
     return wls, systems

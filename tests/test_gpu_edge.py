@@ -18,7 +18,7 @@ SOLVERS = [0, 1]
 
 @pytest.fixture(scope="module")
 def c1sys():
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     ctx, k = make_system(wl, target=True)
     return wl, ctx, k
 
@@ -110,7 +110,7 @@ def test_indefinite_system_is_breakdown(solver):
     import torch
     from paper_1806_07938_amd import Context, system_from
     from paper_1806_07938_amd.tt import TT_BREAKDOWN
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     s = _s(wl)
     wl.noise_var = -1e5
     ctx = Context(0)
@@ -125,7 +125,7 @@ def test_per_slope_noise(solver):
     from oracle.covariance import slope_covariance
     from oracle.solve import cholesky_solve
     from paper_1806_07938_amd import Context
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     nz = 0.05 + 0.3 * np.random.default_rng(2).random(wl.n_slopes)
     ctx = Context(0)
     k = ctx.generate_kernels(wl.n, wl.n_gs, wl.pad_L, wl.D, wl.h_lgs, wl.gs, wl.valid, wl.h, wl.w, wl.r0, wl.L0)
@@ -147,7 +147,7 @@ def test_ngs_and_off_axis_target(solver):
     from oracle.covariance import system_matrix
     from oracle.projection import phi_exact, phi_paper_dense
     from oracle.solve import cholesky_solve
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     wl.h_lgs = math.inf
     wl.target = (8 * W.ARCSEC, -5 * W.ARCSEC)
     ctx, k = make_system(wl, target=True)
@@ -168,7 +168,7 @@ def test_argument_and_state_errors():
     import torch
     from paper_1806_07938_amd import Context, TTError
     from paper_1806_07938_amd.tt import TT_INVALID_ARG, TT_NOT_READY
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     ctx = Context(0)
     dev = torch_dev()
     with pytest.raises(TTError) as e:
@@ -207,7 +207,7 @@ def test_two_systems_and_repeated_solves():
     from paper_1806_07938_amd import Context, system_from
     ctx = Context(0)
     dev = torch_dev()
-    for wl in (W.c1(), W.tiny(n=5, n_gs=2, seed=3, pad_L=10)):
+    for wl in (W.lgs3_10x10(), W.tiny(n=5, n_gs=2, seed=3, pad_L=10)):
         system_from(ctx, wl, target=True)
         s = W.gaussian_slopes(wl, seed=1)[0].astype(np.float32)
         zref = cholesky_solve(system_matrix(wl), s.astype(np.float64))

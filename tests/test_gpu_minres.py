@@ -24,7 +24,7 @@ def _wl(case):
     return W.tiny(**case) if isinstance(case, dict) else case()
 
 
-@pytest.mark.parametrize("case", CASES + [W.c1], ids=lambda c: str(c) if isinstance(c, dict) else "c1")
+@pytest.mark.parametrize("case", CASES + [W.lgs3_10x10], ids=lambda c: str(c) if isinstance(c, dict) else "lgs3_10x10")
 def test_early_iterates_match_oracle(case):
     import torch
     from oracle.covariance import system_matrix
@@ -46,7 +46,7 @@ def test_early_iterates_match_oracle(case):
 
 
 @pytest.mark.parametrize("precision", [1, 0])
-@pytest.mark.parametrize("case", CASES + [W.c1], ids=lambda c: str(c) if isinstance(c, dict) else "c1")
+@pytest.mark.parametrize("case", CASES + [W.lgs3_10x10], ids=lambda c: str(c) if isinstance(c, dict) else "lgs3_10x10")
 def test_minres_solve_matches_cholesky(case, precision):
     import torch
     from oracle.covariance import system_matrix
@@ -78,7 +78,7 @@ def test_minres_argument_errors():
     import torch
     from paper_1806_07938_amd import TTError
     from paper_1806_07938_amd.tt import METHOD_MINRES, PRECOND_CIRCULANT, TT_INVALID_ARG
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     ctx, k = make_system(wl, target=False)
     s = torch.zeros(wl.n_slopes, dtype=torch.float32, device=torch_dev())
     for kw in (dict(solver=1), dict(precision=2), dict(preconditioner=PRECOND_CIRCULANT)):

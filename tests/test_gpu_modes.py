@@ -22,7 +22,7 @@ def _wl(case):
     return W.tiny(**case) if isinstance(case, dict) else case()
 
 
-@pytest.mark.parametrize("case", CASES + [W.c1], ids=lambda c: str(c) if isinstance(c, dict) else "c1")
+@pytest.mark.parametrize("case", CASES + [W.lgs3_10x10], ids=lambda c: str(c) if isinstance(c, dict) else "lgs3_10x10")
 def test_mode_removed_product(case):
     import torch
     from oracle.covariance import system_matrix
@@ -43,7 +43,7 @@ def test_mode_removed_product(case):
 
 
 @pytest.mark.parametrize("precision", [1, 0])
-@pytest.mark.parametrize("case", CASES + [W.c1], ids=lambda c: str(c) if isinstance(c, dict) else "c1")
+@pytest.mark.parametrize("case", CASES + [W.lgs3_10x10], ids=lambda c: str(c) if isinstance(c, dict) else "lgs3_10x10")
 def test_mode_removed_solve_and_projection(case, precision):
     import torch
     from oracle.covariance import system_matrix
@@ -76,7 +76,7 @@ def test_mode_removal_errors():
     import torch
     from paper_1806_07938_amd import Context, TTError
     from paper_1806_07938_amd.tt import TT_INVALID_ARG, TT_NOT_READY
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     with pytest.raises(TTError) as e:
         Context(0).set_mode_removal(True)
     assert e.value.status == TT_NOT_READY

@@ -32,7 +32,7 @@ def _system(wl):
     return ctx, k, var, cxy
 
 
-@pytest.mark.parametrize("case", CASES + [W.c1], ids=lambda c: str(c) if isinstance(c, dict) else "c1")
+@pytest.mark.parametrize("case", CASES + [W.lgs3_10x10], ids=lambda c: str(c) if isinstance(c, dict) else "lgs3_10x10")
 def test_products_with_2x2_noise(case):
     import torch
     from oracle.covariance import system_matrix
@@ -55,7 +55,7 @@ SOLVES = [dict(solver=0, precision=0), dict(solver=0, precision=1), dict(solver=
 
 
 @pytest.mark.parametrize("opts", SOLVES, ids=lambda o: "-".join(f"{k}{v}" for k, v in o.items()))
-@pytest.mark.parametrize("case", CASES + [W.c1], ids=lambda c: str(c) if isinstance(c, dict) else "c1")
+@pytest.mark.parametrize("case", CASES + [W.lgs3_10x10], ids=lambda c: str(c) if isinstance(c, dict) else "lgs3_10x10")
 def test_solves_with_2x2_noise(case, opts):
     import torch
     from oracle.covariance import system_matrix
@@ -80,7 +80,7 @@ def test_2x2_noise_errors():
     import torch
     from paper_1806_07938_amd import Context, TTError
     from paper_1806_07938_amd.tt import TT_INVALID_ARG, TT_NOT_READY
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     ctx = Context(0)
     with pytest.raises(TTError) as e:
         ctx.set_noise_xy(np.zeros((wl.n_gs, 76)))

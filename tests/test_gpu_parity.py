@@ -31,7 +31,7 @@ def _wl(case):
     return W.tiny(**case) if isinstance(case, dict) else case()
 
 
-@pytest.mark.parametrize("case", TINY + [W.c1], ids=lambda c: str(c) if isinstance(c, dict) else "c1")
+@pytest.mark.parametrize("case", TINY + [W.lgs3_10x10], ids=lambda c: str(c) if isinstance(c, dict) else "lgs3_10x10")
 def test_kernel_tables(case):
     wl = _wl(case)
     say("tables", wl.name, "n", wl.n, "gs", wl.n_gs)
@@ -42,7 +42,7 @@ def test_kernel_tables(case):
     assert rel_maxabs(got, ref) < 1e-11
 
 
-@pytest.mark.parametrize("case", TINY + [W.c1], ids=lambda c: str(c) if isinstance(c, dict) else "c1")
+@pytest.mark.parametrize("case", TINY + [W.lgs3_10x10], ids=lambda c: str(c) if isinstance(c, dict) else "lgs3_10x10")
 def test_matvec(case):
     import torch
     from oracle.covariance import system_matrix
@@ -62,11 +62,11 @@ def test_matvec(case):
 
 
 @pytest.mark.parametrize("L", [19, 20, 21, 32, 64])
-def test_matvec_padding_invariance_c1(L):
+def test_matvec_padding_invariance_10x10(L):
     import torch
     from oracle.covariance import system_matrix
-    wl = W.c1(pad_L=L)
-    say("matvec c1 L", L)
+    wl = W.lgs3_10x10(pad_L=L)
+    say("matvec 10x10 L", L)
     dev = torch_dev()
     ctx, k = make_system(wl, target=False)
     x = np.random.default_rng(L).standard_normal(wl.n_slopes)
@@ -76,12 +76,12 @@ def test_matvec_padding_invariance_c1(L):
 
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("solver", [1, 0])
-def test_solve_c1(precision, solver):
+def test_solve_10x10(precision, solver):
     import torch
     from oracle.covariance import system_matrix
     from oracle.solve import cholesky_solve
-    wl = W.c1()
-    say("solve c1 precision", precision, "solver", solver)
+    wl = W.lgs3_10x10()
+    say("solve 10x10 precision", precision, "solver", solver)
     dev = torch_dev()
     ctx, k = make_system(wl, target=True)
     s = W.turbulent_slopes(wl)[0].astype(np.float32)
@@ -97,7 +97,7 @@ def test_solve_c1(precision, solver):
     assert np.linalg.norm(z - zref) / np.linalg.norm(zref) < 1e-5
 
 
-@pytest.mark.parametrize("case", TINY[2:] + [W.c1], ids=lambda c: str(c) if isinstance(c, dict) else "c1")
+@pytest.mark.parametrize("case", TINY[2:] + [W.lgs3_10x10], ids=lambda c: str(c) if isinstance(c, dict) else "lgs3_10x10")
 def test_projection(case):
     import torch
     from oracle.projection import phi_paper_dense

@@ -12,7 +12,7 @@ against the oracle's block-circulant preconditioner and PCG, through the C ABI.
   the FP64 residual replacements allowed for), and at the 10x10 workload in
   fewer than plain CG.
 * Shapes: tiny systems with ragged masks and odd paddings, the 10x10 / 3 LGS
-  workload; the 74x74 workload is in test_gpu_c2.py."""
+  workload; the 74x74 workload is in test_gpu_74x74.py."""
 import numpy as np
 import pytest
 
@@ -31,7 +31,7 @@ def _wl(case):
 
 
 @pytest.mark.parametrize("precision,tol", [(1, 1e-10), (0, 1e-5)])
-@pytest.mark.parametrize("case", CASES + [W.c1], ids=lambda c: str(c) if isinstance(c, dict) else "c1")
+@pytest.mark.parametrize("case", CASES + [W.lgs3_10x10], ids=lambda c: str(c) if isinstance(c, dict) else "lgs3_10x10")
 def test_first_iterate_is_alpha_P_s(case, precision, tol):
     import torch
     from oracle.covariance import system_matrix
@@ -54,7 +54,7 @@ def test_first_iterate_is_alpha_P_s(case, precision, tol):
 
 
 @pytest.mark.parametrize("precision", [1, 0])
-@pytest.mark.parametrize("case", CASES + [W.c1], ids=lambda c: str(c) if isinstance(c, dict) else "c1")
+@pytest.mark.parametrize("case", CASES + [W.lgs3_10x10], ids=lambda c: str(c) if isinstance(c, dict) else "lgs3_10x10")
 def test_pcg_solve_matches_cholesky(case, precision):
     import torch
     from oracle.covariance import system_matrix
@@ -84,16 +84,16 @@ def test_pcg_solve_matches_cholesky(case, precision):
         assert abs(info.iterations - k_pcg) <= max(2, 0.05 * k_pcg)
     else:                # FP32: each FP64 residual replacement restarts the recurrences
         assert info.iterations <= 1.5 * k_pcg + 10 * info.refinements
-    if wl.name == "c1":  # the preconditioner pays at the 10x10 workload (311 -> 163 at 1e-6)
+    if wl.name == "lgs3_10x10":  # the preconditioner pays at the 10x10 workload (311 -> 163 at 1e-6)
         assert info.iterations < 0.8 * k_cg
 
 
-def test_pcg_zero_slopes_and_warm_start(c1=None):
+def test_pcg_zero_slopes_and_warm_start():
     import torch
     from oracle.covariance import system_matrix
     from oracle.solve import cholesky_solve
     from paper_1806_07938_amd.tt import PRECOND_CIRCULANT
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     ctx, k = make_system(wl, target=False)
     dev = torch_dev()
     z, _, info = ctx.solve(torch.zeros(wl.n_slopes, dtype=torch.float32, device=dev), preconditioner=PRECOND_CIRCULANT)
@@ -109,7 +109,7 @@ def test_pcg_argument_errors():
     import torch
     from paper_1806_07938_amd import TTError
     from paper_1806_07938_amd.tt import PRECOND_CIRCULANT, TT_INVALID_ARG
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     ctx, k = make_system(wl, target=False)
     s = torch.zeros(wl.n_slopes, dtype=torch.float32, device=torch_dev())
     for kw in (dict(solver=1), dict(precision=2), dict(precision=3)):

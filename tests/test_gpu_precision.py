@@ -26,7 +26,7 @@ FORMS = {2: 2.0 ** -11, 3: 2.0 ** -8}   # precision -> unit roundoff
 
 @pytest.fixture(scope="module")
 def c1sys():
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     ctx, k = make_system(wl, target=True)
     return wl, ctx, k
 

@@ -138,7 +138,7 @@ def test_rows_match_dense():
 
 
 def test_config1_counts():
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     assert wl.n_vs == 76 and wl.n_slopes == 456
     assert W.pupil_mask(74, 39.0, 0.28).sum() == 3972
 
@@ -219,7 +219,7 @@ def test_noise_covariance_structure():
 
 
 def test_elongated_noise_principal_axes_radial():
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     var, cxy = W.elongated_noise(wl)
     n, d = wl.n, wl.d
     idx = np.flatnonzero(wl.valid.ravel())

@@ -18,7 +18,7 @@ from oracle.solve import cg
 
 
 def test_slope_modes_are_hudgin_slopes_of_phase_modes():
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     d = wl.d
     r = G.subap_centers(wl.n, d)[G.valid_index(wl.valid)]
     Z = slope_modes(wl)
@@ -33,7 +33,7 @@ def test_slope_modes_are_hudgin_slopes_of_phase_modes():
 
 
 def test_projectors():
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     M = slope_projector(wl)
     assert np.allclose(M, M.T, atol=1e-13) and np.allclose(M @ M, M, atol=1e-12)
     Z = slope_modes(wl)
@@ -50,7 +50,7 @@ def test_projectors():
 
 
 def test_mode_removed_solution():
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     A = system_matrix(wl)
     M = slope_projector(wl)
     s = W.turbulent_slopes(wl)[0]

@@ -67,16 +67,16 @@ def test_frequency_form_equals_dense_construction(case):
     assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
-def test_symmetric_positive_definite_c1():
-    wl = W.c1()
+def test_symmetric_positive_definite_10x10():
+    wl = W.lgs3_10x10()
     P = _dense_of(CirculantPreconditioner(wl), wl.n_slopes)
     assert np.abs(P - P.T).max() <= 1e-12 * np.abs(P).max()
     assert np.linalg.eigvalsh(0.5 * (P + P.T)).min() > 0
 
 
-def test_embedding_has_negative_eigenvalues_c1():
+def test_embedding_has_negative_eigenvalues_10x10():
     # the reading that clamps them is exercised, and the inverse is still finite Hermitian PD
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     S = kernel_spectra(kernel_tables(wl), wl.n_gs, wl.pad_L)
     Mf = np.moveaxis(S, (0, 1), (-2, -1))
     assert np.linalg.eigvalsh(Mf).min() < -1.0
@@ -88,7 +88,7 @@ def test_embedding_has_negative_eigenvalues_c1():
 
 
 def test_pcg_identity_is_cg():
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     A = system_matrix(wl)
     s = W.turbulent_slopes(wl)[0]
     x1, k1, h1 = cg(lambda v: A @ v, s, tol=1e-8, history=True)
@@ -108,8 +108,8 @@ def test_pcg_exact_inverse_one_iteration():
     assert np.linalg.norm(x - cholesky_solve(A, s)) <= 1e-10 * np.linalg.norm(x)
 
 
-def test_pcg_circulant_reaches_cholesky_in_fewer_iterations_c1():
-    wl = W.c1()
+def test_pcg_circulant_reaches_cholesky_in_fewer_iterations_10x10():
+    wl = W.lgs3_10x10()
     A = system_matrix(wl)
     s = W.turbulent_slopes(wl)[0]
     P = CirculantPreconditioner(wl)

@@ -79,7 +79,7 @@ def test_fft_form_equals_dense_form(n, g, seed):
 
 
 def test_interpolation_gap_is_small_for_config1():
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     z = np.random.default_rng(5).standard_normal(wl.n_slopes)
     a = P.phi_paper_dense(wl, z)
     e = P.phi_exact(wl, z)
@@ -88,8 +88,8 @@ def test_interpolation_gap_is_small_for_config1():
 
 
 def test_grid_size_config2():
-    assert P.new_grid_size(W.c2()) == 106
-    assert P.new_grid_size(W.c1()) == 13
+    assert P.new_grid_size(W.lgs6_74x74()) == 106
+    assert P.new_grid_size(W.lgs3_10x10()) == 13
 
 
 def test_fried_phase_slope_matches_corner_points():

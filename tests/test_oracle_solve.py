@@ -33,7 +33,7 @@ def test_cg_finite_termination(k):
 
 
 def test_cg_matches_cholesky_config1():
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     A = C.system_matrix(wl)
     s = W.turbulent_slopes(wl)[0]
     z = S.cholesky_solve(A, s)
@@ -55,9 +55,9 @@ def test_cg_warm_start_at_solution_does_nothing():
 
 # --- MINRES (§2.G, the paper's Toeplitz solver) ---------------------------------
 
-def test_minres_matches_cholesky_c1():
+def test_minres_matches_cholesky_10x10():
     from oracle.solve import minres
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     A = C.system_matrix(wl)
     s = W.turbulent_slopes(wl)[0]
     x, k, hist = minres(lambda v: A @ v, s, tol=1e-10, history=True)
@@ -96,7 +96,7 @@ def test_minres_symmetric_indefinite():
 def test_minres_equals_cg_iterate_count_order_on_spd():
     # on an SPD system MINRES and CG need iteration counts of the same order
     from oracle.solve import minres
-    wl = W.c1()
+    wl = W.lgs3_10x10()
     A = C.system_matrix(wl)
     s = W.turbulent_slopes(wl)[0]
     _, kcg = S.cg(lambda v: A @ v, s, tol=1e-8)

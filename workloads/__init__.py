@@ -9,10 +9,10 @@ solver) and imports neither the oracle nor the HIP library.
 Workloads (parameters follow Table 1 and Table 2 of the paper where they exist,
 with the readings listed in each constructor):
 
-  c1  8 m pupil, 30 % obstruction, 10x10 Shack-Hartmann, 3 LGS at 90 km on a
+  lgs3_10x10  8 m pupil, 30 % obstruction, 10x10 Shack-Hartmann, 3 LGS at 90 km on a
       30 arcsec ring, layers 0 / 10 km (0.7 / 0.3), r0 = 0.15 m, L0 = 25 m,
       sigma^2 = 0.1 rad^2, FFT side L = 20.  76 valid subapertures, 456 slopes.
-  c2  39 m pupil, 28 % obstruction, 74x74, 6 LGS at 90 km on a 60 arcsec ring,
+  lgs6_74x74  39 m pupil, 28 % obstruction, 74x74, 6 LGS at 90 km on a 60 arcsec ring,
       35 layers 30 m - 26.5 km with seeded exponentially decaying weights,
       r0 = 0.157 m, L0 = 25 m, sigma^2 = 0.1 rad^2, L = 148.  3972 valid
       subapertures per sensor, 47 664 slopes.  Stands in for the HARMONI LTAO
@@ -99,11 +99,11 @@ def ring(n_gs: int, radius_rad: float) -> np.ndarray:
     return np.stack([radius_rad * np.cos(ang), radius_rad * np.sin(ang)], axis=1)
 
 
-def c1(pad_L: int = 20) -> Workload:
+def lgs3_10x10(pad_L: int = 20) -> Workload:
     """8 m, 10x10, 3 LGS on a 30 arcsec ring, 2 layers (Table 1 geometry, reduced)."""
     n, D, obs = 10, 8.0, 0.30
     return Workload(
-        name="c1", n=n, D=D, obstruction=obs, gs=ring(3, 30 * ARCSEC), h_lgs=90e3,
+        name="lgs3_10x10", n=n, D=D, obstruction=obs, gs=ring(3, 30 * ARCSEC), h_lgs=90e3,
         h=np.array([0.0, 10e3]), w=np.array([0.7, 0.3]), r0=0.15, L0=25.0,
         noise_var=0.1, pad_L=pad_L, valid=pupil_mask(n, D, obs))
 
@@ -118,12 +118,12 @@ def c2_profile(seed: int = SEED, n_layer: int = 35):
     return h, w / w.sum()
 
 
-def c2(pad_L: int = 148) -> Workload:
+def lgs6_74x74(pad_L: int = 148) -> Workload:
     """39 m, 74x74, 6 LGS on a 60 arcsec ring, 35 layers (Table 2 geometry)."""
     n, D, obs = 74, 39.0, 0.28
     h, w = c2_profile()
     return Workload(
-        name="c2", n=n, D=D, obstruction=obs, gs=ring(6, 60 * ARCSEC), h_lgs=90e3,
+        name="lgs6_74x74", n=n, D=D, obstruction=obs, gs=ring(6, 60 * ARCSEC), h_lgs=90e3,
         h=h, w=w, r0=0.157, L0=25.0, noise_var=0.1, pad_L=pad_L,
         valid=pupil_mask(n, D, obs))
 
