@@ -96,8 +96,8 @@ def cpu_baseline(wl, s_frame, tol):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "one system is not sharded across GPUs.", file=sys.stderr)
+        print(f"bench.py: the library solves one system on one GPU (asked for --gpus {args.gpus}); "
+              "a system is not sharded across GPUs.", file=sys.stderr)
         sys.exit(2)
     import torch
     import workloads as W
