@@ -175,9 +175,9 @@ def main():
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
-                    "kernel": (f"k_cg_persistent<float, true, 1, {'true' if pc else 'false'}> (FP32 column "
+                    "kernel": (f"k_cg_persistent<float, true, 1, {1 if pc else 0}> (FP32 column "
                                "transforms on the matrix cores)" if prec == PREC_F32 else
-                               f"k_cg_persistent<double, true, 0, {'true' if pc else 'false'}>"),
+                               f"k_cg_persistent<double, true, 0, {1 if pc else 0}>"),
                     "avg_launch_ms": round(avg_launch_ms, 4), "bytes_per_iteration": int(bytes_iter),
                     "iterations_per_launch": round(float(iters.sum() / launches.sum()), 1)}
 
