@@ -244,6 +244,25 @@ tt_status tt_set_mode_removal(tt_ctx* ctx, int on);
 tt_status tt_matvec(tt_ctx* ctx, const float* d_x, float* d_y);
 tt_status tt_matvec_f64(tt_ctx* ctx, const double* d_x, double* d_y);
 
+/* The same FP32 product for count independent systems in one call (the §2.E
+ * product of each system; rows a3-a7 batched over systems): y_i = A_i x_i,
+ * d_x[i], d_y[i] on systems[i] (n_slopes of that system each, device memory,
+ * not overlapping).  The systems may differ in every size; each context appears
+ * at most once, all are on one device, and none has mode removal on
+ * (TT_INVALID_ARG otherwise; an unset context gives TT_NOT_READY).  Sizes are
+ * limited by the column phase: with S = 2 if every pad_L is even, else 1,
+ * (pad_L / S) * n_gs <= 2048 and the LDS of one column item, 4 (pad_L / S)
+ * (3 n_gs^2 + 1) + 16 n_gs (pad_L / S) (twice that when pad_L / S is not a
+ * power of two) + 8 pad_L bytes, at most 160 KiB.
+ * All work is enqueued on the stream of systems[0] (three launches: row
+ * transforms, column transforms with the per-frequency products, inverse row
+ * transforms), in the per-system work buffers of each context: order the call
+ * after other work on those contexts.  Asynchronous unless phase_ms != NULL:
+ * then the call waits and phase_ms[0..2] receive the durations (ms, HIP events)
+ * of the three launches. */
+tt_status tt_matvec_batch(tt_ctx* const* systems, int count, const float* const* d_x,
+                          float* const* d_y, float* phase_ms);
+
 /* Solve W_s (Sigma_ss + Sigma_eta) W_s^T zeta = s by CG (rows a3-a8, a10) and,
  * if d_phi != NULL, project phi = W_phi Sigma_{phi_beta s} zeta (row a9).
  * d_s: n_slopes floats; d_x0: n_slopes doubles (warm start) or NULL (zeta0 = 0);

@@ -378,6 +378,11 @@ tt_status tt_matvec_f64(tt_ctx* c, const double* d_x, double* d_y) {
     return matvec_f64(*c, d_x, d_y, nullptr);
 }
 
+tt_status tt_matvec_batch(tt_ctx* const* systems, int count, const float* const* d_x, float* const* d_y,
+                          float* phase_ms) {
+    TT_GUARD(matvec_batch(systems, count, d_x, d_y, phase_ms));
+}
+
 tt_status tt_solve_frame(tt_ctx* ctx, const float* d_s, const double* d_x0, double* d_zeta, float* d_phi,
                          const tt_solve_opts* opts, tt_solve_info* info) {
     TT_GUARD(solve_impl(ctx, d_s, d_x0, d_zeta, d_phi, opts, info));

@@ -163,6 +163,10 @@ struct tt_ctx {
     int tile_S = 0, tile_elem = 0;      // split and element size the tiles were built for
     int tile_mf = -1;                   // column-transform mode the fragments were built for
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    DevBuf<c32> bU32;                   // batched product: column shares [Lh][S][C][n]
+    DevBuf<unsigned char> bdesc;        // batched product: per-system descriptors (first context of a call)
+    std::vector<unsigned char> bdesc_host;
+    hipEvent_t bev[4] = {nullptr, nullptr, nullptr, nullptr};   // batched product phase timing
     DevBuf<float> Minv32;               // circulant preconditioner spectra [Lh][L][C^2] (general Hermitian packing)
     DevBuf<double> Minv64;
     bool pc_ready = false;              // Minv built for the current system
@@ -178,6 +182,14 @@ struct tt_ctx {
     std::vector<double> gs, h, w;
     double r0 = 0, L0 = 0;
     std::vector<unsigned char> valid;
+
+    tt_ctx() = default;
+    tt_ctx(const tt_ctx&) = delete;
+    tt_ctx& operator=(const tt_ctx&) = delete;
+    ~tt_ctx() {
+        for (hipEvent_t e : {ev0, ev1, bev[0], bev[1], bev[2], bev[3]})
+            if (e) (void)hipEventDestroy(e);
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -196,6 +208,10 @@ tt_status table_spectra(const double* d_tables, long ntab, int m, int off, int L
 // matvec.hip
 tt_status matvec_f32(tt_ctx& c, const float* x, float* y, double* part);
 tt_status matvec_f64(tt_ctx& c, const double* x, double* y, double* part);
+
+// batch.hip
+tt_status matvec_batch(tt_ctx* const* systems, int count, const float* const* d_x, float* const* d_y,
+                       float* phase_ms);
 
 // cg.hip
 tt_status cg_alloc(tt_ctx& c);

@@ -29,8 +29,8 @@ MODEL_HUDGIN, MODEL_FRIED = 0, 1
 # Every function declared in include/tt.h.
 EXPORTED = (
     "tt_create", "tt_destroy", "tt_generate_kernels", "tt_kernels_destroy", "tt_kernels_copy",
-    "tt_set_system", "tt_set_noise_xy", "tt_set_mode_removal", "tt_get_system_info", "tt_matvec", "tt_matvec_f64", "tt_solve_frame",
-    "tt_solve_batch", "tt_project", "tt_status_string", "tt_last_error",
+    "tt_set_system", "tt_set_noise_xy", "tt_set_mode_removal", "tt_get_system_info", "tt_matvec", "tt_matvec_f64", "tt_matvec_batch",
+    "tt_solve_frame", "tt_solve_batch", "tt_project", "tt_status_string", "tt_last_error",
 )
 
 
@@ -314,6 +314,24 @@ def system_from(ctx: Context, wl, target: bool = True, pad_L: Optional[int] = No
     ctx.set_system(k, noise_scalar=wl.noise_var, target=(tuple(wl.target) if target else None),
                    n_prime=n_prime, proj_pad_L=proj_pad_L)
     return k
+
+
+def matvec_batch(contexts, xs, ys=None, timing: bool = False):
+    """tt_matvec_batch: ys[i] = A_i xs[i] (device float32 vectors) for every
+    context in one call on the stream of contexts[0].  With timing=True the
+    call waits and also returns the three phase durations in ms."""
+    import torch
+    m = len(contexts)
+    assert len(xs) == m
+    if ys is None:
+        ys = [torch.empty(c.info["n_slopes"], dtype=torch.float32, device=x.device) for c, x in zip(contexts, xs)]
+    arr = C.c_void_p * max(m, 1)
+    hs = arr(*[c._h for c in contexts])
+    xp = arr(*[_dptr(x, torch.float32, c.info["n_slopes"]) for c, x in zip(contexts, xs)])
+    yp = arr(*[_dptr(y, torch.float32, c.info["n_slopes"]) for c, y in zip(contexts, ys)])
+    ms = (C.c_float * 3)()
+    _check(load().tt_matvec_batch(hs, m, xp, yp, ms if timing else None))
+    return (ys, [float(v) for v in ms]) if timing else ys
 
 
 def solve_batch(contexts, slopes, tol: float = 1e-6, max_iter: int = 20000, precision: int = PREC_F32,

@@ -17,6 +17,8 @@ with the readings listed in each constructor):
       r0 = 0.157 m, L0 = 25 m, sigma^2 = 0.1 rad^2, L = 148.  3972 valid
       subapertures per sensor, 47 664 slopes.  Stands in for the HARMONI LTAO
       system of Table 2, whose 35-layer profile is only given as a figure.
+  lgs6_74x74_family(i)  the 74x74 geometry with seeded layer weights and r0 in
+      [0.10, 0.25] m: distinct systems for batched products (L = 256 by default).
   tiny(...)  small seeded variants (n = 2..8, 1-4 guide stars, NGS or LGS)
              used for exhaustive CPU checks.
 
@@ -27,6 +29,7 @@ variance sigma^2 is comparable with the slope variance.
 from __future__ import annotations
 
 import dataclasses
+import functools
 import math
 from typing import Optional
 
@@ -79,6 +82,11 @@ def pupil_mask(n: int, D: float, obstruction: float, supersample: int = 64) -> n
     """Valid-subaperture rule: a subaperture is kept when at least half of its
     area lies inside the annular pupil (outer diameter D, inner obstruction*D).
     Area fractions are measured on a supersample x supersample point grid."""
+    return _pupil_mask(int(n), float(D), float(obstruction), int(supersample)).copy()
+
+
+@functools.lru_cache(maxsize=32)
+def _pupil_mask(n: int, D: float, obstruction: float, supersample: int) -> np.ndarray:
     d = D / n
     t = (np.arange(supersample) + 0.5) / supersample
     valid = np.zeros((n, n), dtype=bool)
@@ -125,6 +133,23 @@ def lgs6_74x74(pad_L: int = 148) -> Workload:
     return Workload(
         name="lgs6_74x74", n=n, D=D, obstruction=obs, gs=ring(6, 60 * ARCSEC), h_lgs=90e3,
         h=h, w=w, r0=0.157, L0=25.0, noise_var=0.1, pad_L=pad_L,
+        valid=pupil_mask(n, D, obs))
+
+
+def lgs6_74x74_family(index: int, pad_L: int = 256) -> Workload:
+    """Distinct systems of the 74x74 / 6 LGS geometry for batched products: the
+    same pupil and asterism, the 35 altitudes of lgs6_74x74, layer weights drawn
+    with seed SEED + 1 + index and r0 uniform in [0.10, 0.25] m from the same
+    generator.  Index -1 is lgs6_74x74 itself (at this pad_L)."""
+    if index < 0:
+        return lgs6_74x74(pad_L=pad_L)
+    n, D, obs = 74, 39.0, 0.28
+    seed = SEED + 1 + int(index)
+    h, w = c2_profile(seed=seed)
+    r0 = 0.10 + 0.15 * float(np.random.default_rng(seed).random(36)[35])
+    return Workload(
+        name=f"lgs6_74x74_v{index}", n=n, D=D, obstruction=obs, gs=ring(6, 60 * ARCSEC), h_lgs=90e3,
+        h=h, w=w, r0=r0, L0=25.0, noise_var=0.1, pad_L=pad_L,
         valid=pupil_mask(n, D, obs))
 
 
