@@ -18,6 +18,9 @@ spectra, plus the preconditioner spectra when preconditioned, + slopes in and
 out) times iterations per launch, over the launch duration measured with HIP
 events on the library's stream.  The cpu_baseline object
 times the FP64 oracle (CG with its step-by-step 2RBT product) on one frame.
+The batch_matvec object measures the product of 64 distinct systems of the same
+geometry per call (tt_matvec_batch, L = 256): the HBM-bound form of the
+product, with its own roofline for the batched column kernel.
 """
 import argparse
 import json
@@ -48,6 +51,11 @@ def parse():
     ap.add_argument("--preconditioner", choices=["circulant", "none"], default="circulant")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the FP64 / kernel-solver side numbers")
+    ap.add_argument("--batch", type=int, default=64,
+                    help="distinct 74x74 systems in the batched-product measurement (0: skip it)")
+    ap.add_argument("--batch-pad", type=int, default=256, help="FFT side L of the batched systems")
+    ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--batch-only", action="store_true", help="run only the batched-product measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 256 MiB device buffer 3 times (reference kernel for rocprofv3 "
                          "FETCH_SIZE / WRITE_SIZE scale factors)")
@@ -93,6 +101,79 @@ def cpu_baseline(wl, s_frame, tol):
     }
 
 
+def batch_traffic_record():
+    """HBM traffic of the batched column kernel measured with rocprofv3 counters
+    (profiles/k_bcol_*_traffic.md), valid only while its source is unchanged."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_bcol_f32_74x74_L256_x64_traffic.md")
+    src = os.path.join(ROOT, "paper_1806_07938_amd", "csrc", "batch.hip")
+    try:
+        rec = {}
+        for line in open(path):
+            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+                k, v = line.split(":", 1)
+                rec[k] = v.strip()
+        if rec.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+            return None
+        return float(rec["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def batch_matvec(args):
+    """tt_matvec_batch over args.batch distinct 74x74 / 6 LGS systems (seeded
+    layer weights and r0, L = args.batch_pad): spectra of all systems streamed
+    once per call.  Roofline of the column kernel: algorithmic bytes = the
+    packed FP32 spectra of every system, over its HIP-event duration."""
+    import torch
+    import workloads as W
+    from paper_1806_07938_amd import Context, matvec_batch, system_from
+    dev = torch.device("cuda:0")
+    ctxs, keep, xs = [], [], []
+    rng = np.random.default_rng(1806)
+    t0 = time.perf_counter()
+    for i in range(args.batch):
+        wl = W.lgs6_74x74_family(i, pad_L=args.batch_pad)
+        c = Context(0)
+        keep.append(system_from(c, wl, target=False))
+        ctxs.append(c)
+        xs.append(torch.tensor(rng.standard_normal(wl.n_slopes).astype(np.float32), device=dev))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    ys = [torch.empty_like(x) for x in xs]
+    for _ in range(3):
+        matvec_batch(ctxs, xs, ys)
+    torch.cuda.synchronize()
+    phases = []
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        phases.append(matvec_batch(ctxs, xs, ys, timing=True)[1])
+    wall_ms = (time.perf_counter() - t0) * 1e3 / args.batch_steps
+    ph = np.array(phases).mean(axis=0)
+    spectra = float(sum(c.info["spectra_bytes_f32"] for c in ctxs))
+    slopes = float(sum(2 * 4 * c.info["n_slopes"] for c in ctxs))
+    col_gbs = spectra / (ph[1] * 1e-3) / 1e9
+    traffic = batch_traffic_record() if (args.batch == 64 and args.batch_pad == 256) else None
+    return {
+        "workload": (f"{args.batch} distinct 74x74 / 6 LGS / 35-layer systems (seeded layer weights, r0 in "
+                     f"[0.10, 0.25] m), L={args.batch_pad}, one FP32 product each per call"),
+        "systems": args.batch, "pad_L": args.batch_pad, "steps": args.batch_steps,
+        "ms_per_call_wall": round(wall_ms, 4),
+        "ms_per_call_gpu": round(float(ph.sum()), 4),
+        "us_per_system_product": round(float(ph.sum()) * 1e3 / args.batch, 3),
+        "phase_ms": {"row_fwd": round(float(ph[0]), 4), "col": round(float(ph[1]), 4),
+                     "row_inv": round(float(ph[2]), 4)},
+        "algorithmic_bytes": {"spectra": int(spectra), "slopes_in_out": int(slopes)},
+        "whole_product_gbs": round((spectra + slopes) / (ph.sum() * 1e-3) / 1e9, 1),
+        "roofline": {"bound": "hbm", "achieved": round(col_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(col_gbs / HBM_PEAK_GBS, 4), "traffic": round(traffic) if traffic else None,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
+                     "kernel": "k_bcol (batched column transforms and per-frequency products)",
+                     "avg_launch_ms": round(float(ph[1]), 4)},
+        "setup_s": round(setup_s, 1),
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -114,6 +195,9 @@ def main():
             cy.copy_(cx)
         torch.cuda.synchronize()
         del cx, cy
+    if args.batch_only:
+        print(json.dumps({"batch_matvec": batch_matvec(args)}), flush=True)
+        return
     wl = W.lgs6_74x74(pad_L=args.pad)
     frames = W.turbulent_slopes(wl, frames=args.frames).astype(np.float32)
 
@@ -233,6 +317,8 @@ def main():
                           "rel_residual": [float(f"{i.rel_residual:.3e}") for i in ii],
                           "converged": all(i.status == 0 and i.rel_residual <= args.tol for i in ii)}
         out["variants"] = side
+    if args.batch > 0:
+        out["batch_matvec"] = batch_matvec(args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, frames[0], args.tol)
     print(json.dumps(out), flush=True)

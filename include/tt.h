@@ -253,7 +253,7 @@ tt_status tt_matvec_f64(tt_ctx* ctx, const double* d_x, double* d_y);
  * limited by the column phase: with S = 2 if every pad_L is even, else 1,
  * (pad_L / S) * n_gs <= 2048 and the LDS of one column item, 4 (pad_L / S)
  * (3 n_gs^2 + 1) + 16 n_gs (pad_L / S) (twice that when pad_L / S is not a
- * power of two) + 8 pad_L bytes, at most 160 KiB.
+ * power of two) + 8 max(pad_L) bytes, at most 160 KiB.
  * All work is enqueued on the stream of systems[0] (three launches: row
  * transforms, column transforms with the per-frequency products, inverse row
  * transforms), in the per-system work buffers of each context: order the call

@@ -31,12 +31,14 @@
 #include "tt_internal.h"
 
 #include <algorithm>
+#include <cstring>
 
 namespace {
 
-constexpr int BT = 256;     // threads of a column work item
-constexpr int NPF = 64;     // spectra floats prefetched per thread and round
-constexpr int TMAX = 8;     // (frequency, sensor) product tasks per thread at most
+constexpr int BT = 512;     // threads of a column work item (two items per CU, four waves per SIMD)
+constexpr int NPF = 8;      // spectra vectors (VEC floats each) prefetched per thread and round
+constexpr int TMAX = 4;     // (frequency, sensor) product tasks per thread at most
+constexpr int TPF = 2;      // entries of the input column prefetched per thread
 
 struct BSys {
     const float* x;
@@ -49,27 +51,17 @@ struct BSys {
     const float* noise;
     const float* nxy;  // NULL unless the noise has 2x2 blocks
     int n, G, L, n_vs;
-    int row0, col0;    // first flat row (C n per system) and column (L/2 + 1 per system)
+    int col0;          // first flat column of this system (L/2 + 1 columns per system)
 };
 
-// largest b with start(b) <= idx (starts increase with b)
-__device__ inline int find_sys(const BSys* __restrict__ d, int count, int idx, bool by_row) {
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        const int st = by_row ? d[mid].row0 : d[mid].col0;
-        if (st <= idx) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-__global__ void k_brow_fwd(const BSys* __restrict__ sys, int count) {
+// row phases: grid (row, system); rows beyond a system's C n exit
+__global__ void k_brow_fwd(const BSys* __restrict__ sys) {
     __shared__ float xs[512];
     __shared__ c32 tws[1024];
-    const BSys s = sys[find_sys(sys, count, blockIdx.x, true)];
-    const int row = blockIdx.x - s.row0;
+    const BSys s = sys[blockIdx.y];
+    const int row = blockIdx.x;
     const int n = s.n, L = s.L, Lh = L / 2 + 1, C = 2 * s.G;
+    if (row >= C * n) return;
     const int c = row / n, a = row % n;
     for (int b = threadIdx.x; b < n; b += blockDim.x) {
         const int v = s.vmap[a * n + b];
@@ -98,231 +90,427 @@ __device__ inline c32 cmulc(c32 a, c32 b) { return c32{a.x * b.x + a.y * b.y, a.
 // flight (a full __syncthreads would also wait for them).
 __device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-// the spectra are read through a global-address-space pointer so that the
-// loads are counted apart from LDS traffic
-typedef const __attribute__((address_space(1))) float* gfloat_ptr;
+
+// Global memory through global-address-space pointers: loads and stores are
+// then counted apart from LDS traffic (a generic access would make every LDS
+// wait also wait for it).
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ inline c32 gload(const c32* p) {
+    const f2v t = *(const __attribute__((address_space(1))) f2v*)p;
+    return c32{t.x, t.y};
+}
+__device__ inline void gstore(c32* p, c32 v) { *(__attribute__((address_space(1))) f2v*)p = f2v{v.x, v.y}; }
 
 __device__ inline int bitrev(int v, int bits) {
     return bits ? (int)(__builtin_bitreverse32((unsigned)v) >> (32 - bits)) : 0;
 }
 
-// in-place radix-2 decimation-in-time transform of C arrays of length m
-// (input in bit-reversed order, output in natural order); twiddles w_L^{j L/(2hs)}
-template <bool INV>
-__device__ void fft_inplace(c32* A, const c32* tws, int C, int m, int L) {
-    const int half = m >> 1;
-    for (int hs = 1; hs < m; hs <<= 1) {
-        const int step = L / (2 * hs);
-        for (int bf = threadIdx.x; bf < C * half; bf += BT) {
-            const int c = bf / half, r = bf - c * half;
-            const int grp = r / hs, j = r - grp * hs;
-            const int i0 = c * m + grp * 2 * hs + j, i1 = i0 + hs;
-            const c32 w = tws[j * step];
-            const c32 u = A[i0];
-            const c32 v = INV ? cmul(A[i1], w) : cmulc(A[i1], w);
-            A[i0] = c32{u.x + v.x, u.y + v.y};
-            A[i1] = c32{u.x - v.x, u.y - v.y};
+__device__ inline c32 cadd(c32 a, c32 b) { return c32{a.x + b.x, a.y + b.y}; }
+__device__ inline c32 csub(c32 a, c32 b) { return c32{a.x - b.x, a.y - b.y}; }
+__device__ inline c32 mul_mi(c32 a) { return c32{a.y, -a.x}; }   // a (-i)
+__device__ inline c32 mul_pi(c32 a) { return c32{-a.y, a.x}; }   // a (+i)
+
+// Forward transform of C arrays of length m = 2^bits in place: radix-2
+// decimation in frequency, natural-order input, bit-reversed output.  Two
+// stages per pass (half spans H and H/2 on the four entries j, j + H/2, j + H,
+// j + 3H/2 of a block of 2H), a last single stage when bits is odd.  Entries at
+// or beyond nin are zero and are not read (first pass only).
+__device__ void fft_dif(c32* A, const c32* tws, int C, int bits, int L, int nin) {
+    const int m = 1 << bits;
+    int H = m >> 1, lH = bits - 1;
+    bool first = true;
+    while (H >= 2) {
+        const int q = H >> 1, lq = lH - 1;
+        const int nb = C << (bits - 2);
+        const int step = L >> (lH + 1);                 // w_{2H}^j = conj(tws[j step])
+        for (int b = threadIdx.x; b < nb; b += BT) {
+            const int c = b >> (bits - 2), r = b & ((m >> 2) - 1);
+            const int j = r & (q - 1);
+            const int p0 = ((r >> lq) << (lH + 1)) + j;
+            c32* a = A + (c << bits);
+            const c32 z = c32{0.f, 0.f};
+            const c32 x0 = (!first || p0 < nin) ? a[p0] : z;
+            const c32 x1 = (!first || p0 + q < nin) ? a[p0 + q] : z;
+            const c32 x2 = (!first || p0 + H < nin) ? a[p0 + H] : z;
+            const c32 x3 = (!first || p0 + H + q < nin) ? a[p0 + H + q] : z;
+            const c32 w1 = tws[j * step], w2 = tws[2 * j * step];
+            const c32 t0 = cadd(x0, x2), t2 = cmulc(csub(x0, x2), w1);
+            const c32 t1 = cadd(x1, x3), t3 = mul_mi(cmulc(csub(x1, x3), w1));
+            a[p0] = cadd(t0, t1);
+            a[p0 + q] = cmulc(csub(t0, t1), w2);
+            a[p0 + H] = cadd(t2, t3);
+            a[p0 + H + q] = cmulc(csub(t2, t3), w2);
+        }
+        lds_barrier();
+        H >>= 2;
+        lH -= 2;
+        first = false;
+    }
+    if (H == 1) {
+        for (int b = threadIdx.x; b < (C << (bits - 1)); b += BT) {
+            const int i0 = 2 * b, p = i0 & (m - 1);
+            const c32 z = c32{0.f, 0.f};
+            const c32 u = (!first || p < nin) ? A[i0] : z;
+            const c32 v = (!first || p + 1 < nin) ? A[i0 + 1] : z;
+            A[i0] = cadd(u, v);
+            A[i0 + 1] = csub(u, v);
         }
         lds_barrier();
     }
 }
 
-__global__ __launch_bounds__(BT) void k_bcol(const BSys* __restrict__ sys, int count, int total_cols, int S) {
-    extern __shared__ __align__(16) char smem_raw[];
-    // column work item: workgroups 8 apart share an XCD
-    const int id = blockIdx.x, xcd = id & 7, slot = id >> 3;
-    const int col = (slot / S) * 8 + xcd, h = slot % S;
-    if (col >= total_cols) return;
-    const BSys s = sys[find_sys(sys, count, col, false)];
-    const int f2 = col - s.col0;
-    const int n = s.n, G = s.G, C = 2 * G, L = s.L, m = L / S, P = 3 * G * G, Pst = P + 1;
-    const bool fft = (m & (m - 1)) == 0;
-    int bits = 0;
-    while ((1 << bits) < m) ++bits;
-
-    float* Ms = reinterpret_cast<float*>(smem_raw);
-    const size_t ms_bytes = (((size_t)m * Pst * sizeof(float)) + 15) & ~size_t(15);
-    c32* A = reinterpret_cast<c32*>(smem_raw + ms_bytes);     // C x m
-    c32* B = A + (size_t)C * m;                               // C x m (plain-sum transforms only)
-    c32* tws = fft ? B : B + (size_t)C * m;                   // L twiddles
-
-    // twisted input column, zero-padded to m (bit-reversed positions for the FFT)
-    for (int i = threadIdx.x; i < L; i += BT) tws[i] = s.tw[i];
-    __syncthreads();
-    const c32* Tc = s.T + (size_t)f2 * C * n;
-    for (int idx = threadIdx.x; idx < C * m; idx += BT) {
-        const int c = idx / m, a = idx - c * m;
-        c32 v = c32{0.f, 0.f};
-        if (a < n) {
-            v = Tc[c * n + a];
-            if (h) v = cmulc(v, tws[(h * a) % L]);
+// Inverse transform (unnormalised, exponent +) of C arrays of length m = 2^bits
+// in place: radix-2 decimation in time, bit-reversed input, natural output; a
+// first single stage when bits is odd, then two stages per pass (half spans h
+// and 2h on the entries j, j + h, j + 2h, j + 3h of a block of 4h).
+__device__ void fft_dit_inv(c32* A, const c32* tws, int C, int bits, int L) {
+    const int m = 1 << bits;
+    int h = 1, lh = 0;
+    if (bits & 1) {
+        for (int b = threadIdx.x; b < (C << (bits - 1)); b += BT) {
+            const int i0 = 2 * b;
+            const c32 u = A[i0], v = A[i0 + 1];
+            A[i0] = cadd(u, v);
+            A[i0 + 1] = csub(u, v);
         }
-        A[c * m + (fft ? bitrev(a, bits) : a)] = v;
+        lds_barrier();
+        h = 2;
+        lh = 1;
     }
-    __syncthreads();
-
-    // spectra of this item: float j < m P is entry w = j mod P of frequency
-    // k = j / P, i.e. of row S k + h of the column block: offset j + (S - 1) P k + h P.
-    // First round prefetched into registers here, consumed after the forward
-    // transform (the loads overlap it); an out-of-range lane reads the last
-    // entry of the item and discards it.
-    const gfloat_ptr Mcol = (gfloat_ptr)(s.M + (size_t)f2 * L * P);
-    const int Q = m * P;
-    const int dk = BT / P, dw = BT - dk * P;
-    const int k0 = threadIdx.x / P, w0 = threadIdx.x - k0 * P;
-    float pf[NPF];
-    {
-        int k = k0, w = w0;
-#pragma unroll
-        for (int i = 0; i < NPF; ++i) {
-            const int j = threadIdx.x + i * BT;
-            const int off = j < Q ? (S * k + h) * P + w : (S * (m - 1) + h) * P + P - 1;
-            pf[i] = Mcol[off];
-            w += dw;
-            const int cy = w >= P;
-            w -= cy ? P : 0;
-            k += dk + cy;
+    while (h < m) {
+        const int nb = C << (bits - 2);
+        const int sa = L >> (lh + 1), sb = L >> (lh + 2);   // w_{2h}^j = tws[j sa], w_{4h}^j = tws[j sb]
+        for (int b = threadIdx.x; b < nb; b += BT) {
+            const int c = b >> (bits - 2), r = b & ((m >> 2) - 1);
+            const int j = r & (h - 1);
+            const int p0 = ((r >> lh) << (lh + 2)) + j;
+            c32* a = A + (c << bits);
+            const c32 wa = tws[j * sa], wb = tws[j * sb];
+            const c32 x0 = a[p0], x1 = cmul(a[p0 + h], wa), x2 = a[p0 + 2 * h], x3 = cmul(a[p0 + 3 * h], wa);
+            const c32 t0 = cadd(x0, x1), t1 = csub(x0, x1), t2 = cadd(x2, x3), t3 = csub(x2, x3);
+            const c32 u2 = cmul(t2, wb), u3 = mul_pi(cmul(t3, wb));
+            a[p0] = cadd(t0, u2);
+            a[p0 + h] = cadd(t1, u3);
+            a[p0 + 2 * h] = csub(t0, u2);
+            a[p0 + 3 * h] = csub(t1, u3);
         }
-    }
-
-    // forward column transform of the C channels
-    c32* X = A;
-    if (fft) {
-        fft_inplace<false>(A, tws, C, m, L);
-    } else {
-        for (int idx = threadIdx.x; idx < C * m; idx += BT) {
-            const int c = idx / m, k = idx - c * m;
-            const c32* in = A + c * m;
-            float re = 0.f, im = 0.f;
-            int e = 0;
-            const int de = (S * k) % L;
-            for (int a = 0; a < n; ++a) {
-                const c32 t = in[a], w = tws[e];
-                re += t.x * w.x + t.y * w.y;
-                im += t.y * w.x - t.x * w.y;
-                e += de;
-                if (e >= L) e -= L;
-            }
-            B[idx] = c32{re, im};
-        }
-        X = B;
-    }
-
-    // spectra to LDS (first round from the prefetch, then round by round)
-    for (int base = 0; base < Q; base += NPF * BT) {
-        const int kb = (base + threadIdx.x) / P, wb = (base + threadIdx.x) - kb * P;
-        int k = kb, w = wb;
-        if (base) {
-#pragma unroll
-            for (int i = 0; i < NPF; ++i) {
-                const int j = base + threadIdx.x + i * BT;
-                const int off = j < Q ? (S * k + h) * P + w : (S * (m - 1) + h) * P + P - 1;
-                pf[i] = Mcol[off];
-                w += dw;
-                const int cy = w >= P;
-                w -= cy ? P : 0;
-                k += dk + cy;
-            }
-            k = kb;
-            w = wb;
-        }
-#pragma unroll
-        for (int i = 0; i < NPF; ++i) {
-            const int j = base + threadIdx.x + i * BT;
-            if (j < Q) Ms[k * Pst + w] = pf[i];
-            w += dw;
-            const int cy = w >= P;
-            w -= cy ? P : 0;
-            k += dk + cy;
-        }
-    }
-    __syncthreads();
-
-    // per-frequency products summed over the input channels: task (k, g) gives
-    // the x and y outputs of sensor g at frequency k
-    c32 yx[TMAX], yy[TMAX];
-#pragma unroll
-    for (int it = 0; it < TMAX; ++it) {
-        const int task = threadIdx.x + it * BT;
-        yx[it] = yy[it] = c32{0.f, 0.f};
-        if (task < m * G) {
-            const int g = task / m, k = task - g * m;
-            const float* Mf = Ms + k * Pst;
-            c32 ax = c32{0.f, 0.f}, ay = c32{0.f, 0.f};
-            for (int hh = 0; hh < G; ++hh) {
-                const c32 xh = X[(2 * hh) * m + k], yh = X[(2 * hh + 1) * m + k];
-                c32 mxx, mxy, myy;
-                if (hh == g) {
-                    mxx = c32{Mf[3 * g], 0.f};
-                    mxy = c32{Mf[3 * g + 1], 0.f};
-                    myy = c32{Mf[3 * g + 2], 0.f};
-                } else {
-                    const int lo = g < hh ? g : hh, hi = g < hh ? hh : g;
-                    const int sl = 3 * G + 6 * (lo * (2 * G - lo - 1) / 2 + (hi - lo - 1));
-                    const float sg = g < hh ? 1.f : -1.f;  // M_gh = conj(M_hg) for g > h
-                    mxx = c32{Mf[sl], sg * Mf[sl + 1]};
-                    mxy = c32{Mf[sl + 2], sg * Mf[sl + 3]};
-                    myy = c32{Mf[sl + 4], sg * Mf[sl + 5]};
-                }
-                const c32 p0 = cmul(mxx, xh), p1 = cmul(mxy, yh), p2 = cmul(mxy, xh), p3 = cmul(myy, yh);
-                ax.x += p0.x + p1.x;
-                ax.y += p0.y + p1.y;
-                ay.x += p2.x + p3.x;
-                ay.y += p2.y + p3.y;
-            }
-            yx[it] = ax;
-            yy[it] = ay;
-        }
-    }
-    __syncthreads();
-    c32* Y = A;   // the twisted input is no longer needed (FFT: X is A itself, read above)
-#pragma unroll
-    for (int it = 0; it < TMAX; ++it) {
-        const int task = threadIdx.x + it * BT;
-        if (task < m * G) {
-            const int g = task / m, k = task - g * m;
-            const int pos = fft ? bitrev(k, bits) : k;
-            Y[(2 * g) * m + pos] = yx[it];
-            Y[(2 * g + 1) * m + pos] = yy[it];
-        }
-    }
-    __syncthreads();
-
-    // this item's share of the inverse column transform, rows a < n
-    c32* Uo = s.U + ((size_t)f2 * S + h) * C * n;
-    if (fft) {
-        fft_inplace<true>(Y, tws, C, m, L);
-        for (int idx = threadIdx.x; idx < C * n; idx += BT) {
-            const int p = idx / n, a = idx - p * n;
-            c32 v = Y[p * m + a];
-            if (h) v = cmul(v, tws[(h * a) % L]);
-            Uo[idx] = v;
-        }
-    } else {
-        for (int idx = threadIdx.x; idx < C * n; idx += BT) {
-            const int p = idx / n, a = idx - p * n;
-            const c32* yv = Y + p * m;
-            float re = 0.f, im = 0.f;
-            int e = (h * a) % L;
-            const int de = (S * a) % L;
-            for (int k = 0; k < m; ++k) {
-                const c32 y = yv[k], w = tws[e];
-                re += y.x * w.x - y.y * w.y;
-                im += y.x * w.y + y.y * w.x;
-                e += de;
-                if (e >= L) e -= L;
-            }
-            Uo[idx] = c32{re, im};
-        }
+        lds_barrier();
+        h <<= 2;
+        lh += 2;
     }
 }
 
-__global__ void k_brow_inv(const BSys* __restrict__ sys, int count, int S) {
+// spectra of item (f2, h) of a system, in vectors of VEC floats (VEC = 4 when
+// P = 3 G^2 is a multiple of 4, else 1): vector j < m P / VEC is vector
+// w = j mod (P / VEC) of frequency k = j / (P / VEC), i.e. of row S k + h of the
+// column block.  One round covers NPF vectors per thread.
+template <int VEC> struct vecf;
+template <> struct vecf<1> { typedef float t; };
+template <> struct vecf<4> { typedef float t __attribute__((ext_vector_type(4))); };
+template <int VEC>
+using gvec_ptr = const __attribute__((address_space(1))) typename vecf<VEC>::t*;
+
+template <int VEC>
+__device__ __forceinline__ void spectra_load(typename vecf<VEC>::t (&pf)[NPF], const float* Mcol, int base, int Q,
+                                             int P, int S, int h) {
+    const int Pv = P / VEC;
+    const int dk = BT / Pv, dw = BT - dk * Pv;
+    int k = (base + (int)threadIdx.x) / Pv, w = (base + (int)threadIdx.x) - k * Pv;
+    const gvec_ptr<VEC> g = (gvec_ptr<VEC>)Mcol;
+#pragma unroll
+    for (int i = 0; i < NPF; ++i) {
+        if (base + (int)threadIdx.x + i * BT < Q) pf[i] = g[(S * k + h) * Pv + w];
+        w += dw;
+        const int cy = w >= Pv;
+        w -= cy ? Pv : 0;
+        k += dk + cy;
+    }
+}
+
+// the same round into LDS, frequency k at row k (P + 1) floats (padded stride),
+// or at row bitrev(k) when rbits >= 0 (the order of the forward FFT's output)
+template <int VEC>
+__device__ __forceinline__ void spectra_store(const typename vecf<VEC>::t (&pf)[NPF], float* Ms, int base, int Q,
+                                              int P, int rbits) {
+    const int Pv = P / VEC;
+    const int dk = BT / Pv, dw = BT - dk * Pv;
+    int k = (base + (int)threadIdx.x) / Pv, w = (base + (int)threadIdx.x) - k * Pv;
+#pragma unroll
+    for (int i = 0; i < NPF; ++i) {
+        if (base + (int)threadIdx.x + i * BT < Q) {
+            float* d = Ms + (rbits >= 0 ? bitrev(k, rbits) : k) * (P + 1) + w * VEC;
+            if constexpr (VEC == 4) {
+                d[0] = pf[i].x;
+                d[1] = pf[i].y;
+                d[2] = pf[i].z;
+                d[3] = pf[i].w;
+            } else {
+                d[0] = pf[i];
+            }
+        }
+        w += dw;
+        const int cy = w >= Pv;
+        w -= cy ? Pv : 0;
+        k += dk + cy;
+    }
+}
+
+// (row, column) of the flat index threadIdx.x + i BT of a rows x len array,
+// advanced without division
+struct Walk {
+    int r, c, dr, dc, len;
+    __device__ Walk(int len_) : len(len_) {
+        r = (int)threadIdx.x / len_;
+        c = (int)threadIdx.x - r * len_;
+        dr = BT / len_;
+        dc = BT - dr * len_;
+    }
+    __device__ void next() {
+        c += dc;
+        const int cy = c >= len;
+        c -= cy ? len : 0;
+        r += dr + cy;
+    }
+};
+
+// x and y outputs of sensor g at position k: sum over the sensors hh of the
+// 2x2 blocks M_{g hh} (Hermitian packing: real diagonal blocks, pairs g < hh
+// stored once, M_{g hh} = conj(M_{hh g}) for g > hh) times X_hh
+__device__ __forceinline__ void sensor_products(const float* Ms, const c32* X, int m, int P, int G, int g, int k,
+                                                c32& yx, c32& yy) {
+    const float* Mf = Ms + k * (P + 1);
+    c32 ax = c32{0.f, 0.f}, ay = c32{0.f, 0.f};
+    for (int hh = 0; hh < G; ++hh) {
+        const c32 xh = X[(2 * hh) * m + k], yh = X[(2 * hh + 1) * m + k];
+        c32 mxx, mxy, myy;
+        if (hh == g) {
+            mxx = c32{Mf[3 * g], 0.f};
+            mxy = c32{Mf[3 * g + 1], 0.f};
+            myy = c32{Mf[3 * g + 2], 0.f};
+        } else {
+            const int lo = g < hh ? g : hh, hi = g < hh ? hh : g;
+            const int o = 3 * G + 6 * (lo * (2 * G - lo - 1) / 2 + (hi - lo - 1));
+            const float sg = g < hh ? 1.f : -1.f;
+            mxx = c32{Mf[o], sg * Mf[o + 1]};
+            mxy = c32{Mf[o + 2], sg * Mf[o + 3]};
+            myy = c32{Mf[o + 4], sg * Mf[o + 5]};
+        }
+        ax = cadd(ax, cadd(cmul(mxx, xh), cmul(mxy, yh)));
+        ay = cadd(ay, cadd(cmul(mxy, xh), cmul(myy, yh)));
+    }
+    yx = ax;
+    yy = ay;
+}
+
+// Column work items q = 0, 1, ...: xcd = q mod 8, slot = q / 8, column
+// (slot / S) 8 + xcd, share h = slot mod S.  Workgroup b takes q = b, b + grid,
+// ... (grid a multiple of 8): all its items are on its own XCD, and the sibling
+// item q + 8 is processed by workgroup b + 8 at the same time.  The spectra of
+// the next item load under the products and inverse transform of the current.
+template <int VEC>
+__global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, const int* __restrict__ col_sys,
+                                                 int total_cols, int S, int Lmax) {
+    extern __shared__ __align__(16) char smem_raw[];
+    const int sh = S - 1;   // S is 1 or 2
+    int q = blockIdx.x;
+    int col = ((q >> 3) >> sh) * 8 + (q & 7), h = (q >> 3) & sh;
+    if (col >= total_cols) return;
+    c32* tws = reinterpret_cast<c32*>(smem_raw);   // twiddles of the current L
+    char* work = smem_raw + (((size_t)Lmax * sizeof(c32) + 15) & ~size_t(15));
+
+    // this item's spectra and input column, prefetched; the system of the next
+    // item is looked up one item ahead
+    typename vecf<VEC>::t pf[NPF];
+    c32 tp[TPF];
+    int si = col_sys[col];
+    {
+        const BSys& s0 = sys[si];
+        const int f20 = col - s0.col0, P0 = 3 * s0.G * s0.G, Cn0 = 2 * s0.G * s0.n;
+        spectra_load<VEC>(pf, s0.M + (size_t)f20 * s0.L * P0, 0, (s0.L >> sh) * P0 / VEC, P0, S, h);
+#pragma unroll
+        for (int i = 0; i < TPF; ++i) {
+            const int idx = threadIdx.x + i * BT;
+            if (idx < Cn0) tp[i] = gload(s0.T + (size_t)f20 * Cn0 + idx);
+        }
+    }
+    int qn = q + gridDim.x;
+    int coln = ((qn >> 3) >> sh) * 8 + (qn & 7);
+    int sin_ = coln < total_cols ? col_sys[coln] : 0;
+    int prevL = -1;
+    while (true) {
+        const BSys& s = sys[si];
+        const int f2 = col - s.col0;
+        const int n = s.n, G = s.G, C = 2 * G, L = s.L, m = L >> sh, P = 3 * G * G, Q = m * P;
+        const bool fft = (m & (m - 1)) == 0;
+        int bits = 0;
+        while ((1 << bits) < m) ++bits;
+        float* Ms = reinterpret_cast<float*>(work);
+        c32* A = reinterpret_cast<c32*>(work + ((((size_t)m * (P + 1) * sizeof(float)) + 15) & ~size_t(15)));
+        c32* B = A + (size_t)C * m;   // plain-sum transforms only
+        // next item: its system's fields are read now, used after this item's forward transform
+        const bool more = coln < total_cols;
+        const int hn = (qn >> 3) & sh;
+        const BSys& sn = sys[sin_];
+        const float* Mn = sn.M;
+        const c32* Tn = sn.T;
+        const int Ln = sn.L, Gn = sn.G, nn = sn.n, f2n = coln - sn.col0;
+
+        __syncthreads();   // the previous item's last LDS reads are done
+        if (L != prevL) {
+            for (int i = threadIdx.x; i < L; i += BT) tws[i] = gload(s.tw + i);
+            prevL = L;
+            __syncthreads();
+        }
+        // twisted input column (entries a >= n are zero and never read)
+        {
+            const c32* Tc = s.T + (size_t)f2 * C * n;
+            Walk wk(n);
+#pragma unroll
+            for (int i = 0; i < TPF; ++i, wk.next()) {
+                const int idx = threadIdx.x + i * BT;
+                if (idx < C * n) {
+                    c32 v = tp[i];
+                    if (h) v = cmulc(v, tws[wk.c]);   // w_L^{h a} with h = 1, a < L
+                    A[wk.r * m + wk.c] = v;
+                }
+            }
+            for (int idx = threadIdx.x + TPF * BT; idx < C * n; idx += BT, wk.next()) {
+                c32 v = gload(Tc + idx);
+                if (h) v = cmulc(v, tws[wk.c]);
+                A[wk.r * m + wk.c] = v;
+            }
+        }
+        __syncthreads();
+
+        // forward column transform of the C channels
+        c32* X = A;
+        if (fft) {
+            fft_dif(A, tws, C, bits, L, n);   // X at bit-reversed positions
+        } else {
+            Walk wk(m);
+            for (int idx = threadIdx.x; idx < C * m; idx += BT, wk.next()) {
+                const c32* in = A + wk.r * m;
+                float re = 0.f, im = 0.f;
+                int e = 0;
+                const int de = (S * wk.c) % L;
+                for (int a = 0; a < n; ++a) {
+                    const c32 t = in[a], w = tws[e];
+                    re += t.x * w.x + t.y * w.y;
+                    im += t.y * w.x - t.x * w.y;
+                    e += de;
+                    if (e >= L) e -= L;
+                }
+                B[idx] = c32{re, im};
+            }
+            X = B;
+        }
+
+        // this item's spectra to LDS: first round from the registers, then round by round
+        const float* Mcol = s.M + (size_t)f2 * L * P;
+        const int rbits = fft ? bits : -1;
+        spectra_store<VEC>(pf, Ms, 0, Q / VEC, P, rbits);
+        for (int base = NPF * BT; base < Q / VEC; base += NPF * BT) {
+            spectra_load<VEC>(pf, Mcol, base, Q / VEC, P, S, h);
+            spectra_store<VEC>(pf, Ms, base, Q / VEC, P, rbits);
+        }
+        __syncthreads();
+
+        // the next item's spectra and input column start loading, and the system
+        // of the item after it is looked up
+        int sinn = 0, qnn = qn + gridDim.x;
+        const int colnn = ((qnn >> 3) >> sh) * 8 + (qnn & 7);
+        if (more) {
+            const int Pn = 3 * Gn * Gn, Cnn = 2 * Gn * nn;
+            spectra_load<VEC>(pf, Mn + (size_t)f2n * Ln * Pn, 0, (Ln >> sh) * Pn / VEC, Pn, S, hn);
+#pragma unroll
+            for (int i = 0; i < TPF; ++i) {
+                const int idx = threadIdx.x + i * BT;
+                if (idx < Cnn) tp[i] = gload(Tn + (size_t)f2n * Cnn + idx);
+            }
+            if (colnn < total_cols) sinn = col_sys[colnn];
+        }
+
+        // per-frequency products summed over the input channels: task (g, k) gives
+        // the x and y outputs of sensor g at position k (frequency k, or bitrev(k)
+        // after the FFT: spectra rows and X share that order)
+        c32 yx[TMAX], yy[TMAX];
+        {
+            Walk wk(m);
+            const bool wave_uniform = (m & 63) == 0;   // the 64 tasks of a wave share g
+#pragma unroll
+            for (int it = 0; it < TMAX; ++it, wk.next()) {
+                const int task = threadIdx.x + it * BT;
+                yx[it] = yy[it] = c32{0.f, 0.f};
+                if (task < m * G) {
+                    if (wave_uniform)
+                        sensor_products(Ms, X, m, P, G, __builtin_amdgcn_readfirstlane(wk.r), wk.c, yx[it], yy[it]);
+                    else
+                        sensor_products(Ms, X, m, P, G, wk.r, wk.c, yx[it], yy[it]);
+                }
+            }
+        }
+        __syncthreads();
+        c32* Y = A;   // the twisted input is no longer needed (FFT: X is A itself, read above)
+        {
+            Walk wk(m);
+#pragma unroll
+            for (int it = 0; it < TMAX; ++it, wk.next()) {
+                const int task = threadIdx.x + it * BT;
+                if (task < m * G) {
+                    Y[(2 * wk.r) * m + wk.c] = yx[it];
+                    Y[(2 * wk.r + 1) * m + wk.c] = yy[it];
+                }
+            }
+        }
+        __syncthreads();
+
+        // this item's share of the inverse column transform, rows a < n
+        c32* Uo = s.U + ((size_t)f2 * S + h) * C * n;
+        if (fft) {
+            fft_dit_inv(Y, tws, C, bits, L);
+            Walk wk(n);
+            for (int idx = threadIdx.x; idx < C * n; idx += BT, wk.next()) {
+                const int a = wk.c;
+                c32 v = Y[wk.r * m + a];
+                if (h) v = cmul(v, tws[a]);
+                gstore(Uo + idx, v);
+            }
+        } else {
+            Walk wk(n);
+            for (int idx = threadIdx.x; idx < C * n; idx += BT, wk.next()) {
+                const int a = wk.c;
+                const c32* yv = Y + wk.r * m;
+                float re = 0.f, im = 0.f;
+                int e = h ? a : 0;
+                const int de = (S * a) % L;
+                for (int k = 0; k < m; ++k) {
+                    const c32 y = yv[k], w = tws[e];
+                    re += y.x * w.x - y.y * w.y;
+                    im += y.x * w.y + y.y * w.x;
+                    e += de;
+                    if (e >= L) e -= L;
+                }
+                gstore(Uo + idx, c32{re, im});
+            }
+        }
+        if (!more) break;
+        q = qn;
+        col = coln;
+        h = hn;
+        si = sin_;
+        qn = qnn;
+        coln = colnn;
+        sin_ = sinn;
+    }
+}
+
+__global__ void k_brow_inv(const BSys* __restrict__ sys, int S) {
     __shared__ c32 Us[513];
     __shared__ c32 tws[1024];
-    const BSys s = sys[find_sys(sys, count, blockIdx.x, true)];
-    const int row = blockIdx.x - s.row0;
+    const BSys s = sys[blockIdx.y];
+    const int row = blockIdx.x;
     const int n = s.n, L = s.L, Lh = L / 2 + 1, C = 2 * s.G;
+    if (row >= C * n) return;
     const int c = row / n, a = row % n;
     for (int f2 = threadIdx.x; f2 < Lh; f2 += blockDim.x) {
         c32 u = c32{0.f, 0.f};
@@ -356,12 +544,12 @@ __global__ void k_brow_inv(const BSys* __restrict__ sys, int count, int S) {
     }
 }
 
-size_t col_lds(int n, int G, int L, int S) {
+// LDS of one column item past the twiddles: spectra (padded), transform buffer(s)
+size_t col_work_lds(int G, int L, int S) {
     const int m = L / S, C = 2 * G, P = 3 * G * G;
     const bool fft = (m & (m - 1)) == 0;
     const size_t ms = (((size_t)m * (P + 1) * sizeof(float)) + 15) & ~size_t(15);
-    (void)n;
-    return ms + (size_t)C * m * sizeof(c32) * (fft ? 1 : 2) + (size_t)L * sizeof(c32);
+    return ms + (size_t)C * m * sizeof(c32) * (fft ? 1 : 2);
 }
 
 }  // namespace
@@ -369,7 +557,7 @@ size_t col_lds(int n, int G, int L, int S) {
 // Host side of tt_matvec_batch (see include/tt.h).
 tt_status matvec_batch(tt_ctx* const* systems, int count, const float* const* d_x, float* const* d_y,
                        float* phase_ms) {
-    TT_REQUIRE(count >= 0, "count must be >= 0");
+    TT_REQUIRE(count >= 0 && count <= 65535, "count must be in [0, 65535]");
     if (count == 0) return TT_OK;
     TT_REQUIRE(systems && d_x && d_y, "NULL argument");
     tt_ctx& c0 = *systems[0];
@@ -392,48 +580,79 @@ tt_status matvec_batch(tt_ctx* const* systems, int count, const float* const* d_
     int S = 2;
     for (int i = 0; i < count; ++i)
         if (systems[i]->L % 2) S = 1;
-    size_t lds = 0;
+    size_t work = 0;
+    int Lmax = 0, max_rows = 0;
     for (int i = 0; i < count; ++i) {
         const tt_ctx& c = *systems[i];
         TT_REQUIRE((long)(c.L / S) * c.G <= (long)TMAX * BT,
                    "system too large for the batched product: (L / S) * n_gs must be <= " +
                        std::to_string(TMAX * BT));
-        lds = std::max(lds, col_lds(c.n, c.G, c.L, S));
+        work = std::max(work, col_work_lds(c.G, c.L, S));
+        Lmax = std::max(Lmax, c.L);
+        max_rows = std::max(max_rows, c.C * c.n);
     }
+    const size_t lds = (((size_t)Lmax * sizeof(c32) + 15) & ~size_t(15)) + work;
     TT_REQUIRE(lds <= 160 * 1024, "system too large for the batched product: " + std::to_string(lds) +
                                       " bytes of LDS per column item");
     TT_HIP(hipSetDevice(c0.device));
 
+    // descriptors, then the system of every flat column; uploaded only when
+    // they differ from the last upload of this first context
     std::vector<BSys> d(count);
-    int rows = 0, cols = 0;
+    int cols = 0;
     for (int i = 0; i < count; ++i) {
         tt_ctx& c = *systems[i];
         const size_t ucount = (size_t)c.Lh * S * c.C * c.n;
         if (c.bU32.n < ucount) TT_CHECK(c.bU32.alloc(ucount));
         d[i] = BSys{d_x[i], d_y[i], c.vmap.p, c.tw32.p, c.T32.p, c.bU32.p, c.M32.p, c.noise32.p,
-                    c.has_nxy ? c.nxy32.p : nullptr, c.n, c.G, c.L, c.n_vs, rows, cols};
-        rows += c.C * c.n;
+                    c.has_nxy ? c.nxy32.p : nullptr, c.n, c.G, c.L, c.n_vs, cols};
         cols += c.Lh;
     }
-    const size_t bytes = sizeof(BSys) * (size_t)count;
-    if (c0.bdesc.n < bytes) TT_CHECK(c0.bdesc.alloc(bytes));
-    c0.bdesc_host.assign(reinterpret_cast<const unsigned char*>(d.data()),
-                         reinterpret_cast<const unsigned char*>(d.data()) + bytes);
-    TT_HIP(hipMemcpyAsync(c0.bdesc.p, c0.bdesc_host.data(), bytes, hipMemcpyHostToDevice, c0.stream));
+    const size_t dbytes = ((sizeof(BSys) * (size_t)count) + 15) & ~size_t(15);
+    std::vector<unsigned char> hb(dbytes + sizeof(int) * (size_t)cols, 0);
+    std::memcpy(hb.data(), d.data(), sizeof(BSys) * (size_t)count);
+    {
+        int* cs = reinterpret_cast<int*>(hb.data() + dbytes);
+        for (int i = 0, k = 0; i < count; ++i)
+            for (int f2 = 0; f2 < systems[i]->Lh; ++f2) cs[k++] = i;
+    }
+    if (c0.bdesc.n < hb.size()) {
+        TT_CHECK(c0.bdesc.alloc(hb.size()));
+        c0.bdesc_host.clear();
+    }
+    if (c0.bdesc_host != hb) {
+        c0.bdesc_host.swap(hb);
+        TT_HIP(hipMemcpyAsync(c0.bdesc.p, c0.bdesc_host.data(), c0.bdesc_host.size(), hipMemcpyHostToDevice,
+                              c0.stream));
+    }
     const BSys* dd = reinterpret_cast<const BSys*>(c0.bdesc.p);
+    const int* col_sys = reinterpret_cast<const int*>(c0.bdesc.p + dbytes);
 
-    TT_HIP(hipFuncSetAttribute((const void*)k_bcol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    const unsigned col_grid = (unsigned)(cdiv(cols, 8) * 8 * S);
+    // persistent column items: as many workgroups as fit at once (a multiple of 8);
+    // spectra in float4 when every 3 G^2 is a multiple of 4
+    bool vec4 = true;
+    for (int i = 0; i < count; ++i)
+        if ((3 * systems[i]->G * systems[i]->G) % 4) vec4 = false;
+    const void* kcol = vec4 ? (const void*)k_bcol<4> : (const void*)k_bcol<1>;
+    TT_HIP(hipFuncSetAttribute(kcol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int per_cu = 0;
+    TT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kcol, BT, lds));
+    const long items = (long)cdiv(cols, 8) * 8 * S;
+    const long fit = std::max(8L, (long)std::max(per_cu, 1) * std::max(c0.num_cu, 1) / 8 * 8);
+    const unsigned col_grid = (unsigned)std::min(items, fit);
     if (phase_ms && !c0.bev[0])
         for (auto& e : c0.bev) TT_HIP(hipEventCreate(&e));
     if (phase_ms) TT_HIP(hipEventRecord(c0.bev[0], c0.stream));
-    hipLaunchKernelGGL(k_brow_fwd, dim3(rows), dim3(128), 0, c0.stream, dd, count);
+    hipLaunchKernelGGL(k_brow_fwd, dim3(max_rows, count), dim3(128), 0, c0.stream, dd);
     TT_HIP(hipGetLastError());
     if (phase_ms) TT_HIP(hipEventRecord(c0.bev[1], c0.stream));
-    hipLaunchKernelGGL(k_bcol, dim3(col_grid), dim3(BT), lds, c0.stream, dd, count, cols, S);
+    if (vec4)
+        hipLaunchKernelGGL(k_bcol<4>, dim3(col_grid), dim3(BT), lds, c0.stream, dd, col_sys, cols, S, Lmax);
+    else
+        hipLaunchKernelGGL(k_bcol<1>, dim3(col_grid), dim3(BT), lds, c0.stream, dd, col_sys, cols, S, Lmax);
     TT_HIP(hipGetLastError());
     if (phase_ms) TT_HIP(hipEventRecord(c0.bev[2], c0.stream));
-    hipLaunchKernelGGL(k_brow_inv, dim3(rows), dim3(128), 0, c0.stream, dd, count, S);
+    hipLaunchKernelGGL(k_brow_inv, dim3(max_rows, count), dim3(128), 0, c0.stream, dd, S);
     TT_HIP(hipGetLastError());
     if (phase_ms) {
         TT_HIP(hipEventRecord(c0.bev[3], c0.stream));
