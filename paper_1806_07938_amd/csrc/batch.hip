@@ -54,32 +54,41 @@ struct BSys {
     int col0;          // first flat column of this system (L/2 + 1 columns per system)
 };
 
-// row phases: grid (row, system); rows beyond a system's C n exit
-__global__ void k_brow_fwd(const BSys* __restrict__ sys) {
-    __shared__ float xs[512];
+// Row phases: grid (row tile, system).  A workgroup takes RF (forward) or RI
+// (inverse) consecutive rows a of one channel c, so that for every f2 its
+// entries of T and U are contiguous in memory; tiles beyond a system's
+// channels exit.
+constexpr int RF = 16, RI = 8, RBT = 256;
+
+__global__ __launch_bounds__(RBT) void k_brow_fwd(const BSys* __restrict__ sys) {
+    __shared__ float xs[RF][513];
     __shared__ c32 tws[1024];
     const BSys s = sys[blockIdx.y];
-    const int row = blockIdx.x;
     const int n = s.n, L = s.L, Lh = L / 2 + 1, C = 2 * s.G;
-    if (row >= C * n) return;
-    const int c = row / n, a = row % n;
-    for (int b = threadIdx.x; b < n; b += blockDim.x) {
-        const int v = s.vmap[a * n + b];
-        xs[b] = v >= 0 ? s.x[(long)c * s.n_vs + v] : 0.f;
+    const int tiles = (n + RF - 1) / RF;
+    const int c = blockIdx.x / tiles, a0 = (blockIdx.x - c * tiles) * RF;
+    if (c >= C) return;
+    const int rows = min(RF, n - a0);
+    for (int i = threadIdx.x; i < rows * n; i += RBT) {
+        const int r = i / n, b = i - r * n;
+        const int v = s.vmap[(a0 + r) * n + b];
+        xs[r][b] = v >= 0 ? s.x[(long)c * s.n_vs + v] : 0.f;
     }
-    for (int k = threadIdx.x; k < L; k += blockDim.x) tws[k] = s.tw[k];
+    for (int k = threadIdx.x; k < L; k += RBT) tws[k] = s.tw[k];
     __syncthreads();
-    for (int f2 = threadIdx.x; f2 < Lh; f2 += blockDim.x) {
+    for (int idx = threadIdx.x; idx < Lh * RF; idx += RBT) {
+        const int f2 = idx / RF, r = idx - f2 * RF;
+        if (r >= rows) continue;
         float re = 0.f, im = 0.f;
         int m = 0;
         for (int b = 0; b < n; ++b) {
             const c32 w = tws[m];
-            re += xs[b] * w.x;
-            im -= xs[b] * w.y;
+            re += xs[r][b] * w.x;
+            im -= xs[r][b] * w.y;
             m += f2;
             if (m >= L) m -= L;
         }
-        s.T[((long)f2 * C + c) * n + a] = c32{re, im};
+        s.T[((long)f2 * C + c) * n + a0 + r] = c32{re, im};
     }
 }
 
@@ -504,34 +513,39 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
     }
 }
 
-__global__ void k_brow_inv(const BSys* __restrict__ sys, int S) {
-    __shared__ c32 Us[513];
+__global__ __launch_bounds__(RBT) void k_brow_inv(const BSys* __restrict__ sys, int S) {
+    __shared__ c32 Us[513][RI];
     __shared__ c32 tws[1024];
     const BSys s = sys[blockIdx.y];
-    const int row = blockIdx.x;
     const int n = s.n, L = s.L, Lh = L / 2 + 1, C = 2 * s.G;
-    if (row >= C * n) return;
-    const int c = row / n, a = row % n;
-    for (int f2 = threadIdx.x; f2 < Lh; f2 += blockDim.x) {
+    const int tiles = (n + RI - 1) / RI;
+    const int c = blockIdx.x / tiles, a0 = (blockIdx.x - c * tiles) * RI;
+    if (c >= C) return;
+    const int rows = min(RI, n - a0);
+    // the S column shares summed: U[f2][a0 + r] for r < rows, contiguous in r
+    for (int idx = threadIdx.x; idx < Lh * RI; idx += RBT) {
+        const int f2 = idx / RI, r = idx - f2 * RI;
         c32 u = c32{0.f, 0.f};
-        for (int h = 0; h < S; ++h) {
-            const c32 v = s.U[(((long)f2 * S + h) * C + c) * n + a];
-            u.x += v.x;
-            u.y += v.y;
-        }
-        Us[f2] = u;
+        if (r < rows)
+            for (int h = 0; h < S; ++h) {
+                const c32 v = s.U[(((long)f2 * S + h) * C + c) * n + a0 + r];
+                u.x += v.x;
+                u.y += v.y;
+            }
+        Us[f2][r] = u;
     }
-    for (int k = threadIdx.x; k < L; k += blockDim.x) tws[k] = s.tw[k];
+    for (int k = threadIdx.x; k < L; k += RBT) tws[k] = s.tw[k];
     __syncthreads();
     const float inv = 1.f / ((float)L * (float)L);
     const bool even = (L % 2) == 0;
-    for (int b = threadIdx.x; b < n; b += blockDim.x) {
-        const int v = s.vmap[a * n + b];
+    for (int idx = threadIdx.x; idx < rows * n; idx += RBT) {
+        const int r = idx / n, b = idx - r * n;
+        const int v = s.vmap[(a0 + r) * n + b];
         if (v < 0) continue;
-        float acc = Us[0].x;
+        float acc = Us[0][r].x;
         int m = b;
         for (int f2 = 1; f2 < Lh; ++f2) {
-            const c32 u = Us[f2], w = tws[m];
+            const c32 u = Us[f2][r], w = tws[m];
             const float wt = (even && 2 * f2 == L) ? 1.f : 2.f;
             acc += wt * (u.x * w.x - u.y * w.y);
             m += b;
@@ -581,7 +595,7 @@ tt_status matvec_batch(tt_ctx* const* systems, int count, const float* const* d_
     for (int i = 0; i < count; ++i)
         if (systems[i]->L % 2) S = 1;
     size_t work = 0;
-    int Lmax = 0, max_rows = 0;
+    int Lmax = 0, fwd_tiles = 0, inv_tiles = 0;
     for (int i = 0; i < count; ++i) {
         const tt_ctx& c = *systems[i];
         TT_REQUIRE((long)(c.L / S) * c.G <= (long)TMAX * BT,
@@ -589,7 +603,8 @@ tt_status matvec_batch(tt_ctx* const* systems, int count, const float* const* d_
                        std::to_string(TMAX * BT));
         work = std::max(work, col_work_lds(c.G, c.L, S));
         Lmax = std::max(Lmax, c.L);
-        max_rows = std::max(max_rows, c.C * c.n);
+        fwd_tiles = std::max(fwd_tiles, c.C * (int)cdiv(c.n, RF));
+        inv_tiles = std::max(inv_tiles, c.C * (int)cdiv(c.n, RI));
     }
     const size_t lds = (((size_t)Lmax * sizeof(c32) + 15) & ~size_t(15)) + work;
     TT_REQUIRE(lds <= 160 * 1024, "system too large for the batched product: " + std::to_string(lds) +
@@ -643,7 +658,7 @@ tt_status matvec_batch(tt_ctx* const* systems, int count, const float* const* d_
     if (phase_ms && !c0.bev[0])
         for (auto& e : c0.bev) TT_HIP(hipEventCreate(&e));
     if (phase_ms) TT_HIP(hipEventRecord(c0.bev[0], c0.stream));
-    hipLaunchKernelGGL(k_brow_fwd, dim3(max_rows, count), dim3(128), 0, c0.stream, dd);
+    hipLaunchKernelGGL(k_brow_fwd, dim3(fwd_tiles, count), dim3(RBT), 0, c0.stream, dd);
     TT_HIP(hipGetLastError());
     if (phase_ms) TT_HIP(hipEventRecord(c0.bev[1], c0.stream));
     if (vec4)
@@ -652,7 +667,7 @@ tt_status matvec_batch(tt_ctx* const* systems, int count, const float* const* d_
         hipLaunchKernelGGL(k_bcol<1>, dim3(col_grid), dim3(BT), lds, c0.stream, dd, col_sys, cols, S, Lmax);
     TT_HIP(hipGetLastError());
     if (phase_ms) TT_HIP(hipEventRecord(c0.bev[2], c0.stream));
-    hipLaunchKernelGGL(k_brow_inv, dim3(max_rows, count), dim3(128), 0, c0.stream, dd, S);
+    hipLaunchKernelGGL(k_brow_inv, dim3(inv_tiles, count), dim3(RBT), 0, c0.stream, dd, S);
     TT_HIP(hipGetLastError());
     if (phase_ms) {
         TT_HIP(hipEventRecord(c0.bev[3], c0.stream));
