@@ -151,3 +151,19 @@ def test_batch_74x74(family74):
     say("phase ms", ms)
     for wl, op, x, y in zip(wls, ops, xs, ys):
         assert rel_maxabs(y.cpu().numpy(), op(x.astype(np.float64))) < 3e-6, wl.name
+
+
+@pytest.mark.parametrize("cases", [
+    # G = 4 at L = 256 next to G = 3: float loads, 6144 spectra floats per item (two rounds)
+    [dict(n=7, n_gs=4, lgs=True, n_layer=2, seed=8, pad_L=256), ("lgs3_10x10", 20)],
+    # G = 8 at L = 256: float4 loads, 24576 floats per item (two rounds), 117 KB of LDS per item
+    [dict(n=3, n_gs=8, lgs=True, n_layer=2, seed=9, mask="full", pad_L=256),
+     dict(n=4, n_gs=2, lgs=False, n_layer=2, seed=10, pad_L=8)],
+], ids=["float", "float4"])
+def test_batch_spectra_in_several_rounds(cases):
+    from paper_1806_07938_amd import matvec_batch
+    wls, systems, xd, refs = _batch(cases, 11)
+    say("matvec batch, spectra in several rounds", [wl.name + f"/L{wl.pad_L}" for wl in wls])
+    ys = matvec_batch([s[0] for s in systems], xd)
+    for wl, y, ref in zip(wls, ys, refs):
+        assert rel_maxabs(y.cpu().numpy(), ref) < 3e-6, wl.name
