@@ -80,7 +80,14 @@ typedef enum {
 typedef enum {
     TT_SOLVER_PERSISTENT = 0, /* one persistent launch per solve segment, grid
                                  barriers between phases, on-device convergence */
-    TT_SOLVER_KERNELS = 1     /* one launch per phase, host polls convergence */
+    TT_SOLVER_KERNELS = 1,    /* one launch per phase, host polls convergence */
+    TT_SOLVER_BATCHED = 2     /* for tt_solve_batch: CG on every system of the call in
+                                 lockstep, each iteration's products by one batched
+                                 product (as tt_matvec_batch, whose size limits apply)
+                                 and the vector updates by kernels over all systems;
+                                 FP32 with the FP64 residual replacement per system,
+                                 TT_METHOD_CG, no preconditioner, no mode removal.
+                                 tt_solve_frame with it solves a batch of one. */
 } tt_solver_kind;
 
 typedef enum {
@@ -279,7 +286,11 @@ tt_status tt_solve_frame(tt_ctx* ctx, const float* d_s, const double* d_x0,
  * in size and geometry; contexts must not repeat).  For i < count, frame i is
  * tt_solve_frame(systems[i], d_s[i], d_x0 ? d_x0[i] : NULL, d_zeta[i],
  * d_phi ? d_phi[i] : NULL, opts, infos ? &infos[i] : NULL), in order, one
- * after another (each solve occupies the whole device).  Returns TT_OK when
+ * after another (each solve occupies the whole device) -- except with
+ * opts->solver == TT_SOLVER_BATCHED, where all frames iterate together and
+ * every context must be on one device (the work runs on the stream of
+ * systems[0] and on each context's own stream, the call waits for both).
+ * Returns TT_OK when
  * every frame did, else the first non-OK status in the order TT_BREAKDOWN,
  * TT_NOT_CONVERGED (all frames are still attempted and infos filled), or the
  * first argument / runtime error (later frames are then not attempted). */

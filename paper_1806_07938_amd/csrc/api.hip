@@ -170,18 +170,8 @@ tt_status set_system_impl(tt_ctx* c, const tt_kernels* k, const double* noise_va
     return TT_OK;
 }
 
-tt_status solve_impl(tt_ctx* c, const float* s, const double* x0, double* zeta, float* phi, const tt_solve_opts* opts,
-                     tt_solve_info* info) {
-    TT_REQUIRE(c && s && zeta, "NULL argument");
-    if (!c->ready) {
-        tt_set_error("tt_solve_frame: no system set");
-        return TT_NOT_READY;
-    }
-    if (phi && !c->proj.on) {
-        tt_set_error("tt_solve_frame: d_phi given but no target was set");
-        return TT_NOT_READY;
-    }
-    tt_solve_opts o;
+// Solve options with their defaults, checked against the context.
+tt_status parse_opts(const tt_ctx* c, const tt_solve_opts* opts, tt_solve_opts& o) {
     o.tol = 1e-6;
     o.max_iter = 20000;
     o.precision = TT_PREC_F32;
@@ -195,9 +185,10 @@ tt_status solve_impl(tt_ctx* c, const float* s, const double* x0, double* zeta, 
     TT_REQUIRE(o.precision == TT_PREC_F32 || o.precision == TT_PREC_F64 || o.precision == TT_PREC_F16 ||
                    o.precision == TT_PREC_BF16,
                "unknown precision");
+    TT_REQUIRE(o.solver == TT_SOLVER_PERSISTENT || o.solver == TT_SOLVER_KERNELS || o.solver == TT_SOLVER_BATCHED,
+               "unknown solver");
     TT_REQUIRE(o.solver == TT_SOLVER_PERSISTENT || (o.precision != TT_PREC_F16 && o.precision != TT_PREC_BF16),
                "TT_PREC_F16 / TT_PREC_BF16 need TT_SOLVER_PERSISTENT");
-    TT_REQUIRE(o.solver == TT_SOLVER_PERSISTENT || o.solver == TT_SOLVER_KERNELS, "unknown solver");
     TT_REQUIRE(std::isfinite(o.refine_drop) && o.refine_drop >= 0 && o.refine_drop < 1, "refine_drop in [0, 1)");
     TT_REQUIRE(o.preconditioner == TT_PRECOND_NONE || o.preconditioner == TT_PRECOND_CIRCULANT,
                "unknown preconditioner");
@@ -209,17 +200,30 @@ tt_status solve_impl(tt_ctx* c, const float* s, const double* x0, double* zeta, 
                    (o.solver == TT_SOLVER_PERSISTENT && o.preconditioner == TT_PRECOND_NONE &&
                     (o.precision == TT_PREC_F32 || o.precision == TT_PREC_F64)),
                "TT_METHOD_MINRES needs TT_SOLVER_PERSISTENT, TT_PREC_F32 or TT_PREC_F64 and no preconditioner");
+    TT_REQUIRE(o.solver != TT_SOLVER_BATCHED || o.precision == TT_PREC_F32,
+               "TT_SOLVER_BATCHED needs TT_PREC_F32");
     TT_REQUIRE(!c->modes || o.solver == TT_SOLVER_KERNELS, "mode removal needs TT_SOLVER_KERNELS");
-    TT_CHECK(use_device(c->device));
-    tt_solve_info inf{};
+    return TT_OK;
+}
 
-    if (o.solver == TT_SOLVER_PERSISTENT)
-        TT_CHECK(solve_persistent(*c, s, x0, zeta, o, inf));
-    else
-        TT_CHECK(solve_kernels(*c, s, x0, zeta, o, inf));
-    // mode removal: (M_s W_s)(Sigma_ss + Sigma_eta)(M_s W_s)^T zeta = M_s s with the
-    // product projected on both sides (matvec.hip) and every residual projected
-    // (cg.hip); the solution is projected at the end
+// context and output checks shared by tt_solve_frame and tt_solve_batch
+tt_status check_frame(const tt_ctx* c, const float* s, const double* zeta, const float* phi) {
+    TT_REQUIRE(c && s && zeta, "NULL argument");
+    if (!c->ready) {
+        tt_set_error("tt_solve_frame: no system set");
+        return TT_NOT_READY;
+    }
+    if (phi && !c->proj.on) {
+        tt_set_error("tt_solve_frame: d_phi given but no target was set");
+        return TT_NOT_READY;
+    }
+    return TT_OK;
+}
+
+// after the iterations: mode removal projects the solution (the system is
+// (M_s W_s)(Sigma_ss + Sigma_eta)(M_s W_s)^T zeta = M_s s, products projected on
+// both sides and every residual projected), then the projection phi
+tt_status finish_frame(tt_ctx* c, double* zeta, float* phi) {
     if (c->modes) {
         TT_CHECK(modes_project_f64(*c, zeta));
         TT_HIP(hipStreamSynchronize(c->stream));
@@ -228,6 +232,23 @@ tt_status solve_impl(tt_ctx* c, const float* s, const double* x0, double* zeta, 
         TT_CHECK(projection_apply(*c, zeta, phi));
         TT_HIP(hipStreamSynchronize(c->stream));
     }
+    return TT_OK;
+}
+
+tt_status solve_impl(tt_ctx* c, const float* s, const double* x0, double* zeta, float* phi, const tt_solve_opts* opts,
+                     tt_solve_info* info) {
+    TT_CHECK(check_frame(c, s, zeta, phi));
+    tt_solve_opts o;
+    TT_CHECK(parse_opts(c, opts, o));
+    TT_CHECK(use_device(c->device));
+    tt_solve_info inf{};
+    if (o.solver == TT_SOLVER_PERSISTENT)
+        TT_CHECK(solve_persistent(*c, s, x0, zeta, o, inf));
+    else if (o.solver == TT_SOLVER_KERNELS)
+        TT_CHECK(solve_kernels(*c, s, x0, zeta, o, inf));
+    else
+        TT_CHECK(solve_batched(&c, 1, &s, x0 ? &x0 : nullptr, &zeta, o, &inf));
+    TT_CHECK(finish_frame(c, zeta, phi));
     if (info) *info = inf;
     return (tt_status)inf.status;
 }
@@ -243,6 +264,26 @@ static tt_status batch_impl(tt_ctx* const* systems, int count, const float* cons
     for (int i = 0; i < count; ++i)
         for (int j = 0; j < i; ++j) TT_REQUIRE(systems[i] != systems[j], "a context appears twice in the batch");
     bool breakdown = false, notconv = false;
+    tt_solve_opts o;
+    if (count > 0) TT_CHECK(parse_opts(systems[0], opts, o));
+    if (count > 0 && o.solver == TT_SOLVER_BATCHED) {
+        // all systems iterate together (solve_batched); options checked for each
+        for (int i = 0; i < count; ++i) {
+            TT_CHECK(check_frame(systems[i], d_s[i], d_zeta[i], d_phi ? d_phi[i] : nullptr));
+            tt_solve_opts oi;
+            TT_CHECK(parse_opts(systems[i], opts, oi));
+        }
+        TT_CHECK(use_device(systems[0]->device));
+        std::vector<tt_solve_info> inf((size_t)count);
+        TT_CHECK(solve_batched(systems, count, d_s, d_x0, d_zeta, o, inf.data()));
+        for (int i = 0; i < count; ++i) {
+            TT_CHECK(finish_frame(systems[i], d_zeta[i], d_phi ? d_phi[i] : nullptr));
+            if (infos) infos[i] = inf[i];
+            if (inf[i].status == TT_BREAKDOWN) breakdown = true;
+            else if (inf[i].status == TT_NOT_CONVERGED) notconv = true;
+        }
+        return breakdown ? TT_BREAKDOWN : notconv ? TT_NOT_CONVERGED : TT_OK;
+    }
     for (int i = 0; i < count; ++i) {
         const tt_status st = solve_impl(systems[i], d_s[i], d_x0 ? d_x0[i] : nullptr, d_zeta[i],
                                         d_phi ? d_phi[i] : nullptr, opts, infos ? &infos[i] : nullptr);

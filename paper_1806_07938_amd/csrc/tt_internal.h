@@ -220,6 +220,10 @@ tt_status solve_kernels(tt_ctx& c, const float* s, const double* x0, double* zet
 tt_status solve_persistent(tt_ctx& c, const float* s, const double* x0, double* zeta,
                            const tt_solve_opts& o, tt_solve_info& info);
 
+// batch_solve.hip: lockstep FP32 CG over several systems (TT_SOLVER_BATCHED)
+tt_status solve_batched(tt_ctx* const* systems, int count, const float* const* d_s, const double* const* d_x0,
+                        double* const* d_zeta, const tt_solve_opts& o, tt_solve_info* infos);
+
 // precond.hip
 tt_status precond_build(tt_ctx& c);   // Minv32 / Minv64 of the current system (once per system)
 double precond_noise(const tt_ctx& c);

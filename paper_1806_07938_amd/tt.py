@@ -23,7 +23,7 @@ TT_OK, TT_INVALID_ARG, TT_HIP_ERROR, TT_OUT_OF_MEMORY, TT_NOT_CONVERGED, TT_BREA
 PREC_F32, PREC_F64, PREC_F16, PREC_BF16 = 0, 1, 2, 3
 PRECOND_NONE, PRECOND_CIRCULANT = 0, 1
 METHOD_CG, METHOD_MINRES = 0, 1
-SOLVER_PERSISTENT, SOLVER_KERNELS = 0, 1
+SOLVER_PERSISTENT, SOLVER_KERNELS, SOLVER_BATCHED = 0, 1, 2
 MODEL_HUDGIN, MODEL_FRIED = 0, 1
 
 # Every function declared in include/tt.h.
