@@ -20,7 +20,9 @@ events on the library's stream.  The cpu_baseline object
 times the FP64 oracle (CG with its step-by-step 2RBT product) on one frame.
 The batch_matvec object measures the product of 64 distinct systems of the same
 geometry per call (tt_matvec_batch, L = 256): the HBM-bound form of the
-product, with its own roofline for the batched column kernel.
+product, with its own roofline for the batched column kernel; batch_solve
+solves one frame on each of those systems together (TT_SOLVER_BATCHED) and
+reports the throughput in ms per solve.
 """
 import argparse
 import json
@@ -120,26 +122,58 @@ def batch_traffic_record():
         return None
 
 
-def batch_matvec(args):
-    """tt_matvec_batch over args.batch distinct 74x74 / 6 LGS systems (seeded
-    layer weights and r0, L = args.batch_pad): spectra of all systems streamed
-    once per call.  Roofline of the column kernel: algorithmic bytes = the
-    packed FP32 spectra of every system, over its HIP-event duration."""
+def batch_systems(args):
+    """args.batch distinct 74x74 / 6 LGS systems (seeded layer weights and r0,
+    L = args.batch_pad); returns (contexts, kernel objects, set-up seconds)."""
     import torch
     import workloads as W
-    from paper_1806_07938_amd import Context, matvec_batch, system_from
-    dev = torch.device("cuda:0")
-    ctxs, keep, xs = [], [], []
-    rng = np.random.default_rng(1806)
+    from paper_1806_07938_amd import Context, system_from
+    ctxs, keep = [], []
     t0 = time.perf_counter()
     for i in range(args.batch):
         wl = W.lgs6_74x74_family(i, pad_L=args.batch_pad)
         c = Context(0)
         keep.append(system_from(c, wl, target=False))
         ctxs.append(c)
-        xs.append(torch.tensor(rng.standard_normal(wl.n_slopes).astype(np.float32), device=dev))
     torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
+    return ctxs, keep, time.perf_counter() - t0
+
+
+def batch_solve(args, ctxs, frames):
+    """TT_SOLVER_BATCHED over the same systems: one frame each (the measured
+    frames of lgs6_74x74 reused in turn as right-hand sides), FP32 CG with the
+    FP64 residual replacement, to args.tol; one untimed batch, then one timed."""
+    import torch
+    from paper_1806_07938_amd import solve_batch
+    from paper_1806_07938_amd.tt import SOLVER_BATCHED, TT_NOT_CONVERGED
+    S = [torch.tensor(frames[i % len(frames)], device="cuda:0") for i in range(len(ctxs))]
+    solve_batch(ctxs, S, tol=args.tol, solver=SOLVER_BATCHED, allow=(0, TT_NOT_CONVERGED))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, infos, st = solve_batch(ctxs, S, tol=args.tol, solver=SOLVER_BATCHED, allow=(0, TT_NOT_CONVERGED))
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    it = np.array([i.iterations for i in infos], dtype=np.float64)
+    return {
+        "workload": (f"{len(ctxs)} distinct 74x74 / 6 LGS / 35-layer systems, L={args.batch_pad}, one frame each, "
+                     f"solved together (TT_SOLVER_BATCHED: plain CG in lockstep, FP32 + FP64 residual replacement) "
+                     f"to rel. residual {args.tol:g}"),
+        "systems": len(ctxs), "ms_per_batch": round(wall, 2), "ms_per_solve": round(wall / len(ctxs), 3),
+        "iterations_mean": round(float(it.mean()), 1), "iterations_max": int(it.max()),
+        "rel_residual_max": max(i.rel_residual for i in infos),
+        "all_converged": bool(st == 0 and all(i.status == 0 and i.rel_residual <= args.tol for i in infos)),
+    }
+
+
+def batch_matvec(args, ctxs, setup_s):
+    """tt_matvec_batch over the systems: spectra of all of them streamed once
+    per call.  Roofline of the column kernel: algorithmic bytes = the packed
+    FP32 spectra of every system, over its HIP-event duration."""
+    import torch
+    dev = torch.device("cuda:0")
+    from paper_1806_07938_amd import matvec_batch
+    rng = np.random.default_rng(1806)
+    xs = [torch.tensor(rng.standard_normal(c.info["n_slopes"]).astype(np.float32), device=dev) for c in ctxs]
     ys = [torch.empty_like(x) for x in xs]
     for _ in range(3):
         matvec_batch(ctxs, xs, ys)
@@ -196,7 +230,8 @@ def main():
         torch.cuda.synchronize()
         del cx, cy
     if args.batch_only:
-        print(json.dumps({"batch_matvec": batch_matvec(args)}), flush=True)
+        bctx, bkeep, bsetup = batch_systems(args)
+        print(json.dumps({"batch_matvec": batch_matvec(args, bctx, bsetup)}), flush=True)
         return
     wl = W.lgs6_74x74(pad_L=args.pad)
     frames = W.turbulent_slopes(wl, frames=args.frames).astype(np.float32)
@@ -318,7 +353,9 @@ def main():
                           "converged": all(i.status == 0 and i.rel_residual <= args.tol for i in ii)}
         out["variants"] = side
     if args.batch > 0:
-        out["batch_matvec"] = batch_matvec(args)
+        bctx, bkeep, bsetup = batch_systems(args)
+        out["batch_matvec"] = batch_matvec(args, bctx, bsetup)
+        out["batch_solve"] = batch_solve(args, bctx, frames)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, frames[0], args.tol)
     print(json.dumps(out), flush=True)
