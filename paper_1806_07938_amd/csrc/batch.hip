@@ -54,44 +54,6 @@ struct BSys {
     int col0;          // first flat column of this system (L/2 + 1 columns per system)
 };
 
-// Row phases: grid (row tile, system).  A workgroup takes RF (forward) or RI
-// (inverse) consecutive rows a of one channel c, so that for every f2 its
-// entries of T and U are contiguous in memory; tiles beyond a system's
-// channels exit.
-constexpr int RF = 16, RI = 8, RBT = 256;
-
-__global__ __launch_bounds__(RBT) void k_brow_fwd(const BSys* __restrict__ sys) {
-    __shared__ float xs[RF][513];
-    __shared__ c32 tws[1024];
-    const BSys s = sys[blockIdx.y];
-    const int n = s.n, L = s.L, Lh = L / 2 + 1, C = 2 * s.G;
-    const int tiles = (n + RF - 1) / RF;
-    const int c = blockIdx.x / tiles, a0 = (blockIdx.x - c * tiles) * RF;
-    if (c >= C) return;
-    const int rows = min(RF, n - a0);
-    for (int i = threadIdx.x; i < rows * n; i += RBT) {
-        const int r = i / n, b = i - r * n;
-        const int v = s.vmap[(a0 + r) * n + b];
-        xs[r][b] = v >= 0 ? s.x[(long)c * s.n_vs + v] : 0.f;
-    }
-    for (int k = threadIdx.x; k < L; k += RBT) tws[k] = s.tw[k];
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < Lh * RF; idx += RBT) {
-        const int f2 = idx / RF, r = idx - f2 * RF;
-        if (r >= rows) continue;
-        float re = 0.f, im = 0.f;
-        int m = 0;
-        for (int b = 0; b < n; ++b) {
-            const c32 w = tws[m];
-            re += xs[r][b] * w.x;
-            im -= xs[r][b] * w.y;
-            m += f2;
-            if (m >= L) m -= L;
-        }
-        s.T[((long)f2 * C + c) * n + a0 + r] = c32{re, im};
-    }
-}
-
 __device__ inline c32 cmul(c32 a, c32 b) { return c32{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 __device__ inline c32 cmulc(c32 a, c32 b) { return c32{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y}; }  // a conj(b)
 
@@ -124,6 +86,7 @@ __device__ inline c32 mul_pi(c32 a) { return c32{-a.y, a.x}; }   // a (+i)
 // stages per pass (half spans H and H/2 on the four entries j, j + H/2, j + H,
 // j + 3H/2 of a block of 2H), a last single stage when bits is odd.  Entries at
 // or beyond nin are zero and are not read (first pass only).
+template <int NT>
 __device__ void fft_dif(c32* A, const c32* tws, int C, int bits, int L, int nin) {
     const int m = 1 << bits;
     int H = m >> 1, lH = bits - 1;
@@ -132,7 +95,7 @@ __device__ void fft_dif(c32* A, const c32* tws, int C, int bits, int L, int nin)
         const int q = H >> 1, lq = lH - 1;
         const int nb = C << (bits - 2);
         const int step = L >> (lH + 1);                 // w_{2H}^j = conj(tws[j step])
-        for (int b = threadIdx.x; b < nb; b += BT) {
+        for (int b = threadIdx.x; b < nb; b += NT) {
             const int c = b >> (bits - 2), r = b & ((m >> 2) - 1);
             const int j = r & (q - 1);
             const int p0 = ((r >> lq) << (lH + 1)) + j;
@@ -156,7 +119,7 @@ __device__ void fft_dif(c32* A, const c32* tws, int C, int bits, int L, int nin)
         first = false;
     }
     if (H == 1) {
-        for (int b = threadIdx.x; b < (C << (bits - 1)); b += BT) {
+        for (int b = threadIdx.x; b < (C << (bits - 1)); b += NT) {
             const int i0 = 2 * b, p = i0 & (m - 1);
             const c32 z = c32{0.f, 0.f};
             const c32 u = (!first || p < nin) ? A[i0] : z;
@@ -172,11 +135,12 @@ __device__ void fft_dif(c32* A, const c32* tws, int C, int bits, int L, int nin)
 // in place: radix-2 decimation in time, bit-reversed input, natural output; a
 // first single stage when bits is odd, then two stages per pass (half spans h
 // and 2h on the entries j, j + h, j + 2h, j + 3h of a block of 4h).
+template <int NT>
 __device__ void fft_dit_inv(c32* A, const c32* tws, int C, int bits, int L) {
     const int m = 1 << bits;
     int h = 1, lh = 0;
     if (bits & 1) {
-        for (int b = threadIdx.x; b < (C << (bits - 1)); b += BT) {
+        for (int b = threadIdx.x; b < (C << (bits - 1)); b += NT) {
             const int i0 = 2 * b;
             const c32 u = A[i0], v = A[i0 + 1];
             A[i0] = cadd(u, v);
@@ -189,7 +153,7 @@ __device__ void fft_dit_inv(c32* A, const c32* tws, int C, int bits, int L) {
     while (h < m) {
         const int nb = C << (bits - 2);
         const int sa = L >> (lh + 1), sb = L >> (lh + 2);   // w_{2h}^j = tws[j sa], w_{4h}^j = tws[j sb]
-        for (int b = threadIdx.x; b < nb; b += BT) {
+        for (int b = threadIdx.x; b < nb; b += NT) {
             const int c = b >> (bits - 2), r = b & ((m >> 2) - 1);
             const int j = r & (h - 1);
             const int p0 = ((r >> lh) << (lh + 2)) + j;
@@ -281,6 +245,147 @@ struct Walk {
         r += dr + cy;
     }
 };
+
+// Row phases: grid (row tile, system).  A workgroup takes consecutive rows a
+// of one channel c, so that for every f2 its entries of T and U are contiguous
+// in memory; tiles beyond a system's channels exit.  When L is a power of two
+// the row transforms are FFTs of length L (the passes of the column phase; the
+// forward one reads only the n nonzero inputs, the inverse one takes the half
+// spectrum weighted by 1 or 2 and keeps the real part), else plain sums.
+constexpr int RBT = 256;
+constexpr int RLDS = 33792;   // bytes of row data per workgroup
+
+__host__ __device__ inline bool is_pow2(int v) { return (v & (v - 1)) == 0; }
+__host__ __device__ inline int row_tile_fwd(int L) { return is_pow2(L) ? (RLDS / 8 / L < 16 ? RLDS / 8 / L : 16) : 16; }
+__host__ __device__ inline int row_tile_inv(int L) { return is_pow2(L) ? (RLDS / 8 / L < 16 ? RLDS / 8 / L : 16) : 8; }
+
+__global__ __launch_bounds__(RBT) void k_brow_fwd(const BSys* __restrict__ sys) {
+    __shared__ __align__(16) char lds[RLDS + 1024 * sizeof(c32)];
+    c32* tws = reinterpret_cast<c32*>(lds + RLDS);
+    const BSys s = sys[blockIdx.y];
+    const int n = s.n, L = s.L, Lh = L / 2 + 1, C = 2 * s.G;
+    const int rt = row_tile_fwd(L), tiles = (n + rt - 1) / rt;
+    const int c = blockIdx.x / tiles, a0 = (blockIdx.x - c * tiles) * rt;
+    if (c >= C) return;
+    const int rows = min(rt, n - a0);
+    for (int k = threadIdx.x; k < L; k += RBT) tws[k] = s.tw[k];
+    if (is_pow2(L)) {
+        int bits = 0;
+        while ((1 << bits) < L) ++bits;
+        c32* A = reinterpret_cast<c32*>(lds);   // rows x L
+        for (int i = threadIdx.x; i < rows * n; i += RBT) {
+            const int r = i / n, b = i - r * n;
+            const int v = s.vmap[(a0 + r) * n + b];
+            A[r * L + b] = c32{v >= 0 ? s.x[(long)c * s.n_vs + v] : 0.f, 0.f};
+        }
+        __syncthreads();
+        fft_dif<RBT>(A, tws, rows, bits, L, n);   // bit-reversed output
+        for (int idx = threadIdx.x; idx < Lh * rt; idx += RBT) {
+            const int f2 = idx / rt, r = idx - f2 * rt;
+            if (r < rows) s.T[((long)f2 * C + c) * n + a0 + r] = A[r * L + bitrev(f2, bits)];
+        }
+        return;
+    }
+    float* xs = reinterpret_cast<float*>(lds);   // rows x (n + 1)
+    const int ld = n + 1;
+    for (int i = threadIdx.x; i < rows * n; i += RBT) {
+        const int r = i / n, b = i - r * n;
+        const int v = s.vmap[(a0 + r) * n + b];
+        xs[r * ld + b] = v >= 0 ? s.x[(long)c * s.n_vs + v] : 0.f;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < Lh * rt; idx += RBT) {
+        const int f2 = idx / rt, r = idx - f2 * rt;
+        if (r >= rows) continue;
+        float re = 0.f, im = 0.f;
+        int m = 0;
+        for (int b = 0; b < n; ++b) {
+            const c32 w = tws[m];
+            re += xs[r * ld + b] * w.x;
+            im -= xs[r * ld + b] * w.y;
+            m += f2;
+            if (m >= L) m -= L;
+        }
+        s.T[((long)f2 * C + c) * n + a0 + r] = c32{re, im};
+    }
+}
+
+__global__ __launch_bounds__(RBT) void k_brow_inv(const BSys* __restrict__ sys, int S) {
+    __shared__ __align__(16) char lds[RLDS + 1024 * sizeof(c32)];
+    c32* tws = reinterpret_cast<c32*>(lds + RLDS);
+    const BSys s = sys[blockIdx.y];
+    const int n = s.n, L = s.L, Lh = L / 2 + 1, C = 2 * s.G;
+    const int rt = row_tile_inv(L), tiles = (n + rt - 1) / rt;
+    const int c = blockIdx.x / tiles, a0 = (blockIdx.x - c * tiles) * rt;
+    if (c >= C) return;
+    const int rows = min(rt, n - a0);
+    for (int k = threadIdx.x; k < L; k += RBT) tws[k] = s.tw[k];
+    const float inv = 1.f / ((float)L * (float)L);
+    const bool even = (L % 2) == 0;
+    // the S column shares summed: U[f2][a0 + r], contiguous in r
+    auto share = [&](int f2, int r) {
+        c32 u = c32{0.f, 0.f};
+        for (int h = 0; h < S; ++h) {
+            const c32 v = s.U[(((long)f2 * S + h) * C + c) * n + a0 + r];
+            u.x += v.x;
+            u.y += v.y;
+        }
+        return u;
+    };
+    if (is_pow2(L)) {
+        int bits = 0;
+        while ((1 << bits) < L) ++bits;
+        c32* A = reinterpret_cast<c32*>(lds);   // rows x L, bit-reversed input
+        for (int idx = threadIdx.x; idx < L * rt; idx += RBT) {
+            const int f = idx / rt, r = idx - f * rt;
+            if (r >= rows) continue;
+            c32 u = c32{0.f, 0.f};
+            if (f < Lh) {
+                u = share(f, r);
+                const float wt = (f == 0 || (even && 2 * f == L)) ? 1.f : 2.f;
+                u.x *= wt;
+                u.y *= wt;
+            }
+            A[r * L + bitrev(f, bits)] = u;
+        }
+        __syncthreads();
+        fft_dit_inv<RBT>(A, tws, rows, bits, L);
+        for (int idx = threadIdx.x; idx < rows * n; idx += RBT) {
+            const int r = idx / n, b = idx - r * n;
+            const int v = s.vmap[(a0 + r) * n + b];
+            if (v < 0) continue;
+            const long i = (long)c * s.n_vs + v;
+            float out = A[r * L + b].x * inv + s.noise[i] * s.x[i];
+            if (s.nxy) out += s.nxy[(long)(c >> 1) * s.n_vs + v] * s.x[(long)(c ^ 1) * s.n_vs + v];
+            s.y[i] = out;
+        }
+        return;
+    }
+    c32* Us = reinterpret_cast<c32*>(lds);   // Lh x rt
+    for (int idx = threadIdx.x; idx < Lh * rt; idx += RBT) {
+        const int f2 = idx / rt, r = idx - f2 * rt;
+        Us[idx] = r < rows ? share(f2, r) : c32{0.f, 0.f};
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < rows * n; idx += RBT) {
+        const int r = idx / n, b = idx - r * n;
+        const int v = s.vmap[(a0 + r) * n + b];
+        if (v < 0) continue;
+        float acc = Us[r].x;
+        int m = b;
+        for (int f2 = 1; f2 < Lh; ++f2) {
+            const c32 u = Us[f2 * rt + r], w = tws[m];
+            const float wt = (even && 2 * f2 == L) ? 1.f : 2.f;
+            acc += wt * (u.x * w.x - u.y * w.y);
+            m += b;
+            if (m >= L) m -= L;
+        }
+        const long i = (long)c * s.n_vs + v;
+        float out = acc * inv + s.noise[i] * s.x[i];
+        if (s.nxy) out += s.nxy[(long)(c >> 1) * s.n_vs + v] * s.x[(long)(c ^ 1) * s.n_vs + v];
+        s.y[i] = out;
+    }
+}
 
 // x and y outputs of sensor g at position k: sum over the sensors hh of the
 // 2x2 blocks M_{g hh} (Hermitian packing: real diagonal blocks, pairs g < hh
@@ -394,7 +499,7 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
         // forward column transform of the C channels
         c32* X = A;
         if (fft) {
-            fft_dif(A, tws, C, bits, L, n);   // X at bit-reversed positions
+            fft_dif<BT>(A, tws, C, bits, L, n);   // X at bit-reversed positions
         } else {
             Walk wk(m);
             for (int idx = threadIdx.x; idx < C * m; idx += BT, wk.next()) {
@@ -476,7 +581,7 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
         // this item's share of the inverse column transform, rows a < n
         c32* Uo = s.U + ((size_t)f2 * S + h) * C * n;
         if (fft) {
-            fft_dit_inv(Y, tws, C, bits, L);
+            fft_dit_inv<BT>(Y, tws, C, bits, L);
             Walk wk(n);
             for (int idx = threadIdx.x; idx < C * n; idx += BT, wk.next()) {
                 const int a = wk.c;
@@ -510,51 +615,6 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
         qn = qnn;
         coln = colnn;
         sin_ = sinn;
-    }
-}
-
-__global__ __launch_bounds__(RBT) void k_brow_inv(const BSys* __restrict__ sys, int S) {
-    __shared__ c32 Us[513][RI];
-    __shared__ c32 tws[1024];
-    const BSys s = sys[blockIdx.y];
-    const int n = s.n, L = s.L, Lh = L / 2 + 1, C = 2 * s.G;
-    const int tiles = (n + RI - 1) / RI;
-    const int c = blockIdx.x / tiles, a0 = (blockIdx.x - c * tiles) * RI;
-    if (c >= C) return;
-    const int rows = min(RI, n - a0);
-    // the S column shares summed: U[f2][a0 + r] for r < rows, contiguous in r
-    for (int idx = threadIdx.x; idx < Lh * RI; idx += RBT) {
-        const int f2 = idx / RI, r = idx - f2 * RI;
-        c32 u = c32{0.f, 0.f};
-        if (r < rows)
-            for (int h = 0; h < S; ++h) {
-                const c32 v = s.U[(((long)f2 * S + h) * C + c) * n + a0 + r];
-                u.x += v.x;
-                u.y += v.y;
-            }
-        Us[f2][r] = u;
-    }
-    for (int k = threadIdx.x; k < L; k += RBT) tws[k] = s.tw[k];
-    __syncthreads();
-    const float inv = 1.f / ((float)L * (float)L);
-    const bool even = (L % 2) == 0;
-    for (int idx = threadIdx.x; idx < rows * n; idx += RBT) {
-        const int r = idx / n, b = idx - r * n;
-        const int v = s.vmap[(a0 + r) * n + b];
-        if (v < 0) continue;
-        float acc = Us[0][r].x;
-        int m = b;
-        for (int f2 = 1; f2 < Lh; ++f2) {
-            const c32 u = Us[f2][r], w = tws[m];
-            const float wt = (even && 2 * f2 == L) ? 1.f : 2.f;
-            acc += wt * (u.x * w.x - u.y * w.y);
-            m += b;
-            if (m >= L) m -= L;
-        }
-        const long i = (long)c * s.n_vs + v;
-        float out = acc * inv + s.noise[i] * s.x[i];
-        if (s.nxy) out += s.nxy[(long)(c >> 1) * s.n_vs + v] * s.x[(long)(c ^ 1) * s.n_vs + v];
-        s.y[i] = out;
     }
 }
 
@@ -603,8 +663,8 @@ tt_status matvec_batch(tt_ctx* const* systems, int count, const float* const* d_
                        std::to_string(TMAX * BT));
         work = std::max(work, col_work_lds(c.G, c.L, S));
         Lmax = std::max(Lmax, c.L);
-        fwd_tiles = std::max(fwd_tiles, c.C * (int)cdiv(c.n, RF));
-        inv_tiles = std::max(inv_tiles, c.C * (int)cdiv(c.n, RI));
+        fwd_tiles = std::max(fwd_tiles, c.C * (int)cdiv(c.n, row_tile_fwd(c.L)));
+        inv_tiles = std::max(inv_tiles, c.C * (int)cdiv(c.n, row_tile_inv(c.L)));
     }
     const size_t lds = (((size_t)Lmax * sizeof(c32) + 15) & ~size_t(15)) + work;
     TT_REQUIRE(lds <= 160 * 1024, "system too large for the batched product: " + std::to_string(lds) +
