@@ -12,8 +12,9 @@
 //             f1 = S k + h, k < m = L / S.  As the input column is zero for
 //             a >= n and m >= n,
 //               X[S k + h] = sum_{a<n} (T[f2][c][a] w_L^{h a}) w_m^{k a},
-//             an m-point DFT of the twisted column: a radix-2 FFT in LDS when m
-//             is a power of two, the plain sum otherwise.  Products with the
+//             an m-point DFT of the twisted column: an FFT in LDS when m is a
+//             power of two (radix-2 decimation in frequency, output in
+//             bit-reversed order), the plain sum otherwise.  Products with the
 //             spectra of these m frequencies (Y_p = sum_q M_pq X_q, Hermitian
 //             packing), then this item's share of the inverse column transform
 //               U_h[f2][p][a] = w_L^{-h a} sum_k Y_p[k] w_m^{-k a},  a < n.
@@ -21,13 +22,15 @@
 //             restricted to the valid subapertures (S2, W_s).
 //
 // S = 2 when every L of the batch is even (then L >= 2n gives m >= n), else 1.
-// The two items of one column are given workgroup numbers 8 apart, which the
-// dispatcher places on the same XCD at nearly the same time, so the column of
-// T and the cache lines shared by neighbouring frequencies are read from HBM
-// once.  The spectra of an item are prefetched into registers with coalesced
-// loads while the forward transform runs, then stored to LDS with a padded
-// stride of 3G^2 + 1 floats per frequency (conflict-free reads when the lanes
-// of a wave take consecutive frequencies).
+// The two items of one column get item numbers 8 apart, which land on the same
+// XCD at nearly the same time, so the column of T and the cache lines shared
+// by neighbouring frequencies are read from HBM once.  Column workgroups are
+// persistent over their items: the spectra and input column of the next item
+// load into registers (coalesced) during the current item's products and
+// inverse transform, and are stored to LDS with a padded stride of 3G^2 + 1
+// floats per frequency (conflict-free reads when the lanes of a wave take
+// consecutive frequencies).  The row phases are FFTs of length L as well when
+// L is a power of two.
 #include "tt_internal.h"
 
 #include <algorithm>
