@@ -86,7 +86,9 @@ typedef enum {
                                  product (as tt_matvec_batch, whose size limits apply)
                                  and the vector updates by kernels over all systems;
                                  FP32 with the FP64 residual replacement per system,
-                                 TT_METHOD_CG, no preconditioner, no mode removal.
+                                 TT_METHOD_CG, no mode removal; TT_PRECOND_CIRCULANT
+                                 applies the block-circulant preconditioner batched in
+                                 the same way (spectra built once per context).
                                  tt_solve_frame with it solves a batch of one. */
 } tt_solver_kind;
 
@@ -110,9 +112,10 @@ typedef enum {
                                  Symmetric positive definite; built once per system (FP64,
                                  on the host) at the first solve that asks for it.  The
                                  paper leaves preconditioning open (§2.G).
-                                 TT_SOLVER_PERSISTENT with TT_PREC_F32 or TT_PREC_F64 only,
-                                 and a block's grid rows must fit its threads:
-                                 n * ceil(2 n_gs n / compute units) <= 512. */
+                                 TT_SOLVER_PERSISTENT with TT_PREC_F32 or TT_PREC_F64 (and a
+                                 block's grid rows must fit its threads:
+                                 n * ceil(2 n_gs n / compute units) <= 512), or
+                                 TT_SOLVER_BATCHED (FP32). */
 } tt_preconditioner;
 
 typedef enum {

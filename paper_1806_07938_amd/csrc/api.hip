@@ -192,9 +192,10 @@ tt_status parse_opts(const tt_ctx* c, const tt_solve_opts* opts, tt_solve_opts& 
     TT_REQUIRE(std::isfinite(o.refine_drop) && o.refine_drop >= 0 && o.refine_drop < 1, "refine_drop in [0, 1)");
     TT_REQUIRE(o.preconditioner == TT_PRECOND_NONE || o.preconditioner == TT_PRECOND_CIRCULANT,
                "unknown preconditioner");
-    TT_REQUIRE(o.preconditioner == TT_PRECOND_NONE ||
+    TT_REQUIRE(o.preconditioner == TT_PRECOND_NONE || o.solver == TT_SOLVER_BATCHED ||
                    (o.solver == TT_SOLVER_PERSISTENT && (o.precision == TT_PREC_F32 || o.precision == TT_PREC_F64)),
-               "TT_PRECOND_CIRCULANT needs TT_SOLVER_PERSISTENT with TT_PREC_F32 or TT_PREC_F64");
+               "TT_PRECOND_CIRCULANT needs TT_SOLVER_PERSISTENT with TT_PREC_F32 or TT_PREC_F64, or "
+               "TT_SOLVER_BATCHED");
     TT_REQUIRE(o.method == TT_METHOD_CG || o.method == TT_METHOD_MINRES, "unknown method");
     TT_REQUIRE(o.method == TT_METHOD_CG ||
                    (o.solver == TT_SOLVER_PERSISTENT && o.preconditioner == TT_PRECOND_NONE &&

@@ -358,7 +358,8 @@ __global__ __launch_bounds__(RBT) void k_brow_inv(const BSys* __restrict__ sys, 
             const int v = s.vmap[(a0 + r) * n + b];
             if (v < 0) continue;
             const long i = (long)c * s.n_vs + v;
-            float out = A[r * L + b].x * inv + s.noise[i] * s.x[i];
+            float out = A[r * L + b].x * inv;
+            if (s.noise) out += s.noise[i] * s.x[i];
             if (s.nxy) out += s.nxy[(long)(c >> 1) * s.n_vs + v] * s.x[(long)(c ^ 1) * s.n_vs + v];
             s.y[i] = out;
         }
@@ -384,7 +385,8 @@ __global__ __launch_bounds__(RBT) void k_brow_inv(const BSys* __restrict__ sys, 
             if (m >= L) m -= L;
         }
         const long i = (long)c * s.n_vs + v;
-        float out = acc * inv + s.noise[i] * s.x[i];
+        float out = acc * inv;
+        if (s.noise) out += s.noise[i] * s.x[i];
         if (s.nxy) out += s.nxy[(long)(c >> 1) * s.n_vs + v] * s.x[(long)(c ^ 1) * s.n_vs + v];
         s.y[i] = out;
     }
@@ -419,12 +421,40 @@ __device__ __forceinline__ void sensor_products(const float* Ms, const c32* X, i
     yy = ay;
 }
 
+// Entry (a, b) of the general Hermitian C x C matrix of one frequency packed
+// in C^2 reals: slot a = Re H[a][a]; for a < b, slots C + 2k and C + 2k + 1 =
+// Re, Im H[a][b] with k = a C - a (a + 1) / 2 + b - a - 1; H[b][a] = conj H[a][b].
+__device__ __forceinline__ c32 herm_entry(const float* Mf, int C, int a, int b) {
+    if (a == b) return c32{Mf[a], 0.f};
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    const int k = lo * C - lo * (lo + 1) / 2 + hi - lo - 1;
+    const float im = Mf[C + 2 * k + 1];
+    return c32{Mf[C + 2 * k], a < b ? im : -im};
+}
+
+// outputs 2g and 2g + 1 at position k of Y = H X (the block-circulant
+// preconditioner's per-frequency matrices)
+__device__ __forceinline__ void herm_products(const float* Ms, const c32* X, int m, int P, int C, int g, int k,
+                                              c32& y0, c32& y1) {
+    const float* Mf = Ms + k * (P + 1);
+    c32 a0 = c32{0.f, 0.f}, a1 = c32{0.f, 0.f};
+    for (int q = 0; q < C; ++q) {
+        const c32 xq = X[q * m + k];
+        a0 = cadd(a0, cmul(herm_entry(Mf, C, 2 * g, q), xq));
+        a1 = cadd(a1, cmul(herm_entry(Mf, C, 2 * g + 1, q), xq));
+    }
+    y0 = a0;
+    y1 = a1;
+}
+
 // Column work items q = 0, 1, ...: xcd = q mod 8, slot = q / 8, column
 // (slot / S) 8 + xcd, share h = slot mod S.  Workgroup b takes q = b, b + grid,
 // ... (grid a multiple of 8): all its items are on its own XCD, and the sibling
 // item q + 8 is processed by workgroup b + 8 at the same time.  The spectra of
 // the next item load under the products and inverse transform of the current.
-template <int VEC>
+// PACK 0: the slope-slope spectra (3 G^2 reals per frequency); PACK 1: the
+// preconditioner's general Hermitian spectra (C^2 reals per frequency)
+template <int VEC, int PACK>
 __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, const int* __restrict__ col_sys,
                                                  int total_cols, int S, int Lmax) {
     extern __shared__ __align__(16) char smem_raw[];
@@ -442,7 +472,7 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
     int si = col_sys[col];
     {
         const BSys& s0 = sys[si];
-        const int f20 = col - s0.col0, P0 = 3 * s0.G * s0.G, Cn0 = 2 * s0.G * s0.n;
+        const int f20 = col - s0.col0, P0 = PACK ? 4 * s0.G * s0.G : 3 * s0.G * s0.G, Cn0 = 2 * s0.G * s0.n;
         spectra_load<VEC>(pf, s0.M + (size_t)f20 * s0.L * P0, 0, (s0.L >> sh) * P0 / VEC, P0, S, h);
 #pragma unroll
         for (int i = 0; i < TPF; ++i) {
@@ -457,7 +487,7 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
     while (true) {
         const BSys& s = sys[si];
         const int f2 = col - s.col0;
-        const int n = s.n, G = s.G, C = 2 * G, L = s.L, m = L >> sh, P = 3 * G * G, Q = m * P;
+        const int n = s.n, G = s.G, C = 2 * G, L = s.L, m = L >> sh, P = PACK ? C * C : 3 * G * G, Q = m * P;
         const bool fft = (m & (m - 1)) == 0;
         int bits = 0;
         while ((1 << bits) < m) ++bits;
@@ -537,7 +567,7 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
         int sinn = 0, qnn = qn + gridDim.x;
         const int colnn = ((qnn >> 3) >> sh) * 8 + (qnn & 7);
         if (more) {
-            const int Pn = 3 * Gn * Gn, Cnn = 2 * Gn * nn;
+            const int Pn = PACK ? 4 * Gn * Gn : 3 * Gn * Gn, Cnn = 2 * Gn * nn;
             spectra_load<VEC>(pf, Mn + (size_t)f2n * Ln * Pn, 0, (Ln >> sh) * Pn / VEC, Pn, S, hn);
 #pragma unroll
             for (int i = 0; i < TPF; ++i) {
@@ -559,10 +589,18 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
                 const int task = threadIdx.x + it * BT;
                 yx[it] = yy[it] = c32{0.f, 0.f};
                 if (task < m * G) {
-                    if (wave_uniform)
-                        sensor_products(Ms, X, m, P, G, __builtin_amdgcn_readfirstlane(wk.r), wk.c, yx[it], yy[it]);
-                    else
-                        sensor_products(Ms, X, m, P, G, wk.r, wk.c, yx[it], yy[it]);
+                    if constexpr (PACK == 0) {
+                        if (wave_uniform)
+                            sensor_products(Ms, X, m, P, G, __builtin_amdgcn_readfirstlane(wk.r), wk.c, yx[it],
+                                            yy[it]);
+                        else
+                            sensor_products(Ms, X, m, P, G, wk.r, wk.c, yx[it], yy[it]);
+                    } else {
+                        if (wave_uniform)
+                            herm_products(Ms, X, m, P, C, __builtin_amdgcn_readfirstlane(wk.r), wk.c, yx[it], yy[it]);
+                        else
+                            herm_products(Ms, X, m, P, C, wk.r, wk.c, yx[it], yy[it]);
+                    }
                 }
             }
         }
@@ -622,8 +660,8 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
 }
 
 // LDS of one column item past the twiddles: spectra (padded), transform buffer(s)
-size_t col_work_lds(int G, int L, int S) {
-    const int m = L / S, C = 2 * G, P = 3 * G * G;
+size_t col_work_lds(int G, int L, int S, int pack) {
+    const int m = L / S, C = 2 * G, P = pack ? C * C : 3 * G * G;
     const bool fft = (m & (m - 1)) == 0;
     const size_t ms = (((size_t)m * (P + 1) * sizeof(float)) + 15) & ~size_t(15);
     return ms + (size_t)C * m * sizeof(c32) * (fft ? 1 : 2);
@@ -631,9 +669,11 @@ size_t col_work_lds(int G, int L, int S) {
 
 }  // namespace
 
-// Host side of tt_matvec_batch (see include/tt.h).
-tt_status matvec_batch(tt_ctx* const* systems, int count, const float* const* d_x, float* const* d_y,
-                       float* phase_ms) {
+// Host side of tt_matvec_batch (see include/tt.h), op 0, and of the batched
+// block-circulant preconditioner u = W_s S2 F^-1 (M_+ + sigma^2)^-1 F S1 W_s^T r,
+// op 1 (spectra built by precond_build; no noise term).
+tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x, float* const* d_y, int op,
+                      float* phase_ms) {
     TT_REQUIRE(count >= 0 && count <= 65535, "count must be in [0, 65535]");
     if (count == 0) return TT_OK;
     TT_REQUIRE(systems && d_x && d_y, "NULL argument");
@@ -647,6 +687,7 @@ tt_status matvec_batch(tt_ctx* const* systems, int count, const float* const* d_
         }
         TT_REQUIRE(systems[i]->device == c0.device, "all contexts of a batch must be on one device");
         TT_REQUIRE(!systems[i]->modes, "mode removal is not supported in a batch (use tt_matvec)");
+        TT_REQUIRE(op == 0 || systems[i]->pc_ready, "preconditioner spectra not built");
     }
     {
         std::vector<const tt_ctx*> sorted(systems, systems + count);
@@ -664,7 +705,7 @@ tt_status matvec_batch(tt_ctx* const* systems, int count, const float* const* d_
         TT_REQUIRE((long)(c.L / S) * c.G <= (long)TMAX * BT,
                    "system too large for the batched product: (L / S) * n_gs must be <= " +
                        std::to_string(TMAX * BT));
-        work = std::max(work, col_work_lds(c.G, c.L, S));
+        work = std::max(work, col_work_lds(c.G, c.L, S, op));
         Lmax = std::max(Lmax, c.L);
         fwd_tiles = std::max(fwd_tiles, c.C * (int)cdiv(c.n, row_tile_fwd(c.L)));
         inv_tiles = std::max(inv_tiles, c.C * (int)cdiv(c.n, row_tile_inv(c.L)));
@@ -682,8 +723,9 @@ tt_status matvec_batch(tt_ctx* const* systems, int count, const float* const* d_
         tt_ctx& c = *systems[i];
         const size_t ucount = (size_t)c.Lh * S * c.C * c.n;
         if (c.bU32.n < ucount) TT_CHECK(c.bU32.alloc(ucount));
-        d[i] = BSys{d_x[i], d_y[i], c.vmap.p, c.tw32.p, c.T32.p, c.bU32.p, c.M32.p, c.noise32.p,
-                    c.has_nxy ? c.nxy32.p : nullptr, c.n, c.G, c.L, c.n_vs, cols};
+        d[i] = BSys{d_x[i], d_y[i], c.vmap.p, c.tw32.p, c.T32.p, c.bU32.p, op ? c.Minv32.p : c.M32.p,
+                    op ? nullptr : c.noise32.p, (!op && c.has_nxy) ? c.nxy32.p : nullptr, c.n, c.G, c.L, c.n_vs,
+                    cols};
         cols += c.Lh;
     }
     const size_t dbytes = ((sizeof(BSys) * (size_t)count) + 15) & ~size_t(15);
@@ -694,24 +736,26 @@ tt_status matvec_batch(tt_ctx* const* systems, int count, const float* const* d_
         for (int i = 0, k = 0; i < count; ++i)
             for (int f2 = 0; f2 < systems[i]->Lh; ++f2) cs[k++] = i;
     }
-    if (c0.bdesc.n < hb.size()) {
-        TT_CHECK(c0.bdesc.alloc(hb.size()));
-        c0.bdesc_host.clear();
+    DevBuf<unsigned char>& db = c0.bdesc[op];
+    std::vector<unsigned char>& dh = c0.bdesc_host[op];
+    if (db.n < hb.size()) {
+        TT_CHECK(db.alloc(hb.size()));
+        dh.clear();
     }
-    if (c0.bdesc_host != hb) {
-        c0.bdesc_host.swap(hb);
-        TT_HIP(hipMemcpyAsync(c0.bdesc.p, c0.bdesc_host.data(), c0.bdesc_host.size(), hipMemcpyHostToDevice,
-                              c0.stream));
+    if (dh != hb) {
+        dh.swap(hb);
+        TT_HIP(hipMemcpyAsync(db.p, dh.data(), dh.size(), hipMemcpyHostToDevice, c0.stream));
     }
-    const BSys* dd = reinterpret_cast<const BSys*>(c0.bdesc.p);
-    const int* col_sys = reinterpret_cast<const int*>(c0.bdesc.p + dbytes);
+    const BSys* dd = reinterpret_cast<const BSys*>(db.p);
+    const int* col_sys = reinterpret_cast<const int*>(db.p + dbytes);
 
     // persistent column items: as many workgroups as fit at once (a multiple of 8);
     // spectra in float4 when every 3 G^2 is a multiple of 4
     bool vec4 = true;
     for (int i = 0; i < count; ++i)
-        if ((3 * systems[i]->G * systems[i]->G) % 4) vec4 = false;
-    const void* kcol = vec4 ? (const void*)k_bcol<4> : (const void*)k_bcol<1>;
+        if (!op && (3 * systems[i]->G * systems[i]->G) % 4) vec4 = false;   // C^2 is always a multiple of 4
+    const void* kcol = op ? (const void*)k_bcol<4, 1>
+                          : (vec4 ? (const void*)k_bcol<4, 0> : (const void*)k_bcol<1, 0>);
     TT_HIP(hipFuncSetAttribute(kcol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
     TT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kcol, BT, lds));
@@ -724,10 +768,12 @@ tt_status matvec_batch(tt_ctx* const* systems, int count, const float* const* d_
     hipLaunchKernelGGL(k_brow_fwd, dim3(fwd_tiles, count), dim3(RBT), 0, c0.stream, dd);
     TT_HIP(hipGetLastError());
     if (phase_ms) TT_HIP(hipEventRecord(c0.bev[1], c0.stream));
-    if (vec4)
-        hipLaunchKernelGGL(k_bcol<4>, dim3(col_grid), dim3(BT), lds, c0.stream, dd, col_sys, cols, S, Lmax);
+    if (op)
+        hipLaunchKernelGGL((k_bcol<4, 1>), dim3(col_grid), dim3(BT), lds, c0.stream, dd, col_sys, cols, S, Lmax);
+    else if (vec4)
+        hipLaunchKernelGGL((k_bcol<4, 0>), dim3(col_grid), dim3(BT), lds, c0.stream, dd, col_sys, cols, S, Lmax);
     else
-        hipLaunchKernelGGL(k_bcol<1>, dim3(col_grid), dim3(BT), lds, c0.stream, dd, col_sys, cols, S, Lmax);
+        hipLaunchKernelGGL((k_bcol<1, 0>), dim3(col_grid), dim3(BT), lds, c0.stream, dd, col_sys, cols, S, Lmax);
     TT_HIP(hipGetLastError());
     if (phase_ms) TT_HIP(hipEventRecord(c0.bev[2], c0.stream));
     hipLaunchKernelGGL(k_brow_inv, dim3(inv_tiles, count), dim3(RBT), 0, c0.stream, dd, S);
@@ -738,4 +784,9 @@ tt_status matvec_batch(tt_ctx* const* systems, int count, const float* const* d_
         for (int k = 0; k < 3; ++k) TT_HIP(hipEventElapsedTime(&phase_ms[k], c0.bev[k], c0.bev[k + 1]));
     }
     return TT_OK;
+}
+
+tt_status matvec_batch(tt_ctx* const* systems, int count, const float* const* d_x, float* const* d_y,
+                       float* phase_ms) {
+    return batch_apply(systems, count, d_x, d_y, 0, phase_ms);
 }

@@ -5,12 +5,18 @@
 // replacement and certification of row a10 are those of the single-system
 // path (cg.hip), per system, between chunks of iterations.
 //
-// Per system the recurrences are exactly those of TT_SOLVER_KERNELS in FP32:
+// Plain CG, per system the recurrences of TT_SOLVER_KERNELS in FP32:
 //   q = A p;  alpha = rr_j / (p . q);  x += alpha p;  r -= alpha q;
-//   rr_{j+1} = r . r;  beta = rr_{j+1} / rr_j;  p = r + beta p,
-// with FP64 dot products summed in a fixed order.  The iteration index of a
-// system within a chunk is its count at the chunk's start plus the step, so no
-// kernel reads a counter that another block of the same launch writes.
+//   rr_{j+1} = r . r;  beta = rr_{j+1} / rr_j;  p = r + beta p.
+// Preconditioned by the block-circulant inverse P (batched as the product):
+//   q = A p;  alpha = ru_j / (p . q);  x += alpha p;  r -= alpha q;  u = P r;
+//   ru_{j+1} = r . u;  beta = ru_{j+1} / ru_j;  p = u + beta p,
+// restarted from p = u = P r at every residual replacement; the stopping and
+// replacement tests use r . r as in plain CG.  FP64 dot products are summed in
+// a fixed order.  The iteration index of a system within a chunk is its count
+// at the chunk's start plus the step, and the scalars of iteration j + 1 go to
+// the other parity slot, so no kernel reads a value another block of the same
+// launch writes.
 #include "cg_common.h"
 
 #include <algorithm>
@@ -27,8 +33,10 @@ struct BVec {
     float* r;
     float* p;
     const float* q;
+    const float* u;  // P r (preconditioned)
     double* partA;   // VB partials of p . q
     double* partB;   // VB partials of r . r
+    double* partC;   // VB partials of r . u
     CgScalars* S;
     long n;
     int it0;         // iterations done at the start of the chunk
@@ -65,6 +73,42 @@ __global__ __launch_bounds__(VT) void k_bdot(const BVec* __restrict__ vs) {
     if (threadIdx.x == 0) d.partA[blockIdx.x] = s;
 }
 
+// grid (VB, systems): partC = r . u of this block's share (running systems, or
+// every system that has not stopped for good when starting)
+__global__ __launch_bounds__(VT) void k_bdot_ru(const BVec* __restrict__ vs, int starting) {
+    __shared__ double red[VT];
+    const BVec d = vs[blockIdx.y];
+    const int st = d.S->state;
+    if (starting ? (st == ST_BREAK || st == ST_CAP) : st != ST_RUN) return;
+    double v = 0.0;
+    for (long i = (long)blockIdx.x * VT + threadIdx.x; i < d.n; i += (long)VB * VT)
+        v += (double)d.r[i] * (double)d.u[i];
+    const double s = vblock_sum(v, red);
+    if (threadIdx.x == 0) d.partC[blockIdx.x] = s;
+}
+
+// (re)start of preconditioned CG at iteration it0: p = u, ru = r . u, and the
+// replacement bookkeeping (rr of this iteration = the FP64 true residual)
+__global__ __launch_bounds__(VT) void k_bpc_start(const BVec* __restrict__ vs) {
+    __shared__ double red[VT];
+    const BVec d = vs[blockIdx.y];
+    CgScalars* S = d.S;
+    if (S->state == ST_BREAK || S->state == ST_CAP) return;
+    const double ru = vsum_partials(d.partC, red);
+    if (!(ru > 0.0) || !isfinite(ru)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) S->state = ST_BREAK;
+        return;
+    }
+    for (long i = (long)blockIdx.x * VT + threadIdx.x; i < d.n; i += (long)VB * VT) d.p[i] = d.u[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        S->ru[d.it0 & 1] = ru;
+        S->rr[d.it0 & 1] = S->rr_true;
+        S->rr_max = S->rr_true;
+        S->state = ST_RUN;
+    }
+}
+
+template <bool PC>
 __global__ __launch_bounds__(VT) void k_bupdate_xr(const BVec* __restrict__ vs, int step) {
     __shared__ double red[VT];
     const BVec d = vs[blockIdx.y];
@@ -72,7 +116,7 @@ __global__ __launch_bounds__(VT) void k_bupdate_xr(const BVec* __restrict__ vs, 
     if (S->state != ST_RUN) return;
     const int it = d.it0 + step;
     const double pAp = vsum_partials(d.partA, red);
-    const double alpha = S->rr[it & 1] / pAp;
+    const double alpha = (PC ? S->ru[it & 1] : S->rr[it & 1]) / pAp;
     if (!(pAp > 0.0) || !isfinite(alpha)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             S->state = ST_BREAK;
@@ -121,26 +165,76 @@ __global__ __launch_bounds__(VT) void k_bupdate_p(const BVec* __restrict__ vs, i
     }
 }
 
+__global__ __launch_bounds__(VT) void k_bupdate_p_pc(const BVec* __restrict__ vs, int step, int max_iter) {
+    __shared__ double red[VT];
+    const BVec d = vs[blockIdx.y];
+    CgScalars* S = d.S;
+    if (S->state != ST_RUN) return;
+    const int it = d.it0 + step;
+    const double rn = vsum_partials(d.partB, red);
+    const double run = vsum_partials(d.partC, red);
+    const bool conv = rn <= S->tol2;
+    const bool refine = S->drop2 > 0.0 && rn < S->drop2 * S->rr_max;
+    const bool cap = it + 1 >= max_iter;
+    const bool bad = !isfinite(rn) || !(run > 0.0) || !isfinite(run);
+    if (conv || refine || cap || bad) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            S->rr[(it + 1) & 1] = rn;
+            S->iter = it + 1;
+            S->state = bad ? ST_BREAK : conv ? ST_CONV : refine ? ST_REFINE : ST_CAP;
+        }
+        return;
+    }
+    const float beta = (float)(run / S->ru[it & 1]);
+    for (long i = (long)blockIdx.x * VT + threadIdx.x; i < d.n; i += (long)VB * VT) d.p[i] = d.u[i] + beta * d.p[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        S->rr[(it + 1) & 1] = rn;
+        S->ru[(it + 1) & 1] = run;
+        S->iter = it + 1;
+    }
+}
+
 // the solver scalars of every system, gathered for one copy to the host
 __global__ void k_bgather(const BVec* __restrict__ vs, int count, CgScalars* __restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) out[i] = *vs[i].S;
 }
 
+
+// Preconditioned start of the systems in vs (count of them, on stream st):
+// u = P r, ru = r . u, p = u.
+tt_status pc_start(tt_ctx* const* act, int na, const std::vector<const float*>& pr, const std::vector<float*>& pu,
+                   const BVec* dvec, hipStream_t st) {
+    TT_CHECK(batch_apply(act, na, pr.data(), pu.data(), 1, nullptr));
+    hipLaunchKernelGGL(k_bdot_ru, dim3(VB, na), dim3(VT), 0, st, dvec, 1);
+    hipLaunchKernelGGL(k_bpc_start, dim3(VB, na), dim3(VT), 0, st, dvec);
+    TT_HIP(hipGetLastError());
+    return TT_OK;
+}
+
+BVec bvec_of(tt_ctx& c, int it0) {
+    return BVec{c.x32.p, c.r32.p, c.p32.p, c.q32.p, c.bu32.p, c.part.p, c.part.p + VB, c.part.p + 2 * VB,
+                cg_scalars(c), (long)c.n_slopes, it0, 0};
+}
+
 }  // namespace
 
-// Lockstep FP32 CG over systems[0..count) (contexts already validated: ready,
-// distinct, one device, no mode removal); infos[i] and zeta[i] as tt_solve_frame.
-// Returns TT_OK, or the first runtime error; per-system outcomes are in
-// infos[i].status.
+// Lockstep FP32 CG (plain, or preconditioned by the block-circulant inverse)
+// over systems[0..count) (contexts already validated: ready, distinct, one
+// device, no mode removal); infos[i] and zeta[i] as tt_solve_frame.  Returns
+// TT_OK, or the first runtime error; per-system outcomes are in infos[i].status.
 tt_status solve_batched(tt_ctx* const* systems, int count, const float* const* d_s, const double* const* d_x0,
                         double* const* d_zeta, const tt_solve_opts& o, tt_solve_info* infos) {
     if (count == 0) return TT_OK;
-    tt_ctx& c0 = *systems[0];
+    const bool pc = o.preconditioner == TT_PRECOND_CIRCULANT;
     std::vector<CgScalars> h(count);
     std::vector<int> have_true(count, 0), done(count, 0), code(count, TT_OK), refinements(count, 0);
     for (int i = 0; i < count; ++i) {
         tt_ctx& c = *systems[i];
+        if (pc) {
+            TT_CHECK(precond_build(c));
+            if (c.bu32.n < (size_t)c.n_slopes) TT_CHECK(c.bu32.alloc(c.n_slopes));
+        }
         TT_CHECK(cg_setup(c, d_s[i], d_x0 ? d_x0[i] : nullptr, o, true));
         TT_HIP(hipMemcpyAsync(&h[i], c.scal.p, sizeof(CgScalars), hipMemcpyDeviceToHost, c.stream));
         TT_HIP(hipStreamSynchronize(c.stream));
@@ -149,46 +243,73 @@ tt_status solve_batched(tt_ctx* const* systems, int count, const float* const* d
             have_true[i] = 1;
         }
     }
-    DevBuf<BVec> dvec;
+    DevBuf<BVec> dvec, d1;
     DevBuf<CgScalars> dS;
     TT_CHECK(dvec.alloc((size_t)count));
+    TT_CHECK(d1.alloc(1));
     TT_CHECK(dS.alloc((size_t)count));
     std::vector<BVec> hv;
     std::vector<tt_ctx*> act;
     std::vector<int> idx;
-    std::vector<const float*> px;
-    std::vector<float*> qy;
-    const int chunk = 16;
-    while (true) {
+    std::vector<const float*> px, pr;
+    std::vector<float*> qy, pu;
+    auto gather_active = [&]() {
         act.clear();
         idx.clear();
         hv.clear();
         px.clear();
         qy.clear();
+        pr.clear();
+        pu.clear();
         for (int i = 0; i < count; ++i) {
             if (done[i]) continue;
             tt_ctx& c = *systems[i];
             act.push_back(&c);
             idx.push_back(i);
-            hv.push_back(BVec{c.x32.p, c.r32.p, c.p32.p, c.q32.p, c.part.p, c.part.p + VB, cg_scalars(c),
-                              (long)c.n_slopes, h[i].iter, 0});
+            hv.push_back(bvec_of(c, h[i].iter));
             px.push_back(c.p32.p);
             qy.push_back(c.q32.p);
+            pr.push_back(c.r32.p);
+            pu.push_back(c.bu32.p);
         }
+    };
+    // the batched launches go to the stream of the first system still iterating
+    // (batch_apply uses it too)
+    if (pc) {   // p = u = P r for every system that iterates
+        gather_active();
+        const int na = (int)act.size();
+        if (na > 0) {
+            const hipStream_t st = act[0]->stream;
+            TT_HIP(hipMemcpyAsync(dvec.p, hv.data(), sizeof(BVec) * na, hipMemcpyHostToDevice, st));
+            TT_CHECK(pc_start(act.data(), na, pr, pu, dvec.p, st));
+            TT_HIP(hipStreamSynchronize(st));
+        }
+    }
+    const int chunk = 16;
+    while (true) {
+        gather_active();
         const int na = (int)act.size();
         if (na == 0) break;
-        TT_HIP(hipMemcpyAsync(dvec.p, hv.data(), sizeof(BVec) * na, hipMemcpyHostToDevice, c0.stream));
+        const hipStream_t st = act[0]->stream;
+        TT_HIP(hipMemcpyAsync(dvec.p, hv.data(), sizeof(BVec) * na, hipMemcpyHostToDevice, st));
         for (int k = 0; k < chunk; ++k) {
-            TT_CHECK(matvec_batch(act.data(), na, px.data(), qy.data(), nullptr));
-            hipLaunchKernelGGL(k_bdot, dim3(VB, na), dim3(VT), 0, c0.stream, dvec.p);
-            hipLaunchKernelGGL(k_bupdate_xr, dim3(VB, na), dim3(VT), 0, c0.stream, dvec.p, k);
-            hipLaunchKernelGGL(k_bupdate_p, dim3(VB, na), dim3(VT), 0, c0.stream, dvec.p, k, o.max_iter);
+            TT_CHECK(batch_apply(act.data(), na, px.data(), qy.data(), 0, nullptr));
+            hipLaunchKernelGGL(k_bdot, dim3(VB, na), dim3(VT), 0, st, dvec.p);
+            if (pc) {
+                hipLaunchKernelGGL(k_bupdate_xr<true>, dim3(VB, na), dim3(VT), 0, st, dvec.p, k);
+                TT_CHECK(batch_apply(act.data(), na, pr.data(), pu.data(), 1, nullptr));
+                hipLaunchKernelGGL(k_bdot_ru, dim3(VB, na), dim3(VT), 0, st, dvec.p, 0);
+                hipLaunchKernelGGL(k_bupdate_p_pc, dim3(VB, na), dim3(VT), 0, st, dvec.p, k, o.max_iter);
+            } else {
+                hipLaunchKernelGGL(k_bupdate_xr<false>, dim3(VB, na), dim3(VT), 0, st, dvec.p, k);
+                hipLaunchKernelGGL(k_bupdate_p, dim3(VB, na), dim3(VT), 0, st, dvec.p, k, o.max_iter);
+            }
         }
-        hipLaunchKernelGGL(k_bgather, dim3(cdiv(na, 64)), dim3(64), 0, c0.stream, dvec.p, na, dS.p);
+        hipLaunchKernelGGL(k_bgather, dim3(cdiv(na, 64)), dim3(64), 0, st, dvec.p, na, dS.p);
         TT_HIP(hipGetLastError());
         std::vector<CgScalars> g(na);
-        TT_HIP(hipMemcpyAsync(g.data(), dS.p, sizeof(CgScalars) * na, hipMemcpyDeviceToHost, c0.stream));
-        TT_HIP(hipStreamSynchronize(c0.stream));
+        TT_HIP(hipMemcpyAsync(g.data(), dS.p, sizeof(CgScalars) * na, hipMemcpyDeviceToHost, st));
+        TT_HIP(hipStreamSynchronize(st));
         for (int a = 0; a < na; ++a) {
             const int i = idx[a];
             tt_ctx& c = *systems[i];
@@ -202,7 +323,12 @@ tt_status solve_batched(tt_ctx* const* systems, int count, const float* const* d
                 done[i] = 1;
             } else if (h[i].state == ST_REFINE || h[i].state == ST_CONV) {
                 bool conv = false;
-                TT_CHECK(cg_replace(c, d_s[i], true, it, &conv, &h[i]));
+                if (pc) {
+                    TT_CHECK(cg_true_residual(c, d_s[i], true, &h[i]));
+                    conv = h[i].rr_true <= h[i].tol2;
+                } else {
+                    TT_CHECK(cg_replace(c, d_s[i], true, it, &conv, &h[i]));
+                }
                 refinements[i]++;
                 if (conv) {
                     have_true[i] = 1;
@@ -212,9 +338,20 @@ tt_status solve_batched(tt_ctx* const* systems, int count, const float* const* d
                     code[i] = TT_NOT_CONVERGED;
                     done[i] = 1;
                 } else {
+                    if (pc) {   // restart from the true residual: r = r64, p = u = P r
+                        TT_CHECK(cg_copy_r64_to_r32(c));
+                        tt_ctx* one[1] = {&c};
+                        const BVec b1 = bvec_of(c, it);
+                        TT_HIP(hipMemcpyAsync(d1.p, &b1, sizeof(BVec), hipMemcpyHostToDevice, c.stream));
+                        TT_CHECK(pc_start(one, 1, {c.r32.p}, {c.bu32.p}, d1.p, c.stream));
+                    }
                     // restarted: its scalars on the device are current again
                     TT_HIP(hipMemcpyAsync(&h[i], c.scal.p, sizeof(CgScalars), hipMemcpyDeviceToHost, c.stream));
                     TT_HIP(hipStreamSynchronize(c.stream));
+                    if (h[i].state == ST_BREAK) {
+                        code[i] = TT_BREAKDOWN;
+                        done[i] = 1;
+                    }
                 }
             }
         }

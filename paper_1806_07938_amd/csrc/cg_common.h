@@ -13,6 +13,7 @@ struct CgScalars {
     int state;        // 0 running, 1 replacement due, 2 recursive residual converged,
                       // 3 breakdown, 4 iteration cap
     int iter;         // iterations done
+    double ru[2];     // r.u = r.P r, slot (iteration & 1) (preconditioned CG, batched solver)
 };
 
 enum { ST_RUN = 0, ST_REFINE = 1, ST_CONV = 2, ST_BREAK = 3, ST_CAP = 4 };

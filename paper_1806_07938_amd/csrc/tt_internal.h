@@ -164,8 +164,9 @@ struct tt_ctx {
     int tile_mf = -1;                   // column-transform mode the fragments were built for
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     DevBuf<c32> bU32;                   // batched product: column shares [Lh][S][C][n]
-    DevBuf<unsigned char> bdesc;        // batched product: per-system descriptors (first context of a call)
-    std::vector<unsigned char> bdesc_host;
+    DevBuf<float> bu32;                 // batched preconditioned CG: u = P r
+    DevBuf<unsigned char> bdesc[2];     // batched product / preconditioner: per-system descriptors
+    std::vector<unsigned char> bdesc_host[2];   // (kept by the first context of a call)
     hipEvent_t bev[4] = {nullptr, nullptr, nullptr, nullptr};   // batched product phase timing
     DevBuf<float> Minv32;               // circulant preconditioner spectra [Lh][L][C^2] (general Hermitian packing)
     DevBuf<double> Minv64;
@@ -212,6 +213,8 @@ tt_status matvec_f64(tt_ctx& c, const double* x, double* y, double* part);
 // batch.hip
 tt_status matvec_batch(tt_ctx* const* systems, int count, const float* const* d_x, float* const* d_y,
                        float* phase_ms);
+tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x, float* const* d_y, int op,
+                      float* phase_ms);   // op 0: the product, op 1: the block-circulant preconditioner
 
 // cg.hip
 tt_status cg_alloc(tt_ctx& c);

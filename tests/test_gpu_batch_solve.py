@@ -35,8 +35,9 @@ def _check_frame(wl, s, z, tol, inf):
     assert np.linalg.norm(z - zref) <= 1e-5 * np.linalg.norm(zref), wl.name
 
 
+@pytest.mark.parametrize("pc", [0, 1], ids=["cg", "pcg"])
 @pytest.mark.parametrize("tol", [1e-6, 1e-9])
-def test_batched_solver_matches_oracle(tol):
+def test_batched_solver_matches_oracle(tol, pc):
     import torch
     from oracle.projection import phi_paper_dense
     from paper_1806_07938_amd import solve_batch
@@ -44,11 +45,11 @@ def test_batched_solver_matches_oracle(tol):
     wls, systems = _systems()
     dev = torch_dev()
     S = [torch.tensor(W.turbulent_slopes(wl)[0].astype(np.float32), device=dev) for wl in wls]
-    zs, phis, infos, st = solve_batch([c for c, k in systems], S, tol=tol, solver=SOLVER_BATCHED)
+    zs, phis, infos, st = solve_batch([c for c, k in systems], S, tol=tol, solver=SOLVER_BATCHED, preconditioner=pc)
     assert st == 0
     for wl, s, z, ph, inf in zip(wls, S, zs, phis, infos):
-        say("batched", wl.name, "L", wl.pad_L, "iterations", inf.iterations, "refinements", inf.refinements,
-            "rel", inf.rel_residual)
+        say("batched", "pcg" if pc else "cg", wl.name, "L", wl.pad_L, "iterations", inf.iterations,
+            "refinements", inf.refinements, "rel", inf.rel_residual)
         zc = z.cpu().numpy()
         _check_frame(wl, s.cpu().numpy(), zc, tol, inf)
         ref = phi_paper_dense(wl, zc.astype(np.float32).astype(np.float64))
@@ -94,16 +95,24 @@ def test_batched_solver_statuses_and_errors():
     ctxs = [c for c, k in systems]
     S = [torch.tensor(W.turbulent_slopes(wl)[0].astype(np.float32), device=dev) for wl in wls]
     # an iteration cap stops every frame; all frames reported
-    zs, _, infos, st = solve_batch(ctxs, S, tol=1e-12, max_iter=5, solver=SOLVER_BATCHED,
-                                   allow=(0, TT_NOT_CONVERGED))
-    assert st == TT_NOT_CONVERGED
-    assert all(i.status == TT_NOT_CONVERGED and i.iterations == 5 for i in infos)
+    for pc in (0, PRECOND_CIRCULANT):
+        zs, _, infos, st = solve_batch(ctxs, S, tol=1e-12, max_iter=5, solver=SOLVER_BATCHED, preconditioner=pc,
+                                       allow=(0, TT_NOT_CONVERGED))
+        assert st == TT_NOT_CONVERGED
+        assert all(i.status == TT_NOT_CONVERGED and i.iterations == 5 for i in infos)
+    # the first system converged at the start (zero right-hand side): the others
+    # iterate on the stream of the first system still iterating
+    Z0 = [torch.zeros_like(S[0])] + S[1:]
+    zs, _, infos, st = solve_batch(ctxs, Z0, tol=1e-8, solver=SOLVER_BATCHED, preconditioner=PRECOND_CIRCULANT)
+    assert st == 0 and infos[0].iterations == 0
+    for wl, s, z, inf in list(zip(wls, Z0, zs, infos))[1:]:
+        _check_frame(wl, s.cpu().numpy(), z.cpu().numpy(), 1e-8, inf)
     # a zero right-hand side is solved by zeta = 0 without iterating
     Z = [torch.zeros_like(s) for s in S]
     zs, _, infos, st = solve_batch(ctxs[:2], Z[:2], solver=SOLVER_BATCHED)
     assert st == 0 and all(i.iterations == 0 for i in infos)
     assert all(float(z.abs().max()) == 0.0 for z in zs)
-    for kw in (dict(precision=PREC_F64), dict(preconditioner=PRECOND_CIRCULANT)):
+    for kw in (dict(precision=PREC_F64), dict(precision=PREC_F64, preconditioner=PRECOND_CIRCULANT)):
         with pytest.raises(TTError) as e:
             solve_batch(ctxs, S, solver=SOLVER_BATCHED, **kw)
         assert e.value.status == TT_INVALID_ARG
