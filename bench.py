@@ -139,26 +139,37 @@ def batch_systems(args):
     return ctxs, keep, time.perf_counter() - t0
 
 
-def batch_solve(args, ctxs, frames):
+def batch_solve(args, ctxs, frames, pc):
     """TT_SOLVER_BATCHED over the same systems: one frame each (the measured
-    frames of lgs6_74x74 reused in turn as right-hand sides), FP32 CG with the
-    FP64 residual replacement, to args.tol; one untimed batch, then one timed."""
+    frames of lgs6_74x74 reused in turn as right-hand sides), FP32 CG (plain,
+    or preconditioned by the block-circulant inverse when pc) with the FP64
+    residual replacement, to args.tol; one untimed batch (it also builds the
+    preconditioner spectra, timed apart), then one timed."""
     import torch
     from paper_1806_07938_amd import solve_batch
     from paper_1806_07938_amd.tt import SOLVER_BATCHED, TT_NOT_CONVERGED
     S = [torch.tensor(frames[i % len(frames)], device="cuda:0") for i in range(len(ctxs))]
-    solve_batch(ctxs, S, tol=args.tol, solver=SOLVER_BATCHED, allow=(0, TT_NOT_CONVERGED))
+    t0 = time.perf_counter()
+    if pc:   # preconditioner spectra, once per system (host FP64), before the untimed batch
+        solve_batch(ctxs, S, tol=args.tol, max_iter=0, solver=SOLVER_BATCHED, preconditioner=pc,
+                    allow=(0, TT_NOT_CONVERGED))
+    torch.cuda.synchronize()
+    pc_setup_s = time.perf_counter() - t0
+    solve_batch(ctxs, S, tol=args.tol, solver=SOLVER_BATCHED, preconditioner=pc, allow=(0, TT_NOT_CONVERGED))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, _, infos, st = solve_batch(ctxs, S, tol=args.tol, solver=SOLVER_BATCHED, allow=(0, TT_NOT_CONVERGED))
+    _, _, infos, st = solve_batch(ctxs, S, tol=args.tol, solver=SOLVER_BATCHED, preconditioner=pc,
+                                  allow=(0, TT_NOT_CONVERGED))
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3
     it = np.array([i.iterations for i in infos], dtype=np.float64)
     return {
         "workload": (f"{len(ctxs)} distinct 74x74 / 6 LGS / 35-layer systems, L={args.batch_pad}, one frame each, "
-                     f"solved together (TT_SOLVER_BATCHED: plain CG in lockstep, FP32 + FP64 residual replacement) "
-                     f"to rel. residual {args.tol:g}"),
+                     f"solved together (TT_SOLVER_BATCHED: "
+                     + ("CG preconditioned by the block-circulant inverse" if pc else "plain CG")
+                     + f" in lockstep, FP32 + FP64 residual replacement) to rel. residual {args.tol:g}"),
         "systems": len(ctxs), "ms_per_batch": round(wall, 2), "ms_per_solve": round(wall / len(ctxs), 3),
+        "preconditioner_setup_s": round(pc_setup_s, 1) if pc else None,
         "iterations_mean": round(float(it.mean()), 1), "iterations_max": int(it.max()),
         "rel_residual_max": max(i.rel_residual for i in infos),
         "all_converged": bool(st == 0 and all(i.status == 0 and i.rel_residual <= args.tol for i in infos)),
@@ -355,7 +366,8 @@ def main():
     if args.batch > 0:
         bctx, bkeep, bsetup = batch_systems(args)
         out["batch_matvec"] = batch_matvec(args, bctx, bsetup)
-        out["batch_solve"] = batch_solve(args, bctx, frames)
+        out["batch_solve"] = batch_solve(args, bctx, frames, 0)
+        out["batch_solve_pcg"] = batch_solve(args, bctx, frames, 1)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, frames[0], args.tol)
     print(json.dumps(out), flush=True)

@@ -254,6 +254,11 @@ tt_status solve_batched(tt_ctx* const* systems, int count, const float* const* d
     std::vector<const float*> px, pr;
     std::vector<float*> qy, pu;
     auto gather_active = [&]() {
+        for (int i = 0; i < count; ++i)   // iteration cap reached (max_iter 0 included)
+            if (!done[i] && h[i].iter >= o.max_iter) {
+                code[i] = TT_NOT_CONVERGED;
+                done[i] = 1;
+            }
         act.clear();
         idx.clear();
         hv.clear();

@@ -100,6 +100,12 @@ def test_batched_solver_statuses_and_errors():
                                        allow=(0, TT_NOT_CONVERGED))
         assert st == TT_NOT_CONVERGED
         assert all(i.status == TT_NOT_CONVERGED and i.iterations == 5 for i in infos)
+    # max_iter = 0: no iteration, zeta = 0 and the true residual of it
+    zs, _, infos, st = solve_batch(ctxs, S, max_iter=0, solver=SOLVER_BATCHED, preconditioner=PRECOND_CIRCULANT,
+                                   allow=(0, TT_NOT_CONVERGED))
+    assert st == TT_NOT_CONVERGED
+    assert all(i.iterations == 0 and abs(i.rel_residual - 1.0) < 1e-12 for i in infos)
+    assert all(float(z.abs().max()) == 0.0 for z in zs)
     # the first system converged at the start (zero right-hand side): the others
     # iterate on the stream of the first system still iterating
     Z0 = [torch.zeros_like(S[0])] + S[1:]
