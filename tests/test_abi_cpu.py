@@ -1,6 +1,8 @@
 """CPU checks of the C ABI: the library loads, exports every function that
 include/tt.h declares, and rejects bad arguments before touching a device."""
 import ctypes as C
+
+import numpy as np
 import os
 import re
 
@@ -50,6 +52,30 @@ def test_null_arguments_rejected(lib):
     assert lib.tt_kernels_copy(None, None, 0) == tt.TT_INVALID_ARG
     assert lib.tt_destroy(None) == tt.TT_OK
     assert lib.tt_kernels_destroy(None) == tt.TT_OK
+    # batched product: an empty batch is a no-op, missing arrays and negative counts are refused
+    assert lib.tt_matvec_batch(None, 0, None, None, None) == tt.TT_OK
+    assert lib.tt_matvec_batch(None, 1, None, None, None) == tt.TT_INVALID_ARG
+    assert lib.tt_matvec_batch(None, -1, None, None, None) == tt.TT_INVALID_ARG
+    assert lib.tt_solve_batch(None, 0, None, None, None, None, None, None) == tt.TT_OK
+    assert lib.tt_solve_batch(None, 2, None, None, None, None, None, None) == tt.TT_INVALID_ARG
+
+
+def test_batch_workload_family():
+    # distinct 74x74 systems for the batched product: same geometry, seeded
+    # weights (normalised, decaying with altitude on average) and r0 in range
+    import workloads as W
+    base = W.lgs6_74x74(pad_L=256)
+    fam = [W.lgs6_74x74_family(i) for i in range(4)]
+    assert W.lgs6_74x74_family(-1).name == "lgs6_74x74"
+    for wl in fam:
+        assert wl.pad_L == 256 and wl.n == 74 and wl.n_vs == 3972 and wl.n_gs == 6
+        assert np.array_equal(wl.valid, base.valid) and np.allclose(wl.h, base.h)
+        assert abs(wl.w.sum() - 1.0) < 1e-12 and (wl.w > 0).all()
+        assert 0.10 <= wl.r0 <= 0.25
+    assert len({round(wl.r0, 12) for wl in fam}) == 4
+    assert all(not np.allclose(fam[0].w, wl.w) for wl in fam[1:])
+    again = W.lgs6_74x74_family(2)
+    assert again.r0 == fam[2].r0 and np.array_equal(again.w, fam[2].w)
 
 
 def test_struct_layouts_match_header():
