@@ -198,7 +198,7 @@ tt_status tt_create(tt_ctx** out, int device, void* stream);
 tt_status tt_destroy(tt_ctx* ctx);
 
 /* Covariance generation, FP64 on the device (App. A.2 Hudgin slope-slope
- * equations with the §2.D cone scaling; row a1 of the hot path).  For every
+ * equations with the §2.D cone scaling).  For every
  * unordered guide-star pair g <= h and component xx, xy (= yx), yy it evaluates
  * the (2n-1)^2 unique elements of the 2RBT block Theta^{gh}_{pq} (§2.D):
  *   t(u, v) = sum_k w_k Hud_pq( s_k (u d, v d) + h_k (alpha_h - alpha_g); s_k d ),
@@ -213,7 +213,7 @@ tt_status tt_kernels_destroy(tt_kernels* k);
  * n_gs (n_gs + 1) / 2 * 3 * (2n-1)^2.  Synchronous. */
 tt_status tt_kernels_copy(const tt_kernels* k, double* host_out, size_t count);
 
-/* Build the system (row a2 and set-up): FP64 2-D real DFT of every embedded
+/* Build the system (spectra and set-up): FP64 2-D real DFT of every embedded
  * table (K[(-u) mod L, (-v) mod L] = t(u, v)), packed per frequency as the
  * 2 n_gs x 2 n_gs Hermitian matrix of §2.E's per-frequency products (FP64 and
  * FP32 copies), the W_s index maps, the noise variance Sigma_eta = diag
@@ -250,12 +250,12 @@ tt_status tt_set_noise_xy(tt_ctx* ctx, const double* cov_xy);
 tt_status tt_set_mode_removal(tt_ctx* ctx, int on);
 
 /* y = W_s (Sigma_ss + Sigma_eta) W_s^T x, once, by the fused 2RBT product of
- * §2.E (rows a3-a7).  d_x, d_y: n_slopes elements; they must not overlap. */
+ * §2.E.  d_x, d_y: n_slopes elements; they must not overlap. */
 tt_status tt_matvec(tt_ctx* ctx, const float* d_x, float* d_y);
 tt_status tt_matvec_f64(tt_ctx* ctx, const double* d_x, double* d_y);
 
 /* The same FP32 product for count independent systems in one call (the §2.E
- * product of each system; rows a3-a7 batched over systems): y_i = A_i x_i,
+ * product of each system, batched over systems): y_i = A_i x_i,
  * d_x[i], d_y[i] on systems[i] (n_slopes of that system each, device memory,
  * not overlapping).  The systems may differ in every size; each context appears
  * at most once, all are on one device, and none has mode removal on
@@ -273,8 +273,8 @@ tt_status tt_matvec_f64(tt_ctx* ctx, const double* d_x, double* d_y);
 tt_status tt_matvec_batch(tt_ctx* const* systems, int count, const float* const* d_x,
                           float* const* d_y, float* phase_ms);
 
-/* Solve W_s (Sigma_ss + Sigma_eta) W_s^T zeta = s by CG (rows a3-a8, a10) and,
- * if d_phi != NULL, project phi = W_phi Sigma_{phi_beta s} zeta (row a9).
+/* Solve W_s (Sigma_ss + Sigma_eta) W_s^T zeta = s by CG (§2.G) and,
+ * if d_phi != NULL, project phi = W_phi Sigma_{phi_beta s} zeta (§2.E).
  * d_s: n_slopes floats; d_x0: n_slopes doubles (warm start) or NULL (zeta0 = 0);
  * d_zeta: n_slopes doubles (out); d_phi: n_vphi floats (out) or NULL.
  * opts NULL = tol 1e-6, max_iter 20000, TT_PREC_F32, persistent.
@@ -301,8 +301,8 @@ tt_status tt_solve_batch(tt_ctx* const* systems, int count, const float* const* 
                          const double* const* d_x0, double* const* d_zeta, float* const* d_phi,
                          const tt_solve_opts* opts, tt_solve_info* infos);
 
-/* phi = W_phi sum_k I'_k S2 F^-1 { sum_q Xi'~_{q,k} . F[S1 zeta_q] } (row a9,
- * §2.E LGS phase-slope equation with a common n').  d_zeta: n_slopes doubles
+/* phi = W_phi sum_k I'_k S2 F^-1 { sum_q Xi'~_{q,k} . F[S1 zeta_q] }
+ * (§2.E LGS phase-slope equation with a common n').  d_zeta: n_slopes doubles
  * (rounded to FP32 for the products), d_phi: n_vphi floats.  Requires a target. */
 tt_status tt_project(tt_ctx* ctx, const double* d_zeta, float* d_phi);
 

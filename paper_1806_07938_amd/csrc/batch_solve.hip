@@ -1,8 +1,8 @@
 // Frames of many systems solved together (TT_SOLVER_BATCHED): conjugate
-// gradients (§2.G, row a8) run in lockstep over every system still iterating,
+// gradients (§2.G) run in lockstep over every system still iterating,
 // each iteration's products by one batched 2RBT product (batch.hip) and the
 // vector updates by kernels over all systems at once; the FP64 residual
-// replacement and certification of row a10 are those of the single-system
+// replacement and the certification of the tolerance are those of the single-system
 // path (cg.hip), per system, between chunks of iterations.
 //
 // Plain CG, per system the recurrences of TT_SOLVER_KERNELS in FP32:

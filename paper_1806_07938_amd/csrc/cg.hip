@@ -1,6 +1,6 @@
 // Conjugate gradients for W_s (Sigma_ss + Sigma_eta) W_s^T zeta = s (§2.C first
-// step, §2.G), one launch per phase (TT_SOLVER_KERNELS), row a8, with the FP64
-// residual replacement of row a10.
+// step, §2.G), one launch per phase (TT_SOLVER_KERNELS), with the FP64 residual
+// replacement that certifies the tolerance.
 //
 // Iteration j (textbook CG):
 //   q = A p                                   (fused 2RBT product, matvec.hip)

@@ -1,5 +1,5 @@
 // The fused 2RBT product y = W_s (Sigma_ss + Sigma_eta) W_s^T x (§2.E, Sigma_ss
-// zeta equation; §2.F masks), rows a3-a7, one launch per phase.
+// zeta equation; §2.F masks), one launch per phase.
 //
 // The two-dimensional transform of every channel is split into a row pass
 // (along x, real input -> half spectrum f2 in [0, L/2]) and a column pass

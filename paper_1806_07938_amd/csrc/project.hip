@@ -1,4 +1,4 @@
-// Projection to the target direction, row a9:
+// Projection to the target direction:
 //
 //   phi = W_phi sum_k I'_k S2 F^-1 { sum_q Xi'~_{q,k} . F[S1 zeta_q] }
 //

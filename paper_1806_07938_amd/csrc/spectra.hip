@@ -1,4 +1,4 @@
-// Spectra of the embedded covariance tables, float64 (row a2; §2.E: the FFT of
+// Spectra of the embedded covariance tables, float64 (§2.E: the FFT of
 // the unique-element vector is computed offline).
 //
 // A table t(U, V), U, V in [-off, m-1-off] (U column lag, V row lag), is

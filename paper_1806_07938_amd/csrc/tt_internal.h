@@ -81,7 +81,7 @@ using c32 = cplx<float>;
 using c64 = cplx<double>;
 
 // ---------------------------------------------------------------------------
-// generated covariance tables (row a1)
+// generated covariance tables (App. A.2 / A.3, §2.D cone scaling)
 // ---------------------------------------------------------------------------
 struct tt_kernels {
     int device = 0;

@@ -1,4 +1,4 @@
-// Covariance generation in float64 on the device (row a1).
+// Covariance generation in float64 on the device (App. A.2 / A.3).
 //
 // Slope-slope tables (App. A.2 Hudgin-like slope-slope equations, or the App.
 // A.3 Fried equations, §2.D cone scaling): for every unordered guide-star pair g <= h, component c in
