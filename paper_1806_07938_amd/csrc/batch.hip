@@ -89,7 +89,13 @@ __device__ inline c32 mul_pi(c32 a) { return c32{-a.y, a.x}; }   // a (+i)
 // stages per pass (half spans H and H/2 on the four entries j, j + H/2, j + H,
 // j + 3H/2 of a block of 2H), a last single stage when bits is odd.  Entries at
 // or beyond nin are zero and are not read (first pass only).
-template <int NT>
+// LDS index of entry i of an FFT buffer: with PAD one element of padding
+// follows every 16, which spreads the strided accesses of the short-span
+// passes over the banks
+template <bool PAD>
+__device__ __forceinline__ int pidx(int i) { return PAD ? i + (i >> 4) : i; }
+
+template <int NT, bool PAD>
 __device__ void fft_dif(c32* A, const c32* tws, int C, int bits, int L, int nin) {
     const int m = 1 << bits;
     int H = m >> 1, lH = bits - 1;
@@ -102,19 +108,20 @@ __device__ void fft_dif(c32* A, const c32* tws, int C, int bits, int L, int nin)
             const int c = b >> (bits - 2), r = b & ((m >> 2) - 1);
             const int j = r & (q - 1);
             const int p0 = ((r >> lq) << (lH + 1)) + j;
-            c32* a = A + (c << bits);
+            const int i0 = pidx<PAD>((c << bits) + p0), i1 = pidx<PAD>((c << bits) + p0 + q);
+            const int i2 = pidx<PAD>((c << bits) + p0 + H), i3 = pidx<PAD>((c << bits) + p0 + H + q);
             const c32 z = c32{0.f, 0.f};
-            const c32 x0 = (!first || p0 < nin) ? a[p0] : z;
-            const c32 x1 = (!first || p0 + q < nin) ? a[p0 + q] : z;
-            const c32 x2 = (!first || p0 + H < nin) ? a[p0 + H] : z;
-            const c32 x3 = (!first || p0 + H + q < nin) ? a[p0 + H + q] : z;
+            const c32 x0 = (!first || p0 < nin) ? A[i0] : z;
+            const c32 x1 = (!first || p0 + q < nin) ? A[i1] : z;
+            const c32 x2 = (!first || p0 + H < nin) ? A[i2] : z;
+            const c32 x3 = (!first || p0 + H + q < nin) ? A[i3] : z;
             const c32 w1 = tws[j * step], w2 = tws[2 * j * step];
             const c32 t0 = cadd(x0, x2), t2 = cmulc(csub(x0, x2), w1);
             const c32 t1 = cadd(x1, x3), t3 = mul_mi(cmulc(csub(x1, x3), w1));
-            a[p0] = cadd(t0, t1);
-            a[p0 + q] = cmulc(csub(t0, t1), w2);
-            a[p0 + H] = cadd(t2, t3);
-            a[p0 + H + q] = cmulc(csub(t2, t3), w2);
+            A[i0] = cadd(t0, t1);
+            A[i1] = cmulc(csub(t0, t1), w2);
+            A[i2] = cadd(t2, t3);
+            A[i3] = cmulc(csub(t2, t3), w2);
         }
         lds_barrier();
         H >>= 2;
@@ -124,11 +131,12 @@ __device__ void fft_dif(c32* A, const c32* tws, int C, int bits, int L, int nin)
     if (H == 1) {
         for (int b = threadIdx.x; b < (C << (bits - 1)); b += NT) {
             const int i0 = 2 * b, p = i0 & (m - 1);
+            const int j0 = pidx<PAD>(i0), j1 = pidx<PAD>(i0 + 1);
             const c32 z = c32{0.f, 0.f};
-            const c32 u = (!first || p < nin) ? A[i0] : z;
-            const c32 v = (!first || p + 1 < nin) ? A[i0 + 1] : z;
-            A[i0] = cadd(u, v);
-            A[i0 + 1] = csub(u, v);
+            const c32 u = (!first || p < nin) ? A[j0] : z;
+            const c32 v = (!first || p + 1 < nin) ? A[j1] : z;
+            A[j0] = cadd(u, v);
+            A[j1] = csub(u, v);
         }
         lds_barrier();
     }
@@ -138,16 +146,16 @@ __device__ void fft_dif(c32* A, const c32* tws, int C, int bits, int L, int nin)
 // in place: radix-2 decimation in time, bit-reversed input, natural output; a
 // first single stage when bits is odd, then two stages per pass (half spans h
 // and 2h on the entries j, j + h, j + 2h, j + 3h of a block of 4h).
-template <int NT>
+template <int NT, bool PAD>
 __device__ void fft_dit_inv(c32* A, const c32* tws, int C, int bits, int L) {
     const int m = 1 << bits;
     int h = 1, lh = 0;
     if (bits & 1) {
         for (int b = threadIdx.x; b < (C << (bits - 1)); b += NT) {
-            const int i0 = 2 * b;
-            const c32 u = A[i0], v = A[i0 + 1];
-            A[i0] = cadd(u, v);
-            A[i0 + 1] = csub(u, v);
+            const int j0 = pidx<PAD>(2 * b), j1 = pidx<PAD>(2 * b + 1);
+            const c32 u = A[j0], v = A[j1];
+            A[j0] = cadd(u, v);
+            A[j1] = csub(u, v);
         }
         lds_barrier();
         h = 2;
@@ -160,15 +168,16 @@ __device__ void fft_dit_inv(c32* A, const c32* tws, int C, int bits, int L) {
             const int c = b >> (bits - 2), r = b & ((m >> 2) - 1);
             const int j = r & (h - 1);
             const int p0 = ((r >> lh) << (lh + 2)) + j;
-            c32* a = A + (c << bits);
+            const int i0 = pidx<PAD>((c << bits) + p0), i1 = pidx<PAD>((c << bits) + p0 + h);
+            const int i2 = pidx<PAD>((c << bits) + p0 + 2 * h), i3 = pidx<PAD>((c << bits) + p0 + 3 * h);
             const c32 wa = tws[j * sa], wb = tws[j * sb];
-            const c32 x0 = a[p0], x1 = cmul(a[p0 + h], wa), x2 = a[p0 + 2 * h], x3 = cmul(a[p0 + 3 * h], wa);
+            const c32 x0 = A[i0], x1 = cmul(A[i1], wa), x2 = A[i2], x3 = cmul(A[i3], wa);
             const c32 t0 = cadd(x0, x1), t1 = csub(x0, x1), t2 = cadd(x2, x3), t3 = csub(x2, x3);
             const c32 u2 = cmul(t2, wb), u3 = mul_pi(cmul(t3, wb));
-            a[p0] = cadd(t0, u2);
-            a[p0 + h] = cadd(t1, u3);
-            a[p0 + 2 * h] = csub(t0, u2);
-            a[p0 + 3 * h] = csub(t1, u3);
+            A[i0] = cadd(t0, u2);
+            A[i1] = cadd(t1, u3);
+            A[i2] = csub(t0, u2);
+            A[i3] = csub(t1, u3);
         }
         lds_barrier();
         h <<= 2;
@@ -282,7 +291,7 @@ __global__ __launch_bounds__(RBT) void k_brow_fwd(const BSys* __restrict__ sys) 
             A[r * L + b] = c32{v >= 0 ? s.x[(long)c * s.n_vs + v] : 0.f, 0.f};
         }
         __syncthreads();
-        fft_dif<RBT>(A, tws, rows, bits, L, n);   // bit-reversed output
+        fft_dif<RBT, false>(A, tws, rows, bits, L, n);   // bit-reversed output
         for (int idx = threadIdx.x; idx < Lh * rt; idx += RBT) {
             const int f2 = idx / rt, r = idx - f2 * rt;
             if (r < rows) s.T[((long)f2 * C + c) * n + a0 + r] = A[r * L + bitrev(f2, bits)];
@@ -352,7 +361,7 @@ __global__ __launch_bounds__(RBT) void k_brow_inv(const BSys* __restrict__ sys, 
             A[r * L + bitrev(f, bits)] = u;
         }
         __syncthreads();
-        fft_dit_inv<RBT>(A, tws, rows, bits, L);
+        fft_dit_inv<RBT, false>(A, tws, rows, bits, L);
         for (int idx = threadIdx.x; idx < rows * n; idx += RBT) {
             const int r = idx / n, b = idx - r * n;
             const int v = s.vmap[(a0 + r) * n + b];
@@ -396,11 +405,12 @@ __global__ __launch_bounds__(RBT) void k_brow_inv(const BSys* __restrict__ sys, 
 // 2x2 blocks M_{g hh} (Hermitian packing: real diagonal blocks, pairs g < hh
 // stored once, M_{g hh} = conj(M_{hh g}) for g > hh) times X_hh
 __device__ __forceinline__ void sensor_products(const float* Ms, const c32* X, int m, int P, int G, int g, int k,
-                                                c32& yx, c32& yy) {
+                                                bool pad, c32& yx, c32& yy) {
     const float* Mf = Ms + k * (P + 1);
     c32 ax = c32{0.f, 0.f}, ay = c32{0.f, 0.f};
     for (int hh = 0; hh < G; ++hh) {
-        const c32 xh = X[(2 * hh) * m + k], yh = X[(2 * hh + 1) * m + k];
+        const int ix = (2 * hh) * m + k, iy = ix + m;
+        const c32 xh = X[pad ? pidx<true>(ix) : ix], yh = X[pad ? pidx<true>(iy) : iy];
         c32 mxx, mxy, myy;
         if (hh == g) {
             mxx = c32{Mf[3 * g], 0.f};
@@ -435,11 +445,12 @@ __device__ __forceinline__ c32 herm_entry(const float* Mf, int C, int a, int b) 
 // outputs 2g and 2g + 1 at position k of Y = H X (the block-circulant
 // preconditioner's per-frequency matrices)
 __device__ __forceinline__ void herm_products(const float* Ms, const c32* X, int m, int P, int C, int g, int k,
-                                              c32& y0, c32& y1) {
+                                              bool pad, c32& y0, c32& y1) {
     const float* Mf = Ms + k * (P + 1);
     c32 a0 = c32{0.f, 0.f}, a1 = c32{0.f, 0.f};
     for (int q = 0; q < C; ++q) {
-        const c32 xq = X[q * m + k];
+        const int iq = q * m + k;
+        const c32 xq = X[pad ? pidx<true>(iq) : iq];
         a0 = cadd(a0, cmul(herm_entry(Mf, C, 2 * g, q), xq));
         a1 = cadd(a1, cmul(herm_entry(Mf, C, 2 * g + 1, q), xq));
     }
@@ -493,7 +504,7 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
         while ((1 << bits) < m) ++bits;
         float* Ms = reinterpret_cast<float*>(work);
         c32* A = reinterpret_cast<c32*>(work + ((((size_t)m * (P + 1) * sizeof(float)) + 15) & ~size_t(15)));
-        c32* B = A + (size_t)C * m;   // plain-sum transforms only
+        c32* B = A + (size_t)C * m;   // plain-sum transforms only (the FFT buffer A is padded, pidx)
         // next item: its system's fields are read now, used after this item's forward transform
         const bool more = coln < total_cols;
         const int hn = (qn >> 3) & sh;
@@ -518,13 +529,15 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
                 if (idx < C * n) {
                     c32 v = tp[i];
                     if (h) v = cmulc(v, tws[wk.c]);   // w_L^{h a} with h = 1, a < L
-                    A[wk.r * m + wk.c] = v;
+                    const int i = wk.r * m + wk.c;
+                    A[fft ? pidx<true>(i) : i] = v;
                 }
             }
             for (int idx = threadIdx.x + TPF * BT; idx < C * n; idx += BT, wk.next()) {
                 c32 v = gload(Tc + idx);
                 if (h) v = cmulc(v, tws[wk.c]);
-                A[wk.r * m + wk.c] = v;
+                const int i = wk.r * m + wk.c;
+                A[fft ? pidx<true>(i) : i] = v;
             }
         }
         __syncthreads();
@@ -532,7 +545,7 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
         // forward column transform of the C channels
         c32* X = A;
         if (fft) {
-            fft_dif<BT>(A, tws, C, bits, L, n);   // X at bit-reversed positions
+            fft_dif<BT, true>(A, tws, C, bits, L, n);   // X at bit-reversed positions
         } else {
             Walk wk(m);
             for (int idx = threadIdx.x; idx < C * m; idx += BT, wk.next()) {
@@ -591,15 +604,16 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
                 if (task < m * G) {
                     if constexpr (PACK == 0) {
                         if (wave_uniform)
-                            sensor_products(Ms, X, m, P, G, __builtin_amdgcn_readfirstlane(wk.r), wk.c, yx[it],
+                            sensor_products(Ms, X, m, P, G, __builtin_amdgcn_readfirstlane(wk.r), wk.c, fft, yx[it],
                                             yy[it]);
                         else
-                            sensor_products(Ms, X, m, P, G, wk.r, wk.c, yx[it], yy[it]);
+                            sensor_products(Ms, X, m, P, G, wk.r, wk.c, fft, yx[it], yy[it]);
                     } else {
                         if (wave_uniform)
-                            herm_products(Ms, X, m, P, C, __builtin_amdgcn_readfirstlane(wk.r), wk.c, yx[it], yy[it]);
+                            herm_products(Ms, X, m, P, C, __builtin_amdgcn_readfirstlane(wk.r), wk.c, fft, yx[it],
+                                          yy[it]);
                         else
-                            herm_products(Ms, X, m, P, C, wk.r, wk.c, yx[it], yy[it]);
+                            herm_products(Ms, X, m, P, C, wk.r, wk.c, fft, yx[it], yy[it]);
                     }
                 }
             }
@@ -612,8 +626,9 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
             for (int it = 0; it < TMAX; ++it, wk.next()) {
                 const int task = threadIdx.x + it * BT;
                 if (task < m * G) {
-                    Y[(2 * wk.r) * m + wk.c] = yx[it];
-                    Y[(2 * wk.r + 1) * m + wk.c] = yy[it];
+                    const int ix = (2 * wk.r) * m + wk.c, iy = ix + m;
+                    Y[fft ? pidx<true>(ix) : ix] = yx[it];
+                    Y[fft ? pidx<true>(iy) : iy] = yy[it];
                 }
             }
         }
@@ -622,11 +637,11 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
         // this item's share of the inverse column transform, rows a < n
         c32* Uo = s.U + ((size_t)f2 * S + h) * C * n;
         if (fft) {
-            fft_dit_inv<BT>(Y, tws, C, bits, L);
+            fft_dit_inv<BT, true>(Y, tws, C, bits, L);
             Walk wk(n);
             for (int idx = threadIdx.x; idx < C * n; idx += BT, wk.next()) {
                 const int a = wk.c;
-                c32 v = Y[wk.r * m + a];
+                c32 v = Y[pidx<true>(wk.r * m + a)];
                 if (h) v = cmul(v, tws[a]);
                 gstore(Uo + idx, v);
             }
@@ -664,7 +679,7 @@ size_t col_work_lds(int G, int L, int S, int pack) {
     const int m = L / S, C = 2 * G, P = pack ? C * C : 3 * G * G;
     const bool fft = (m & (m - 1)) == 0;
     const size_t ms = (((size_t)m * (P + 1) * sizeof(float)) + 15) & ~size_t(15);
-    return ms + (size_t)C * m * sizeof(c32) * (fft ? 1 : 2);
+    return ms + (fft ? ((size_t)C * m + (size_t)C * m / 16 + 1) * sizeof(c32) : (size_t)C * m * sizeof(c32) * 2);
 }
 
 }  // namespace
