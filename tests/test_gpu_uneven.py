@@ -1,0 +1,62 @@
+"""Batched products and batched solves on uneven systems (grids 40 / 60 / 74 /
+84, 4-8 LGS, 10-35 layers, noise 0.01-0.5 rad^2, L = 128 or 256), through the
+C ABI, against the oracle's FP64 step-by-step 2RBT operator of each system
+(itself pinned to the dense product on small grids).
+
+Products: 3e-6 of the largest entry (FP32 spectra and transforms).  Solves
+(batched CG and batched PCG, one measured frame per system): every frame
+certified by the library's FP64 residual, and the residual recomputed with
+the oracle's operator within 1.01 x tol."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_helpers import make_system, rel_maxabs, say, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def uneven():
+    from oracle.covariance import kernel_tables
+    from oracle.toeplitz import ToeplitzOperator
+    wls = [W.uneven_family(i) for i in range(4)]
+    say("uneven systems:", [wl.name for wl in wls])
+    systems = [make_system(wl, target=False) for wl in wls]
+    workers = min(16, os.cpu_count() or 1)
+    say("uneven systems: oracle tables with", workers, "workers")
+    ops = [ToeplitzOperator(wl, tables=kernel_tables(wl, workers=workers)) for wl in wls]
+    return wls, systems, ops
+
+
+def test_uneven_batched_product(uneven):
+    import torch
+    from paper_1806_07938_amd import matvec_batch
+    wls, systems, ops = uneven
+    dev = torch_dev()
+    rng = np.random.default_rng(21)
+    xs = [rng.standard_normal(wl.n_slopes).astype(np.float32) for wl in wls]
+    ys = matvec_batch([c for c, k in systems], [torch.tensor(x, device=dev) for x in xs])
+    for wl, op, x, y in zip(wls, ops, xs, ys):
+        assert rel_maxabs(y.cpu().numpy(), op(x.astype(np.float64))) < 3e-6, wl.name
+
+
+@pytest.mark.parametrize("pc", [0, 1], ids=["cg", "pcg"])
+def test_uneven_batched_solves(uneven, pc):
+    import torch
+    from paper_1806_07938_amd import solve_batch
+    from paper_1806_07938_amd.tt import SOLVER_BATCHED
+    wls, systems, ops = uneven
+    dev = torch_dev()
+    S = [W.turbulent_slopes(wl)[0].astype(np.float32) for wl in wls]
+    tol = 1e-6
+    zs, _, infos, st = solve_batch([c for c, k in systems], [torch.tensor(s, device=dev) for s in S], tol=tol,
+                                   solver=SOLVER_BATCHED, preconditioner=pc)
+    assert st == 0
+    for wl, op, s, z, inf in zip(wls, ops, S, zs, infos):
+        say("uneven", "pcg" if pc else "cg", wl.name, "iterations", inf.iterations, "rel", inf.rel_residual)
+        assert inf.status == 0 and inf.rel_residual <= tol
+        sd = s.astype(np.float64)
+        assert np.linalg.norm(sd - op(z.cpu().numpy())) <= 1.01 * tol * np.linalg.norm(sd), wl.name

@@ -19,6 +19,8 @@ with the readings listed in each constructor):
       system of Table 2, whose 35-layer profile is only given as a figure.
   lgs6_74x74_family(i)  the 74x74 geometry with seeded layer weights and r0 in
       [0.10, 0.25] m: distinct systems for batched products (L = 256 by default).
+  uneven_family(i)  uneven systems (grids 40 / 60 / 74 / 84, 4-8 LGS, 10-35
+      layers, noise 0.01-0.5 rad^2) for batched solves of different systems.
   tiny(...)  small seeded variants (n = 2..8, 1-4 guide stars, NGS or LGS)
              used for exhaustive CPU checks.
 
@@ -151,6 +153,26 @@ def lgs6_74x74_family(index: int, pad_L: int = 256) -> Workload:
         name=f"lgs6_74x74_v{index}", n=n, D=D, obstruction=obs, gs=ring(6, 60 * ARCSEC), h_lgs=90e3,
         h=h, w=w, r0=r0, L0=25.0, noise_var=0.1, pad_L=pad_L,
         valid=pupil_mask(n, D, obs))
+
+
+def uneven_family(index: int) -> Workload:
+    """Uneven systems for batched solves: grid n from (40, 60, 74, 84) in turn,
+    4-8 LGS at 90 km on a 40-70 arcsec ring, 10-35 layers (geometric altitudes
+    30 m - 26.5 km, weights as c2_profile with seed SEED + 100 + index), r0 in
+    [0.10, 0.25] m, noise variance in [0.01, 0.5] rad^2, 28 % obstruction on a
+    pupil of 0.527 m per subaperture, L the smallest power of two >= 2n."""
+    rng = np.random.default_rng(SEED + 100 + int(index))
+    n = (40, 60, 74, 84)[int(index) % 4]
+    n_gs = int(rng.integers(4, 9))
+    n_layer = int(rng.integers(10, 36))
+    h, w = c2_profile(seed=SEED + 100 + int(index), n_layer=n_layer)
+    D = 0.52703 * n
+    L = 1 << (2 * n - 1).bit_length()
+    return Workload(
+        name=f"uneven_{index}_n{n}_g{n_gs}_l{n_layer}", n=n, D=D, obstruction=0.28,
+        gs=ring(n_gs, float(rng.uniform(40, 70)) * ARCSEC), h_lgs=90e3, h=h, w=w,
+        r0=float(rng.uniform(0.10, 0.25)), L0=25.0, noise_var=float(rng.uniform(0.01, 0.5)), pad_L=L,
+        valid=pupil_mask(n, D, 0.28))
 
 
 def tiny(n: int = 4, n_gs: int = 2, lgs: bool = True, n_layer: int = 2,
