@@ -10,8 +10,8 @@
 //   row_fwd : T[f2][c][a] = sum_{b<n} x_c[a][b] w_L^{f2 b},        w_L = exp(-2 pi i / L)
 //   col     : column work item (system, f2, h), h < S, owns the frequencies
 //             f1 = S k + h, k < m = L / S.  As the input column is zero for
-//             a >= n and m >= n,
-//               X[S k + h] = sum_{a<n} (T[f2][c][a] w_L^{h a}) w_m^{k a},
+//             a >= n and w_m^{k a} depends on a mod m only,
+//               X[S k + h] = sum_{a<n} (T[f2][c][a] w_L^{h a}) w_m^{k (a mod m)},
 //             an m-point DFT of the twisted column: an FFT in LDS when m is a
 //             power of two (radix-2 decimation in frequency, output in
 //             bit-reversed order), the plain sum otherwise.  Products with the
@@ -21,7 +21,11 @@
 //   row_inv : y_p[a][b] = L^-2 sum_{f2} wt(f2) Re(sum_h U_h[f2][p][a] w_L^{-f2 b}) + noise,
 //             restricted to the valid subapertures (S2, W_s).
 //
-// S = 2 when every L of the batch is even (then L >= 2n gives m >= n), else 1.
+// S = 2 when every L of the batch is even (then L >= 2n gives m >= n), else 1;
+// the preconditioner (C^2 reals per frequency, twice the LDS) takes S = 4 when
+// every L is a multiple of 4: then m = L / 4 may be below n (never below n / 2)
+// and the column is folded, entry a going to a mod m with the same twist, and
+// the inverse share of row a is read at a mod m.
 // The two items of one column get item numbers 8 apart, which land on the same
 // XCD at nearly the same time, so the column of T and the cache lines shared
 // by neighbouring frequencies are read from HBM once.  Column workgroups are
@@ -469,9 +473,9 @@ template <int VEC, int PACK>
 __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, const int* __restrict__ col_sys,
                                                  int total_cols, int S, int Lmax) {
     extern __shared__ __align__(16) char smem_raw[];
-    const int sh = S - 1;   // S is 1 or 2
+    const int sh = S == 4 ? 2 : S - 1, hm = S - 1;   // S is 1, 2 or 4
     int q = blockIdx.x;
-    int col = ((q >> 3) >> sh) * 8 + (q & 7), h = (q >> 3) & sh;
+    int col = ((q >> 3) >> sh) * 8 + (q & 7), h = (q >> 3) & hm;
     if (col >= total_cols) return;
     c32* tws = reinterpret_cast<c32*>(smem_raw);   // twiddles of the current L
     char* work = smem_raw + (((size_t)Lmax * sizeof(c32) + 15) & ~size_t(15));
@@ -507,7 +511,7 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
         c32* B = A + (size_t)C * m;   // plain-sum transforms only (the FFT buffer A is padded, pidx)
         // next item: its system's fields are read now, used after this item's forward transform
         const bool more = coln < total_cols;
-        const int hn = (qn >> 3) & sh;
+        const int hn = (qn >> 3) & hm;
         const BSys& sn = sys[sin_];
         const float* Mn = sn.M;
         const c32* Tn = sn.T;
@@ -519,25 +523,29 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
             prevL = L;
             __syncthreads();
         }
-        // twisted input column (entries a >= n are zero and never read)
+        // twisted input column folded to length m: entry a < n goes to a mod m
+        // (m >= n / 2, so at most two terms: those with a >= m are added in a
+        // second pass); entries from min(n, m) on are zero and never read
         {
             const c32* Tc = s.T + (size_t)f2 * C * n;
-            Walk wk(n);
+            auto fold = [&](c32 v, int c, int a, bool add) {
+                int hw = h * a;   // < 2L
+                if (hw >= L) hw -= L;
+                if (h) v = cmulc(v, tws[hw]);   // w_L^{h a}
+                const int i = c * m + (add ? a - m : a);
+                const int li = fft ? pidx<true>(i) : i;
+                A[li] = add ? cadd(A[li], v) : v;
+            };
+            for (int pass = 0; pass < (n > m ? 2 : 1); ++pass) {
+                if (pass) __syncthreads();
+                Walk wk(n);
 #pragma unroll
-            for (int i = 0; i < TPF; ++i, wk.next()) {
-                const int idx = threadIdx.x + i * BT;
-                if (idx < C * n) {
-                    c32 v = tp[i];
-                    if (h) v = cmulc(v, tws[wk.c]);   // w_L^{h a} with h = 1, a < L
-                    const int i = wk.r * m + wk.c;
-                    A[fft ? pidx<true>(i) : i] = v;
+                for (int i = 0; i < TPF; ++i, wk.next()) {
+                    const int idx = threadIdx.x + i * BT;
+                    if (idx < C * n && (wk.c >= m) == (pass == 1)) fold(tp[i], wk.r, wk.c, pass == 1);
                 }
-            }
-            for (int idx = threadIdx.x + TPF * BT; idx < C * n; idx += BT, wk.next()) {
-                c32 v = gload(Tc + idx);
-                if (h) v = cmulc(v, tws[wk.c]);
-                const int i = wk.r * m + wk.c;
-                A[fft ? pidx<true>(i) : i] = v;
+                for (int idx = threadIdx.x + TPF * BT; idx < C * n; idx += BT, wk.next())
+                    if ((wk.c >= m) == (pass == 1)) fold(gload(Tc + idx), wk.r, wk.c, pass == 1);
             }
         }
         __syncthreads();
@@ -545,7 +553,7 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
         // forward column transform of the C channels
         c32* X = A;
         if (fft) {
-            fft_dif<BT, true>(A, tws, C, bits, L, n);   // X at bit-reversed positions
+            fft_dif<BT, true>(A, tws, C, bits, L, n < m ? n : m);   // X at bit-reversed positions
         } else {
             Walk wk(m);
             for (int idx = threadIdx.x; idx < C * m; idx += BT, wk.next()) {
@@ -553,7 +561,7 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
                 float re = 0.f, im = 0.f;
                 int e = 0;
                 const int de = (S * wk.c) % L;
-                for (int a = 0; a < n; ++a) {
+                for (int a = 0; a < (n < m ? n : m); ++a) {
                     const c32 t = in[a], w = tws[e];
                     re += t.x * w.x + t.y * w.y;
                     im += t.y * w.x - t.x * w.y;
@@ -640,9 +648,13 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
             fft_dit_inv<BT, true>(Y, tws, C, bits, L);
             Walk wk(n);
             for (int idx = threadIdx.x; idx < C * n; idx += BT, wk.next()) {
-                const int a = wk.c;
-                c32 v = Y[pidx<true>(wk.r * m + a)];
-                if (h) v = cmul(v, tws[a]);
+                const int a = wk.c;   // V at a mod m, a < n <= 2m
+                c32 v = Y[pidx<true>(wk.r * m + (a < m ? a : a - m))];
+                if (h) {
+                    int hw = h * a;
+                    if (hw >= L) hw -= L;
+                    v = cmul(v, tws[hw]);   // w_L^{-h a}
+                }
                 gstore(Uo + idx, v);
             }
         } else {
@@ -651,7 +663,7 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
                 const int a = wk.c;
                 const c32* yv = Y + wk.r * m;
                 float re = 0.f, im = 0.f;
-                int e = h ? a : 0;
+                int e = (h * a) % L;
                 const int de = (S * a) % L;
                 for (int k = 0; k < m; ++k) {
                     const c32 y = yv[k], w = tws[e];
@@ -710,9 +722,11 @@ tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x
         TT_REQUIRE(std::adjacent_find(sorted.begin(), sorted.end()) == sorted.end(),
                    "a context appears twice in the batch");
     }
-    int S = 2;
-    for (int i = 0; i < count; ++i)
+    int S = op ? 4 : 2;
+    for (int i = 0; i < count; ++i) {
+        if (systems[i]->L % 4) S = std::min(S, 2);
         if (systems[i]->L % 2) S = 1;
+    }
     size_t work = 0;
     int Lmax = 0, fwd_tiles = 0, inv_tiles = 0;
     for (int i = 0; i < count; ++i) {

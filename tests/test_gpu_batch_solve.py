@@ -130,3 +130,23 @@ def test_batched_solver_statuses_and_errors():
         solve_batch(ctxs[:2], S[:2], solver=SOLVER_BATCHED)
     assert e.value.status == TT_INVALID_ARG
     ctxs[1].set_mode_removal(False)
+
+
+def test_batched_pcg_four_way_split():
+    # every pad_L a multiple of 4: the preconditioner's column items take a
+    # quarter of the frequencies each, m = L / 4 below n (folded input), in
+    # plain sums (L = 12, 20) and FFTs (L = 16, 32)
+    import torch
+    from paper_1806_07938_amd import solve_batch
+    from paper_1806_07938_amd.tt import PRECOND_CIRCULANT, SOLVER_BATCHED
+    wls = [W.lgs3_10x10(), W.tiny(n=6, n_gs=2, lgs=True, n_layer=3, seed=4, pad_L=12),
+           W.tiny(n=8, n_gs=4, lgs=False, n_layer=2, seed=6, pad_L=16), W.lgs3_10x10(pad_L=32)]
+    systems = [make_system(wl, target=False) for wl in wls]
+    dev = torch_dev()
+    S = [torch.tensor(W.turbulent_slopes(wl)[0].astype(np.float32), device=dev) for wl in wls]
+    zs, _, infos, st = solve_batch([c for c, k in systems], S, tol=1e-8, solver=SOLVER_BATCHED,
+                                   preconditioner=PRECOND_CIRCULANT)
+    assert st == 0
+    for wl, s, z, inf in zip(wls, S, zs, infos):
+        say("batched pcg, four-way split", wl.name, "L", wl.pad_L, "iterations", inf.iterations)
+        _check_frame(wl, s.cpu().numpy(), z.cpu().numpy(), 1e-8, inf)
