@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--batch-pad", type=int, default=256, help="FFT side L of the batched systems")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--batch-only", action="store_true", help="run only the batched-product measurement")
+    ap.add_argument("--batch-solve-frames", type=int, default=0,
+                    help="with --batch-only: also time the batched solves (plain and preconditioned CG) with this "
+                         "many measured frames of lgs6_74x74 as right-hand sides")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 256 MiB device buffer 3 times (reference kernel for rocprofv3 "
                          "FETCH_SIZE / WRITE_SIZE scale factors)")
@@ -242,7 +245,12 @@ def main():
         del cx, cy
     if args.batch_only:
         bctx, bkeep, bsetup = batch_systems(args)
-        print(json.dumps({"batch_matvec": batch_matvec(args, bctx, bsetup)}), flush=True)
+        res = {"batch_matvec": batch_matvec(args, bctx, bsetup)}
+        if args.batch_solve_frames > 0:
+            fr = W.turbulent_slopes(W.lgs6_74x74(), frames=args.batch_solve_frames).astype(np.float32)
+            res["batch_solve"] = batch_solve(args, bctx, fr, 0)
+            res["batch_solve_pcg"] = batch_solve(args, bctx, fr, 1)
+        print(json.dumps(res), flush=True)
         return
     wl = W.lgs6_74x74(pad_L=args.pad)
     frames = W.turbulent_slopes(wl, frames=args.frames).astype(np.float32)
