@@ -50,7 +50,8 @@ def parse():
                     help="timed form (the FP16 / BF16 column-transform forms are reported under variants)")
     ap.add_argument("--solver", choices=["persistent", "kernels"], default="persistent")
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--preconditioner", choices=["circulant", "none"], default="circulant")
+    ap.add_argument("--preconditioner", choices=["circulant", "none"], default="none",
+                    help="headline solver: plain CG (the method, default) or CG with the block-circulant inverse")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the FP64 / kernel-solver side numbers")
     ap.add_argument("--batch", type=int, default=64,
@@ -86,23 +87,41 @@ def traffic_record(pc):
         return None
 
 
-def cpu_baseline(wl, s_frame, tol):
-    """FP64 oracle: CG (textbook) with the step-by-step 2RBT product, one frame."""
-    from oracle.covariance import kernel_tables
+def _oracle_cg_frame(args):
+    """One frame through the oracle's FP64 CG (worker process, one BLAS thread)."""
+    from threadpoolctl import threadpool_limits
     from oracle.solve import cg
+    op, s, tol = args
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        x, it = cg(op, s, tol=tol, maxiter=20000)
+        return time.perf_counter() - t0, it
+
+
+def cpu_baseline(wl, frames, tol):
+    """FP64 oracle as it stands (textbook CG with its step-by-step 2RBT product,
+    numpy FFTs) on every host core: one frame per worker process, as many
+    frames as workers, solved concurrently; ms per solve = wall time / frames."""
+    import multiprocessing as mp
+    from oracle.covariance import kernel_tables
     from oracle.toeplitz import ToeplitzOperator
-    workers = min(16, os.cpu_count() or 1)
+    workers = max(1, min(16, os.cpu_count() or 1, len(frames)))
     t0 = time.perf_counter()
     op = ToeplitzOperator(wl, tables=kernel_tables(wl, workers=workers))
     setup = time.perf_counter() - t0
+    jobs = [(op, frames[i].astype(np.float64), tol) for i in range(workers)]
     t0 = time.perf_counter()
-    x, it = cg(op, s_frame.astype(np.float64), tol=tol, maxiter=20000)
-    solve_s = time.perf_counter() - t0
+    with mp.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_oracle_cg_frame, jobs, chunksize=1)
+    wall = time.perf_counter() - t0
+    its = [it for _, it in res]
     return {
-        "value": round(solve_s * 1e3, 1), "unit": "ms per solve", "cores": 1, "kind": "oracle",
-        "sample": (f"one frame of the same workload, FP64 CG to rel. residual {tol:g} ({it} iterations) with the "
-                   f"oracle's numpy 2RBT product (single-threaded FFTs); covariance tables built beforehand in "
-                   f"{setup:.1f} s on {workers} processes, not included"),
+        "value": round(wall * 1e3 / workers, 1), "unit": "ms per solve", "cores": workers, "kind": "oracle",
+        "sample": (f"{workers} frames of the same workload solved concurrently, one per process on {workers} host "
+                   f"cores (one BLAS thread each): FP64 textbook CG to rel. residual {tol:g} "
+                   f"({min(its)}-{max(its)} iterations) with the oracle's numpy 2RBT product; wall {wall:.1f} s for "
+                   f"the {workers} solves, single-frame time {np.median([t for t, _ in res]):.1f} s; covariance "
+                   f"tables built beforehand in {setup:.1f} s, not included"),
     }
 
 
@@ -222,6 +241,38 @@ def batch_matvec(args, ctxs, setup_s):
     }
 
 
+def persistent_roofline(infos, wl, info, prec, pc, pad):
+    """Roofline of the persistent solver kernel.  Algorithmic bytes per
+    iteration are those of one 2RBT product (the packed slope spectra and the
+    slopes in and out); with a preconditioner its spectra are reported apart
+    and are not counted in frac."""
+    kms = np.array([i.kernel_ms for i in infos])
+    if kms.sum() <= 0:
+        return None
+    iters = np.array([i.iterations for i in infos], dtype=np.float64)
+    launches = np.array([i.kernel_launches for i in infos], dtype=np.float64)
+    from paper_1806_07938_amd.tt import PREC_F32
+    elem = 4 if prec == PREC_F32 else 8
+    spectra = info["spectra_bytes_f32"] if prec == PREC_F32 else info["spectra_bytes_f64"]
+    bytes_iter = spectra + 2 * wl.n_slopes * elem
+    C = 2 * wl.n_gs
+    pc_bytes = pad * (pad // 2 + 1) * C * C * elem if pc else 0   # general Hermitian packing
+    avg_launch_ms = kms.sum() / launches.sum()
+    ipl = iters.sum() / launches.sum()
+    achieved = bytes_iter * ipl / (avg_launch_ms * 1e-3) / 1e9
+    tpi = traffic_record(pc) if (prec == PREC_F32 and pad == 148) else None
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": round(tpi * ipl) if tpi else None,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
+            "kernel": (f"k_cg_persistent<float, true, 1, {1 if pc else 0}> (FP32 column transforms on the matrix "
+                       "cores)" if prec == PREC_F32 else f"k_cg_persistent<double, true, 0, {1 if pc else 0}>"),
+            "avg_launch_ms": round(avg_launch_ms, 4), "bytes_per_iteration": int(bytes_iter),
+            "bytes_per_iteration_basis": "packed slope spectra + slopes in and out (one 2RBT product)",
+            "preconditioner_spectra_bytes_per_iteration": int(pc_bytes) if pc else None,
+            "iterations_per_launch": round(float(ipl), 1)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -233,7 +284,7 @@ def main():
     from paper_1806_07938_amd import Context, system_from
     from paper_1806_07938_amd.tt import (METHOD_CG, METHOD_MINRES, PRECOND_CIRCULANT, PRECOND_NONE, PREC_BF16,
                                          PREC_F16, PREC_F32, PREC_F64, SOLVER_KERNELS, SOLVER_PERSISTENT,
-                                         TT_NOT_CONVERGED)
+                                         TT_NOT_CONVERGED, close_all)
 
     dev = torch.device("cuda:0")
     if args.copy_calibration:
@@ -250,6 +301,8 @@ def main():
             fr = W.turbulent_slopes(W.lgs6_74x74(), frames=args.batch_solve_frames).astype(np.float32)
             res["batch_solve"] = batch_solve(args, bctx, fr, 0)
             res["batch_solve_pcg"] = batch_solve(args, bctx, fr, 1)
+        torch.cuda.synchronize()
+        close_all()
         print(json.dumps(res), flush=True)
         return
     wl = W.lgs6_74x74(pad_L=args.pad)
@@ -293,31 +346,10 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
 
     iters = np.array([i.iterations for i in infos], dtype=np.float64)
-    kms = np.array([i.kernel_ms for i in infos])
-    launches = np.array([i.kernel_launches for i in infos], dtype=np.float64)
     relres = max(i.rel_residual for i in infos)
     ok = all(i.status == 0 for i in infos) and relres <= args.tol
-
-    spectra = info["spectra_bytes_f32"] if prec == PREC_F32 else info["spectra_bytes_f64"]
-    elem = 4 if prec == PREC_F32 else 8
-    C = 2 * wl.n_gs
-    pc_spectra = args.pad * (args.pad // 2 + 1) * C * C * elem if pc else 0   # general Hermitian packing
-    bytes_iter = spectra + pc_spectra + 2 * wl.n_slopes * elem
-    roofline = None
-    if solver == SOLVER_PERSISTENT and kms.sum() > 0:
-        avg_launch_ms = kms.sum() / launches.sum()
-        bytes_launch = bytes_iter * iters.sum() / launches.sum()
-        achieved = bytes_launch / (avg_launch_ms * 1e-3) / 1e9
-        tpi = traffic_record(pc) if (prec == PREC_F32 and args.pad == 148) else None
-        traffic = round(tpi * iters.sum() / launches.sum()) if tpi else None
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
-                    "kernel": (f"k_cg_persistent<float, true, 1, {1 if pc else 0}> (FP32 column "
-                               "transforms on the matrix cores)" if prec == PREC_F32 else
-                               f"k_cg_persistent<double, true, 0, {1 if pc else 0}>"),
-                    "avg_launch_ms": round(avg_launch_ms, 4), "bytes_per_iteration": int(bytes_iter),
-                    "iterations_per_launch": round(float(iters.sum() / launches.sum()), 1)}
+    roofline = persistent_roofline(infos, wl, info, prec, pc, args.pad) if solver == SOLVER_PERSISTENT else None
+    method_name = "CG preconditioned by the block-circulant inverse" if pc else "plain CG"
 
     out = {
         "metric": METRIC, "value": round(ms_per_step, 4), "unit": "ms", "n_gpus": 1,
@@ -326,9 +358,8 @@ def main():
         "dtype": "f32" if prec == PREC_F32 else "f64", "data": "synthetic",
         "config": {"workload": (f"39 m pupil, 28% obstruction, 74x74 SH (3972 valid/WFS), 6 LGS at 90 km on a 60 "
                                 f"arcsec ring, 35 layers 30 m-26.5 km, r0 0.157 m, L0 25 m, sigma^2 0.1 rad^2, "
-                                f"L={args.pad}, on-axis target; "
-                                + ("CG preconditioned by the block-circulant inverse" if pc else "plain CG")
-                                + f" to rel. residual {args.tol:g}"),
+                                f"L={args.pad}, on-axis target; {method_name} to rel. residual {args.tol:g}, "
+                                f"then the LGS projection"),
                    "n": wl.n, "n_gs": wl.n_gs, "n_layer": wl.n_layer, "n_slopes": wl.n_slopes, "pad_L": args.pad,
                    "solver": args.solver, "preconditioner": "circulant" if pc else "none",
                    "precision": args.precision + ("+f64 residual replacement" if prec == PREC_F32 else ""),
@@ -343,20 +374,16 @@ def main():
     }
     if not args.no_variants:
         side = {}
-        # other forms on frames 0-2: FP64 throughout, FP32 with one launch per
-        # phase, and the FP16 / BF16 column-transform forms (which may stop
-        # short of the tolerance: status and the FP64 residual reached are
+        # other forms on frames 0-2 (status and the FP64 residual reached are
         # reported per frame)
         CG, MR = METHOD_CG, METHOD_MINRES
         for name, p, sv, vpc, mth in (("f32_persistent_plain_cg", PREC_F32, SOLVER_PERSISTENT, PRECOND_NONE, CG),
-                                      ("f32_persistent_pcg", PREC_F32, SOLVER_PERSISTENT, PRECOND_CIRCULANT, CG),
+                                      ("f32_persistent_circulant_pcg", PREC_F32, SOLVER_PERSISTENT, PRECOND_CIRCULANT, CG),
                                       ("f32_persistent_minres", PREC_F32, SOLVER_PERSISTENT, PRECOND_NONE, MR),
                                       ("f64_persistent_plain_cg", PREC_F64, SOLVER_PERSISTENT, PRECOND_NONE, CG),
-                                      ("f64_persistent_pcg", PREC_F64, SOLVER_PERSISTENT, PRECOND_CIRCULANT, CG),
+                                      ("f64_persistent_circulant_pcg", PREC_F64, SOLVER_PERSISTENT, PRECOND_CIRCULANT, CG),
                                       ("f64_persistent_minres", PREC_F64, SOLVER_PERSISTENT, PRECOND_NONE, MR),
-                                      ("f32_kernels_plain_cg", PREC_F32, SOLVER_KERNELS, PRECOND_NONE, CG),
-                                      ("f16_persistent_plain_cg", PREC_F16, SOLVER_PERSISTENT, PRECOND_NONE, CG),
-                                      ("bf16_persistent_plain_cg", PREC_BF16, SOLVER_PERSISTENT, PRECOND_NONE, CG)):
+                                      ("f32_kernels_plain_cg", PREC_F32, SOLVER_KERNELS, PRECOND_NONE, CG)):
             if p == prec and sv == solver and vpc == pc and mth == CG:
                 continue
             allow = (0, TT_NOT_CONVERGED)
@@ -370,14 +397,18 @@ def main():
                           "status": [int(i.status) for i in ii],
                           "rel_residual": [float(f"{i.rel_residual:.3e}") for i in ii],
                           "converged": all(i.status == 0 and i.rel_residual <= args.tol for i in ii)}
+            if sv == SOLVER_PERSISTENT and mth == CG:
+                side[name]["roofline"] = persistent_roofline(ii, wl, info, p, vpc, args.pad)
         out["variants"] = side
     if args.batch > 0:
         bctx, bkeep, bsetup = batch_systems(args)
         out["batch_matvec"] = batch_matvec(args, bctx, bsetup)
         out["batch_solve"] = batch_solve(args, bctx, frames, 0)
         out["batch_solve_pcg"] = batch_solve(args, bctx, frames, 1)
+    torch.cuda.synchronize()
+    close_all()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wl, frames[0], args.tol)
+        out["cpu_baseline"] = cpu_baseline(wl, frames, args.tol)
     print(json.dumps(out), flush=True)
 
 

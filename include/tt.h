@@ -133,7 +133,10 @@ typedef struct {
     double D;                     /* pupil diameter [m]; subaperture d = D/n */
     double h_lgs;                 /* LGS altitude [m]; <= 0 or +inf: natural guide stars */
     const double* gs_xy;          /* 2*n_gs: direction (x, y) of each guide star [rad] */
-    const unsigned char* valid;   /* n*n, row-major, nonzero = valid subaperture (W_s) */
+    const unsigned char* valid;   /* n*n, row-major, nonzero = valid subaperture (W_s), or
+                                     NULL: the rule of tt_pupil_mask with `obstruction` */
+    double obstruction;           /* central obstruction (diameter ratio, [0, 1)); read only
+                                     when valid is NULL */
 } tt_geometry;
 
 /* Layered von Karman atmosphere (§2, App. A.2).  Layer k contributes
@@ -196,6 +199,15 @@ typedef struct tt_kernels tt_kernels;
  * NULL = the null stream).  Owns its device memory until tt_destroy. */
 tt_status tt_create(tt_ctx** out, int device, void* stream);
 tt_status tt_destroy(tt_ctx* ctx);
+
+/* Valid-subaperture rule of the aperture masks (§2.F): subaperture (i, j) of
+ * the n x n grid laid over [-D/2, D/2]^2 is valid when at least half of its
+ * area lies inside the annular pupil of outer diameter D and inner diameter
+ * obstruction * D (exact areas).  out: n*n bytes, row-major (1 valid, 0 not),
+ * written on success; n_valid (may be NULL) receives the count.  Host only: no
+ * device or context is needed.  TT_INVALID_ARG for n outside [1, 512], D <= 0,
+ * obstruction outside [0, 1) or out == NULL. */
+tt_status tt_pupil_mask(int n, double D, double obstruction, unsigned char* out, int* n_valid);
 
 /* Covariance generation, FP64 on the device (App. A.2 Hudgin slope-slope
  * equations with the §2.D cone scaling).  For every

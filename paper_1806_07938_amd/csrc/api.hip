@@ -64,10 +64,17 @@ tt_status generate_impl(tt_ctx* c, const tt_geometry* g, const tt_atmosphere* a,
     TT_REQUIRE(g->gradient_model == TT_MODEL_HUDGIN || g->gradient_model == TT_MODEL_FRIED,
                "unsupported gradient model");
     TT_REQUIRE(std::isfinite(g->D) && g->D > 0, "D must be positive");
-    TT_REQUIRE(g->gs_xy && g->valid, "gs_xy and valid are required");
+    TT_REQUIRE(g->gs_xy, "gs_xy is required");
     TT_REQUIRE(finite_all(g->gs_xy, 2 * g->n_gs), "non-finite guide-star direction");
+    // W_s: the caller's mask, or the valid-subaperture rule (§2.F) with the obstruction
+    std::vector<unsigned char> mask((size_t)g->n * g->n);
+    if (g->valid) {
+        for (int i = 0; i < g->n * g->n; ++i) mask[i] = g->valid[i] ? 1 : 0;
+    } else {
+        TT_CHECK(pupil_rule(g->n, g->D, g->obstruction, mask.data(), nullptr));
+    }
     int nv = 0;
-    for (int i = 0; i < g->n * g->n; ++i) nv += g->valid[i] != 0;
+    for (int i = 0; i < g->n * g->n; ++i) nv += mask[i] != 0;
     TT_REQUIRE(nv > 0, "no valid subaperture");
     TT_REQUIRE(a->n_layer >= 1 && a->n_layer <= 256, "n_layer must be in [1, 256]");
     TT_REQUIRE(a->h && a->w, "h and w are required");
@@ -90,8 +97,7 @@ tt_status generate_impl(tt_ctx* c, const tt_geometry* g, const tt_atmosphere* a,
     k->h_lgs = g->h_lgs;
     k->lgs = lgs;
     k->gs.assign(g->gs_xy, g->gs_xy + 2 * g->n_gs);
-    k->valid.resize((size_t)g->n * g->n);
-    for (int i = 0; i < g->n * g->n; ++i) k->valid[i] = g->valid[i] ? 1 : 0;
+    k->valid = mask;
     k->n_layer = a->n_layer;
     k->h.assign(a->h, a->h + a->n_layer);
     k->w.assign(a->w, a->w + a->n_layer);

@@ -1426,6 +1426,12 @@ tt_status solve_persistent_t(tt_ctx& c, const float* s, const double* x0, double
     int S = std::max(1, nwg / std::max(c.Lh, 1));
     S = std::min(S, std::max(1, c.L / 8));
     const int Lrm = (c.L + S - 1) / S;
+    // every column unit (f2, f1 range) is owned by one block for the whole launch
+    if (c.Lh * S > nwg) {
+        tt_set_error("persistent solver: pad_L / 2 + 1 frequency columns exceed the compute units; use "
+                     "TT_SOLVER_KERNELS or TT_SOLVER_BATCHED");
+        return TT_INVALID_ARG;
+    }
     const size_t lim = 160 * 1024 - 512;   // minus the static LDS (reduction scratch and flags)
     // rows per block: all of a block's rows at once when they fit the threads
     const int rows_per_block = (c.C * c.n + nwg - 1) / nwg;

@@ -241,5 +241,8 @@ tt_status modes_project_phase(tt_ctx& c, float* phi);
 tt_status projection_setup(tt_ctx& c, const tt_target* t);
 tt_status projection_apply(tt_ctx& c, const double* zeta, float* phi);
 
+// pupil.hip: the valid-subaperture rule (tt_pupil_mask)
+tt_status pupil_rule(int n, double D, double obstruction, unsigned char* out, int* n_valid);
+
 // launch-shape helper
 inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }

@@ -8,9 +8,12 @@ library raises: there is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import math
 import os
+import sys
+import weakref
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -30,7 +33,7 @@ MODEL_HUDGIN, MODEL_FRIED = 0, 1
 EXPORTED = (
     "tt_create", "tt_destroy", "tt_generate_kernels", "tt_kernels_destroy", "tt_kernels_copy",
     "tt_set_system", "tt_set_noise_xy", "tt_set_mode_removal", "tt_get_system_info", "tt_matvec", "tt_matvec_f64", "tt_matvec_batch",
-    "tt_solve_frame", "tt_solve_batch", "tt_project", "tt_status_string", "tt_last_error",
+    "tt_solve_frame", "tt_solve_batch", "tt_project", "tt_status_string", "tt_last_error", "tt_pupil_mask",
 )
 
 
@@ -43,7 +46,7 @@ class TTError(RuntimeError):
 class _Geometry(C.Structure):
     _fields_ = [("n", C.c_int), ("n_gs", C.c_int), ("pad_L", C.c_int), ("gradient_model", C.c_int),
                 ("D", C.c_double), ("h_lgs", C.c_double), ("gs_xy", C.POINTER(C.c_double)),
-                ("valid", C.POINTER(C.c_ubyte))]
+                ("valid", C.POINTER(C.c_ubyte)), ("obstruction", C.c_double)]
 
 
 class _Atmosphere(C.Structure):
@@ -75,6 +78,35 @@ class _SystemInfo(C.Structure):
 
 _lib = None
 
+# Library handles still open.  They are closed by an exit hook registered after
+# torch has initialised the device (exit hooks run last-registered first, so
+# before torch's own teardown and before the HIP runtime's static destructors);
+# a handle found open during interpreter finalisation is left to the process
+# exit instead of calling into HIP from a finaliser.
+_open_handles = weakref.WeakSet()
+_exit_hook = False
+
+
+def _close_open_handles():
+    for h in list(_open_handles):
+        try:
+            h.close()
+        except Exception:
+            pass
+
+
+def close_all():
+    """Close every library handle still open (contexts and kernel tables)."""
+    _close_open_handles()
+
+
+def _track(obj):
+    global _exit_hook
+    _open_handles.add(obj)
+    if not _exit_hook:
+        atexit.register(_close_open_handles)
+        _exit_hook = True
+
 
 def load(path: str = LIB_PATH):
     """Load libtt.so (once).  Raises RuntimeError if it is not built."""
@@ -100,6 +132,7 @@ def load(path: str = LIB_PATH):
     lib.tt_project.argtypes = [vp, vp, vp]
     lib.tt_solve_batch.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
                                    C.POINTER(vp), C.POINTER(_SolveOpts), C.POINTER(_SolveInfo)]
+    lib.tt_pupil_mask.argtypes = [C.c_int, C.c_double, C.c_double, C.POINTER(C.c_ubyte), C.POINTER(C.c_int)]
     lib.tt_status_string.argtypes = [C.c_int]
     lib.tt_status_string.restype = C.c_char_p
     lib.tt_last_error.argtypes = []
@@ -152,6 +185,7 @@ class Kernels:
     def __init__(self, handle, n, n_gs):
         self._h = handle
         self.n, self.n_gs = n, n_gs
+        _track(self)
 
     @property
     def count(self):
@@ -171,6 +205,8 @@ class Kernels:
             self._h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -192,17 +228,22 @@ class Context:
         self._h = h
         self.device = device
         self._keep = []
+        _track(self)
 
     # -- set-up -----------------------------------------------------------
     def generate_kernels(self, n: int, n_gs: int, pad_L: int, D: float, h_lgs: float,
                          gs_xy: Sequence[Sequence[float]], valid, h, w, r0: float, L0: float,
-                         model: int = MODEL_HUDGIN) -> Kernels:
+                         model: int = MODEL_HUDGIN, obstruction: float = 0.0) -> Kernels:
+        """valid None: the library's valid-subaperture rule with `obstruction`."""
         gs = np.ascontiguousarray(np.asarray(gs_xy, dtype=np.float64).reshape(-1))
-        vm = np.ascontiguousarray(np.asarray(valid, dtype=np.uint8).reshape(-1))
+        vp = None
+        if valid is not None:
+            vm = np.ascontiguousarray(np.asarray(valid, dtype=np.uint8).reshape(-1))
+            vp = vm.ctypes.data_as(C.POINTER(C.c_ubyte))
         hh = np.ascontiguousarray(np.asarray(h, dtype=np.float64))
         ww = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
         geo = _Geometry(n, n_gs, pad_L, int(model), float(D), float(h_lgs) if math.isfinite(h_lgs) else math.inf,
-                        gs.ctypes.data_as(C.POINTER(C.c_double)), vm.ctypes.data_as(C.POINTER(C.c_ubyte)))
+                        gs.ctypes.data_as(C.POINTER(C.c_double)), vp, float(obstruction))
         atm = _Atmosphere(hh.size, hh.ctypes.data_as(C.POINTER(C.c_double)),
                           ww.ctypes.data_as(C.POINTER(C.c_double)), float(r0), float(L0))
         out = C.c_void_p()
@@ -298,10 +339,23 @@ class Context:
             self._h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
             pass
+
+
+def pupil_mask(n: int, D: float, obstruction: float) -> np.ndarray:
+    """tt_pupil_mask: the library's valid-subaperture rule, (n, n) bool (host only)."""
+    out = np.zeros(n * n, dtype=np.uint8)
+    cnt = C.c_int()
+    _check(load().tt_pupil_mask(int(n), float(D), float(obstruction), out.ctypes.data_as(C.POINTER(C.c_ubyte)),
+                                C.byref(cnt)))
+    m = out.reshape(n, n).astype(bool)
+    assert int(m.sum()) == cnt.value
+    return m
 
 
 def system_from(ctx: Context, wl, target: bool = True, pad_L: Optional[int] = None, proj_pad_L: int = 0,

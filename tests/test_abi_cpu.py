@@ -103,3 +103,28 @@ def test_no_device_reports_error_not_crash(lib):
     st = lib.tt_create(C.byref(h), 0, None)
     assert st in (tt.TT_HIP_ERROR, tt.TT_INVALID_ARG)
     assert lib.tt_last_error().decode() != ""
+
+
+@pytest.mark.parametrize("n,D,obs,count", [(10, 8.0, 0.30, 76), (74, 39.0, 0.28, 3972),
+                                           (40, 0.52703 * 40, 0.28, 1168), (60, 0.52703 * 60, 0.28, 2612),
+                                           (84, 0.52703 * 84, 0.28, 5112)])
+def test_library_pupil_rule_matches_workloads(lib, n, D, obs, count):
+    """tt_pupil_mask (host only, exact areas) against the seeded workloads' mask
+    (the same half-area rule measured on a 64 x 64 point grid per subaperture)."""
+    import workloads as W
+    from paper_1806_07938_amd import tt
+    m = tt.pupil_mask(n, D, obs)
+    assert int(m.sum()) == count
+    assert np.array_equal(m, W.pupil_mask(n, D, obs))
+
+
+def test_library_pupil_rule_limits(lib):
+    from paper_1806_07938_amd import tt
+    assert tt.pupil_mask(4, 2.0, 0.0).sum() == 12        # a disk inscribed in 4 x 4 squares: the corners go
+    assert tt.pupil_mask(1, 1.0, 0.0).all()               # pi/4 of one square
+    assert not tt.pupil_mask(2, 2.0, 0.9).any()           # a thin annulus covers < 1/2 of every square
+    out = (C.c_ubyte * 16)()
+    assert lib.tt_pupil_mask(4, 1.0, 1.0, out, None) == tt.TT_INVALID_ARG
+    assert lib.tt_pupil_mask(0, 1.0, 0.0, out, None) == tt.TT_INVALID_ARG
+    assert lib.tt_pupil_mask(4, -1.0, 0.0, out, None) == tt.TT_INVALID_ARG
+    assert lib.tt_pupil_mask(4, 1.0, 0.0, None, None) == tt.TT_INVALID_ARG

@@ -158,7 +158,7 @@ def test_ngs_and_off_axis_target(solver):
     zref = cholesky_solve(system_matrix(wl), s.astype(np.float64))
     assert np.linalg.norm(z.cpu().numpy() - zref) / np.linalg.norm(zref) < 1e-5
     ref = phi_paper_dense(wl, z.cpu().numpy().astype(np.float32).astype(np.float64))
-    assert np.linalg.norm(phi.cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-5
+    assert rel_maxabs(phi.cpu().numpy(), ref) < 1e-5
     # natural guide stars: the paper's grid form is the exact product
     ex = phi_exact(wl, z.cpu().numpy().astype(np.float32).astype(np.float64))
     assert np.linalg.norm(ref - ex) / np.linalg.norm(ex) < 1e-10
@@ -232,6 +232,6 @@ def test_ngs_projection_layers_summed(n_prime):
     z32 = z.astype(np.float32).astype(np.float64)
     ref = phi_paper_dense(wl, z32, n_prime=(n_prime or None))
     say("ngs projection n'", ctx.info["n_prime"], "difference", np.linalg.norm(phi - ref) / np.linalg.norm(ref))
-    assert np.linalg.norm(phi - ref) / np.linalg.norm(ref) < 1e-5
+    assert rel_maxabs(phi, ref) < 1e-5
     if n_prime == 0:
         assert np.linalg.norm(ref - phi_exact(wl, z32)) / np.linalg.norm(ref) < 1e-10

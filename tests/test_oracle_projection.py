@@ -115,3 +115,29 @@ def test_fried_phase_slope_matches_corner_points():
                         B[:, col] += wl.w[k] * wts[p][q] * cov(rho, (c0 + 0.5 * s[k] * wl.d * corners[q])[None])
                 col += 1
     assert np.abs(A - B).max() <= 1e-11 * np.abs(B).max()
+
+
+@pytest.mark.parametrize("n,target", [(4, (0.0, 0.0)), (6, (0.0, 0.0)), (4, (4e-5, -2e-5))])
+def test_lgs_grid_nodes_on_phase_points_give_the_exact_product(n, target):
+    """Layers at h = 0 and h = H/2 (s_k = 1 and 1/2) with n even: the common grid
+    of §2.D (n' = 2n + 1 nodes of spacing s_k d, centred on the target ray)
+    holds every phase point as a node, so the bilinear I'_k only selects nodes
+    and the paper's form equals the exact W_phi Sigma_phi_s zeta.  A slip in
+    the grid size, its centring or the node spacing moves the phase points off
+    the nodes and breaks the equality."""
+    wl = W.tiny(n=n, n_gs=3, lgs=True, n_layer=2, seed=11, mask="random")
+    wl.h = np.array([0.0, 0.5 * wl.h_lgs])
+    wl.target = target
+    assert np.allclose(G.cone_scale(wl.h, wl.h_lgs), [1.0, 0.5])
+    n_prime = P.new_grid_size(wl)
+    assert n_prime == 2 * n + 1
+    for k in range(wl.n_layer):
+        I = P.interp_matrix(wl, k, n_prime)
+        assert set(np.unique(np.round(I, 12))) <= {0.0, 1.0}
+        assert np.all(np.count_nonzero(np.abs(I) > 1e-12, axis=1) == 1)
+    z = np.random.default_rng(n).standard_normal(wl.n_slopes)
+    e = P.phi_exact(wl, z)
+    a = P.phi_paper_dense(wl, z)
+    b = P.phi_paper_fft(wl, z)
+    assert np.abs(a - e).max() <= 1e-12 * np.abs(e).max()
+    assert np.abs(b - e).max() <= 1e-12 * np.abs(e).max()
