@@ -266,6 +266,21 @@ tt_status tt_set_mode_removal(tt_ctx* ctx, int on);
 tt_status tt_matvec(tt_ctx* ctx, const float* d_x, float* d_y);
 tt_status tt_matvec_f64(tt_ctx* ctx, const double* d_x, double* d_y);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the product of
+ * tt_matvec, same kernels and bitwise the same result, with its transform work
+ * buffers taken from a fixed device array of the library instead of the
+ * context.  The call allocates and frees nothing.  The array holds 8 MiB per
+ * device (kept until the process ends); a system needs
+ * 2 (pad_L / 2 + 1) 2 n_gs n complex floats (each half rounded up to 256
+ * bytes), plus n_slopes floats with mode removal: larger systems get
+ * TT_INVALID_ARG with the sizes in tt_last_error (use tt_matvec).  The array's
+ * address is looked up when a context is created on the device; TT_HIP_ERROR
+ * if that failed.  Every call on one device shares the array: calls that
+ * overlap in time on one device (several streams or threads) race and must be
+ * ordered by the caller.  Asynchronous on the context's stream. */
+tt_status tt_matvec_noalloc(tt_ctx* ctx, const float* d_x, float* d_y);
+
 /* The same FP32 product for count independent systems in one call (the §2.E
  * product of each system, batched over systems): y_i = A_i x_i,
  * d_x[i], d_y[i] on systems[i] (n_slopes of that system each, device memory,

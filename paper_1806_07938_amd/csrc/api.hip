@@ -51,6 +51,7 @@ tt_status create_impl(tt_ctx** out, int device, void* stream) {
         return TT_HIP_ERROR;
     }
     c->num_cu = prop.multiProcessorCount;
+    noalloc_init(device);   // scratch address of tt_matvec_noalloc on this device
     *out = c;
     return TT_OK;
 }

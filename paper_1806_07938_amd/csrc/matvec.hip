@@ -227,6 +227,12 @@ tt_status matvec_f32(tt_ctx& c, const float* x, float* y, double* part) {
                            c.has_nxy ? c.nxy32.p : nullptr, c.mtmp32.p);
 }
 
+// the FP32 product with caller-chosen transform work buffers (tt_matvec_noalloc)
+tt_status matvec_f32_into(tt_ctx& c, const float* x, float* y, c32* T, c32* U, float* tmp) {
+    return matvec_t<float>(c, x, y, nullptr, c.M32.p, c.tw32.p, T, U, c.noise32.p, c.has_nxy ? c.nxy32.p : nullptr,
+                           tmp);
+}
+
 tt_status matvec_f64(tt_ctx& c, const double* x, double* y, double* part) {
     return matvec_t<double>(c, x, y, part, c.M64.p, c.tw64.p, c.T64.p, c.U64.p, c.noise64.p,
                             c.has_nxy ? c.nxy64.p : nullptr, c.mtmp64.p);

@@ -241,6 +241,10 @@ tt_status modes_project_phase(tt_ctx& c, float* phi);
 tt_status projection_setup(tt_ctx& c, const tt_target* t);
 tt_status projection_apply(tt_ctx& c, const double* zeta, float* phi);
 
+// noalloc.hip: device scratch of tt_matvec_noalloc (address looked up once per device)
+void noalloc_init(int device);
+size_t noalloc_scratch_bytes();
+
 // pupil.hip: the valid-subaperture rule (tt_pupil_mask)
 tt_status pupil_rule(int n, double D, double obstruction, unsigned char* out, int* n_valid);
 

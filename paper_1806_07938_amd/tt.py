@@ -33,6 +33,7 @@ MODEL_HUDGIN, MODEL_FRIED = 0, 1
 EXPORTED = (
     "tt_create", "tt_destroy", "tt_generate_kernels", "tt_kernels_destroy", "tt_kernels_copy",
     "tt_set_system", "tt_set_noise_xy", "tt_set_mode_removal", "tt_get_system_info", "tt_matvec", "tt_matvec_f64", "tt_matvec_batch",
+    "tt_matvec_noalloc",
     "tt_solve_frame", "tt_solve_batch", "tt_project", "tt_status_string", "tt_last_error", "tt_pupil_mask",
 )
 
@@ -128,6 +129,7 @@ def load(path: str = LIB_PATH):
     lib.tt_set_mode_removal.argtypes = [vp, C.c_int]
     lib.tt_matvec.argtypes = [vp, vp, vp]
     lib.tt_matvec_f64.argtypes = [vp, vp, vp]
+    lib.tt_matvec_noalloc.argtypes = [vp, vp, vp]
     lib.tt_solve_frame.argtypes = [vp, vp, vp, vp, vp, C.POINTER(_SolveOpts), C.POINTER(_SolveInfo)]
     lib.tt_project.argtypes = [vp, vp, vp]
     lib.tt_solve_batch.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
@@ -289,6 +291,14 @@ class Context:
         if y is None:
             y = torch.empty(n, dtype=torch.float32, device=x.device)
         _check(load().tt_matvec(self._h, _dptr(x, torch.float32, n), _dptr(y, torch.float32, n)))
+        return y
+
+    def matvec_noalloc(self, x, y):
+        """tt_matvec_noalloc: the product of matvec without any device allocation
+        (work buffers in the library's fixed per-device array); y is required."""
+        import torch
+        n = self.info["n_slopes"]
+        _check(load().tt_matvec_noalloc(self._h, _dptr(x, torch.float32, n), _dptr(y, torch.float32, n)))
         return y
 
     def matvec_f64(self, x, y=None):

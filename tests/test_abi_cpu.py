@@ -47,6 +47,7 @@ def test_null_arguments_rejected(lib):
     assert lib.tt_generate_kernels(None, None, None, C.byref(out)) == tt.TT_INVALID_ARG
     assert "NULL" in lib.tt_last_error().decode()
     assert lib.tt_matvec(None, None, None) == tt.TT_INVALID_ARG
+    assert lib.tt_matvec_noalloc(None, None, None) == tt.TT_INVALID_ARG
     assert lib.tt_solve_frame(None, None, None, None, None, None, None) == tt.TT_INVALID_ARG
     assert lib.tt_project(None, None, None) == tt.TT_INVALID_ARG
     assert lib.tt_kernels_copy(None, None, 0) == tt.TT_INVALID_ARG
