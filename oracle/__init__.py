@@ -28,6 +28,11 @@ the paper it follows.  Modules:
               bilinear interpolation (§2.D "Phase-Slope Covariance Matrix",
               §2.E LGS equation), plus the exact dense form for comparison
   opcount     operation-count and compression formulas (§2.D, §2.E)
+  learned     learned preconditioner P = K^T K, K a masked four-layer linear
+              CNN over the slope maps (triangular, so log|det K| is exact),
+              its Kaporin-number training objective on (residual, exact
+              solution) pairs, gradient and Adam step (§2.G leaves
+              preconditioning open); flexible PCG is solve.fpcg
 
 Parity status: every function is pinned by a CPU test (tests/test_oracle_*.py)
 against closed forms, library special functions, brute force or invariants;

@@ -15,6 +15,15 @@
       z = P r;  alpha = r.z / p.Ap;  x += alpha p;  r -= alpha Ap;
       z' = P r';  beta = r'.z' / r.z;  p = z' + beta p,
   with the same stopping rule on the unpreconditioned residual.
+* fpcg: flexible preconditioned CG for a preconditioner that need not be a
+  fixed symmetric operator (the learned one of `oracle.learned`, applied in
+  reduced precision), with the Polak-Ribiere form of beta (Golub & Ye, SIAM J.
+  Sci. Comput. 21 (1999); Notay, SIAM J. Sci. Comput. 22 (2000)):
+      u = P r;  alpha = r.u / p.Ap;  x += alpha p;  r' = r - alpha Ap;
+      u' = P r';  beta = r'.(u' - u) / r.u;  p = u' + beta p.
+  Plain CG is the fallback: when r'.u' is not positive (P not positive on r')
+  the iteration restarts from the current x with u = r from then on.  The
+  stopping rule is that of cg on the unpreconditioned residual.
 * minres: the minimum-residual method for symmetric matrices, the solver the
   paper uses for its Toeplitz system (§2.G; its experiments run it because CG
   stalls on the mode-removed, noiseless system).  Lanczos three-term
@@ -94,6 +103,44 @@ def pcg(apply_A, apply_P, s, tol=1e-6, maxiter=10000, x0=None, history=False):
         it += 1
         hist.append(float(np.linalg.norm(r)) / bnorm)
     return (x, it, hist) if history else (x, it)
+
+
+def fpcg(apply_A, apply_P, s, tol=1e-6, maxiter=10000, x0=None, history=False):
+    s = np.asarray(s, dtype=np.float64)
+    x = np.zeros_like(s) if x0 is None else np.array(x0, dtype=np.float64)
+    r = s - apply_A(x) if x0 is not None else s.copy()
+    bnorm = float(np.sqrt(s @ s))
+    hist = [float(np.linalg.norm(r)) / bnorm if bnorm > 0 else 0.0]
+    it = 0
+    fallback = False
+    if bnorm == 0.0:
+        return (x, 0, hist, fallback) if history else (x, 0)
+    u = apply_P(r)
+    ru = float(r @ u)
+    if not (ru > 0.0 and np.isfinite(ru)):
+        fallback = True
+        u = r.copy()
+        ru = float(r @ r)
+    p = u.copy()
+    while it < maxiter and np.linalg.norm(r) > tol * bnorm:
+        Ap = apply_A(p)
+        alpha = ru / float(p @ Ap)
+        x += alpha * p
+        r -= alpha * Ap
+        it += 1
+        hist.append(float(np.linalg.norm(r)) / bnorm)
+        u_new = r.copy() if fallback else apply_P(r)
+        ru_new = float(r @ u_new)
+        if not fallback and not (ru_new > 0.0 and np.isfinite(ru_new)):
+            fallback = True                      # restart as plain CG
+            u_new = r.copy()
+            ru_new = float(r @ r)
+            p = u_new.copy()
+        else:
+            beta = (ru_new - float(r @ u)) / ru
+            p = u_new + beta * p
+        u, ru = u_new, ru_new
+    return (x, it, hist, fallback) if history else (x, it)
 
 
 def minres(apply_A, s, tol=1e-6, maxiter=10000, x0=None, history=False):
