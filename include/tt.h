@@ -104,7 +104,7 @@ typedef enum {
 
 typedef enum {
     TT_PRECOND_NONE = 0,      /* plain CG (§2.G) */
-    TT_PRECOND_CIRCULANT = 1  /* CG preconditioned by the block-circulant inverse: the
+    TT_PRECOND_CIRCULANT = 1, /* CG preconditioned by the block-circulant inverse: the
                                  restriction to the valid subapertures of
                                  F^-1 (M_+(f) + sigma^2 I)^-1 F, with M(f) the per-frequency
                                  matrix of the embedded slope spectra of the product (§2.E),
@@ -116,6 +116,16 @@ typedef enum {
                                  block's grid rows must fit its threads:
                                  n * ceil(2 n_gs n / compute units) <= 512), or
                                  TT_SOLVER_BATCHED (FP32). */
+    TT_PRECOND_LEARNED = 2    /* flexible CG preconditioned by the learned network attached
+                                 with tt_set_learned: P = K^T K (see tt_learned_create),
+                                 beta in the Polak-Ribiere form r'.(u' - u) / r.u, u = P r,
+                                 restarted from P r at every FP64 residual replacement.
+                                 Plain CG is the fallback: a system whose r.P r is not
+                                 positive or finite, or whose recursive residual has not
+                                 reached a new minimum for 256 iterations, restarts from
+                                 its FP64 true residual as plain CG (tt_solve_info.fallback).
+                                 The FP64 true residual certifies the tolerance either way.
+                                 TT_SOLVER_BATCHED, TT_PREC_F32, no mode removal. */
 } tt_preconditioner;
 
 typedef enum {
@@ -179,6 +189,8 @@ typedef struct {
     double kernel_ms;             /* device time of the persistent solver launches, measured
                                      with events on the context stream (0 for TT_SOLVER_KERNELS) */
     int kernel_launches;          /* persistent solver launches (1 + replacements) */
+    int fallback;                 /* TT_PRECOND_LEARNED: iteration at which the solve fell back
+                                     to plain CG, or -1 */
 } tt_solve_info;
 
 /* Sizes of a configured system. */
@@ -194,6 +206,21 @@ typedef struct {
 
 typedef struct tt_ctx tt_ctx;
 typedef struct tt_kernels tt_kernels;
+typedef struct tt_learned tt_learned;
+
+/* Training of a learned preconditioner (tt_learned_train). */
+typedef struct {
+    int n_pairs;                  /* (residual, exact solution) pairs drawn, e.g. 20000 */
+    int steps;                    /* optimiser steps */
+    int batch;                    /* pairs per step */
+    double lr;                    /* Adam step size; cosine decay to lr / 100 over the steps */
+} tt_train_opts;
+
+typedef struct {
+    double objective_first;       /* training objective J at the first step */
+    double objective_last;        /* mean J over the last tenth of the steps */
+    double ms;                    /* device time of pair generation and training */
+} tt_train_info;
 
 /* Create a context on HIP device `device`, enqueuing on `stream` (a hipStream_t,
  * NULL = the null stream).  Owns its device memory until tt_destroy. */
@@ -332,6 +359,55 @@ tt_status tt_solve_batch(tt_ctx* const* systems, int count, const float* const* 
  * (§2.E LGS phase-slope equation with a common n').  d_zeta: n_slopes doubles
  * (rounded to FP32 for the products), d_phi: n_vphi floats.  Requires a target. */
 tt_status tt_project(tt_ctx* ctx, const double* d_zeta, float* d_phi);
+
+/* Learned preconditioner.  The paper leaves preconditioning of its Toeplitz
+ * system open (§2.G; the conclusion names it the remaining challenge); this is
+ * a factorised approximate inverse P = K^T K learned from the method's own
+ * (residual, exact solution) pairs.  K is a four-layer linear convolutional
+ * network over the 2 n_gs slope maps of the n x n grid (W_s^T r, zeros at
+ * invalid subapertures, §2.F): 3 x 3 kernels, channels 2 n_gs -> hidden ->
+ * hidden -> hidden -> 2 n_gs, zero padding, no bias, output restricted to the
+ * valid subapertures.  Weights are masked so that K is lower triangular in the
+ * order (pixel in row-major order, then channel): no tap on the next row or on
+ * the next pixel of the row; the centre tap from input channel i to output o
+ * only when deg(o) >= deg(i) (channel c of the slope maps has degree c, hidden
+ * channel h degree h mod 2 n_gs).  Then log|det K| = n_vs sum_c log|d_c|, d the
+ * diagonal of the product of the four centre taps, and training minimises
+ * Kaporin's condition number of P A through
+ *   J = N log(t / N) - 2 n_vs sum_c log|d_c|,   t = mean_b (K r_b).(K e_b),
+ * N = n_slopes, over pairs r_b = A e_b with e_b ~ N(0, I) (E[t] = tr(K A K^T)).
+ * Weights are FP32 masters (Adam); the network computes with them rounded to
+ * bfloat16, FP32 accumulation on the matrix cores.
+ *
+ * Weight layout (count from tt_learned_weight_count): the four layers in
+ * order, each [out][in][ky][kx] (ky: row offset - 1, kx: column offset - 1 of
+ * the input read by output (y, x)), row-major. */
+tt_status tt_learned_create(tt_learned** out, int device, int n_gs, int hidden, unsigned long long seed);
+tt_status tt_learned_destroy(tt_learned* net);
+tt_status tt_learned_weight_count(const tt_learned* net, size_t* count);
+/* FP32 master weights (masked entries are zero); set_weights masks what it is
+ * given and resets the optimiser state.  Synchronous. */
+tt_status tt_learned_get_weights(const tt_learned* net, float* host, size_t count);
+tt_status tt_learned_set_weights(tt_learned* net, const float* host, size_t count);
+/* d_z = K^T K d_r on the geometry of ctx (n_slopes floats each), on ctx's stream. */
+tt_status tt_learned_apply(tt_learned* net, tt_ctx* ctx, const float* d_r, float* d_z);
+/* One optimiser step on caller pairs: d_R, d_E device arrays of batch rows of
+ * n_slopes floats (r_b = A e_b).  objective, trace (may be NULL) receive J and t
+ * at the weights used.  Synchronous.  TT_BREAKDOWN (step skipped) if t <= 0 or
+ * a diagonal entry of K is zero. */
+tt_status tt_learned_train_step(tt_learned* net, tt_ctx* ctx, const float* d_R, const float* d_E, int batch,
+                                double lr, double* objective, double* trace);
+/* Training on opts->n_pairs pairs drawn by the library (e ~ N(0, I) from a
+ * Philox4x32-10 stream under the network's seed, r = A_j e by the FP32 product
+ * of systems[j], j = pair mod count; the systems must share the grid and the
+ * valid subapertures, and may differ in atmosphere and noise), then opts->steps
+ * Adam steps on batches drawn by a counter-based hash.  Synchronous; the pairs
+ * (2 n_pairs n_slopes floats of device memory) are freed on return. */
+tt_status tt_learned_train(tt_learned* net, tt_ctx* const* systems, int count, const tt_train_opts* opts,
+                           tt_train_info* info);
+/* Attach (net != NULL) or detach the network used by TT_PRECOND_LEARNED solves
+ * of ctx.  The network is not owned by the context and must outlive its use. */
+tt_status tt_set_learned(tt_ctx* ctx, tt_learned* net);
 
 const char* tt_status_string(tt_status s);
 /* Message of the last failing call on the calling thread ("" if none). */

@@ -197,9 +197,20 @@ tt_status parse_opts(const tt_ctx* c, const tt_solve_opts* opts, tt_solve_opts& 
     TT_REQUIRE(o.solver == TT_SOLVER_PERSISTENT || (o.precision != TT_PREC_F16 && o.precision != TT_PREC_BF16),
                "TT_PREC_F16 / TT_PREC_BF16 need TT_SOLVER_PERSISTENT");
     TT_REQUIRE(std::isfinite(o.refine_drop) && o.refine_drop >= 0 && o.refine_drop < 1, "refine_drop in [0, 1)");
-    TT_REQUIRE(o.preconditioner == TT_PRECOND_NONE || o.preconditioner == TT_PRECOND_CIRCULANT,
+    TT_REQUIRE(o.preconditioner == TT_PRECOND_NONE || o.preconditioner == TT_PRECOND_CIRCULANT ||
+                   o.preconditioner == TT_PRECOND_LEARNED,
                "unknown preconditioner");
-    TT_REQUIRE(o.preconditioner == TT_PRECOND_NONE || o.solver == TT_SOLVER_BATCHED ||
+    if (o.preconditioner == TT_PRECOND_LEARNED) {
+        TT_REQUIRE(o.solver == TT_SOLVER_BATCHED && o.precision == TT_PREC_F32 && o.method == TT_METHOD_CG,
+                   "TT_PRECOND_LEARNED needs TT_SOLVER_BATCHED, TT_PREC_F32 and TT_METHOD_CG");
+        if (!c->learned) {
+            tt_set_error("TT_PRECOND_LEARNED: no network attached (tt_set_learned)");
+            return TT_NOT_READY;
+        }
+        TT_REQUIRE(learned_channels(c->learned) == c->C,
+                   "the attached network's channel count differs from the system's 2 n_gs");
+    }
+    TT_REQUIRE(o.preconditioner != TT_PRECOND_CIRCULANT || o.solver == TT_SOLVER_BATCHED ||
                    (o.solver == TT_SOLVER_PERSISTENT && (o.precision == TT_PREC_F32 || o.precision == TT_PREC_F64)),
                "TT_PRECOND_CIRCULANT needs TT_SOLVER_PERSISTENT with TT_PREC_F32 or TT_PREC_F64, or "
                "TT_SOLVER_BATCHED");
@@ -250,6 +261,7 @@ tt_status solve_impl(tt_ctx* c, const float* s, const double* x0, double* zeta, 
     TT_CHECK(parse_opts(c, opts, o));
     TT_CHECK(use_device(c->device));
     tt_solve_info inf{};
+    inf.fallback = -1;
     if (o.solver == TT_SOLVER_PERSISTENT)
         TT_CHECK(solve_persistent(*c, s, x0, zeta, o, inf));
     else if (o.solver == TT_SOLVER_KERNELS)

@@ -12,7 +12,12 @@
 //   q = A p;  alpha = ru_j / (p . q);  x += alpha p;  r -= alpha q;  u = P r;
 //   ru_{j+1} = r . u;  beta = ru_{j+1} / ru_j;  p = u + beta p,
 // restarted from p = u = P r at every residual replacement; the stopping and
-// replacement tests use r . r as in plain CG.  FP64 dot products are summed in
+// replacement tests use r . r as in plain CG.
+// Preconditioned by the learned network (TT_PRECOND_LEARNED), flexible CG:
+// the same with beta = r_{j+1} . (u_{j+1} - u_j) / ru_j (Polak-Ribiere), u_j
+// kept between iterations; a system whose r . u is not positive or finite, or
+// whose recursive residual has made no new minimum for 256 iterations, falls
+// back to plain CG (u = r) from its FP64 true residual.  FP64 dot products are summed in
 // a fixed order.  The iteration index of a system within a chunk is its count
 // at the chunk's start plus the step, and the scalars of iteration j + 1 go to
 // the other parity slot, so no kernel reads a value another block of the same
@@ -34,13 +39,15 @@ struct BVec {
     float* p;
     const float* q;
     const float* u;  // P r (preconditioned)
+    float* uo;       // the previous u (flexible CG)
     double* partA;   // VB partials of p . q
     double* partB;   // VB partials of r . r
     double* partC;   // VB partials of r . u
+    double* partD;   // VB partials of r . uo (flexible CG)
     CgScalars* S;
     long n;
     int it0;         // iterations done at the start of the chunk
-    int pad;
+    int flex;        // flexible CG (Polak-Ribiere beta)
 };
 
 __device__ double vblock_sum(double v, double* red) {
@@ -80,11 +87,17 @@ __global__ __launch_bounds__(VT) void k_bdot_ru(const BVec* __restrict__ vs, int
     const BVec d = vs[blockIdx.y];
     const int st = d.S->state;
     if (starting ? (st == ST_BREAK || st == ST_CAP) : st != ST_RUN) return;
-    double v = 0.0;
-    for (long i = (long)blockIdx.x * VT + threadIdx.x; i < d.n; i += (long)VB * VT)
+    double v = 0.0, w = 0.0;
+    for (long i = (long)blockIdx.x * VT + threadIdx.x; i < d.n; i += (long)VB * VT) {
         v += (double)d.r[i] * (double)d.u[i];
+        if (d.flex && !starting) w += (double)d.r[i] * (double)d.uo[i];
+    }
     const double s = vblock_sum(v, red);
     if (threadIdx.x == 0) d.partC[blockIdx.x] = s;
+    if (d.flex && !starting) {
+        const double t = vblock_sum(w, red);
+        if (threadIdx.x == 0) d.partD[blockIdx.x] = t;
+    }
 }
 
 // (re)start of preconditioned CG at iteration it0: p = u, ru = r . u, and the
@@ -99,7 +112,10 @@ __global__ __launch_bounds__(VT) void k_bpc_start(const BVec* __restrict__ vs) {
         if (blockIdx.x == 0 && threadIdx.x == 0) S->state = ST_BREAK;
         return;
     }
-    for (long i = (long)blockIdx.x * VT + threadIdx.x; i < d.n; i += (long)VB * VT) d.p[i] = d.u[i];
+    for (long i = (long)blockIdx.x * VT + threadIdx.x; i < d.n; i += (long)VB * VT) {
+        d.p[i] = d.u[i];
+        if (d.flex) d.uo[i] = d.u[i];
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         S->ru[d.it0 & 1] = ru;
         S->rr[d.it0 & 1] = S->rr_true;
@@ -185,14 +201,31 @@ __global__ __launch_bounds__(VT) void k_bupdate_p_pc(const BVec* __restrict__ vs
         }
         return;
     }
-    const float beta = (float)(run / S->ru[it & 1]);
-    for (long i = (long)blockIdx.x * VT + threadIdx.x; i < d.n; i += (long)VB * VT) d.p[i] = d.u[i] + beta * d.p[i];
+    const double rdo = d.flex ? vsum_partials(d.partD, red) : 0.0;
+    const float beta = (float)((run - rdo) / S->ru[it & 1]);
+    for (long i = (long)blockIdx.x * VT + threadIdx.x; i < d.n; i += (long)VB * VT) {
+        d.p[i] = d.u[i] + beta * d.p[i];
+        if (d.flex) d.uo[i] = d.u[i];
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         S->rr[(it + 1) & 1] = rn;
         S->ru[(it + 1) & 1] = run;
         S->iter = it + 1;
     }
 }
+
+// u = r (plain CG in the preconditioned recurrences), for the systems that fell back
+__global__ __launch_bounds__(VT) void k_bcopy_ru(const BVec* __restrict__ vs, const int* __restrict__ which,
+                                                int starting) {
+    const BVec d = vs[which[blockIdx.y]];
+    const int st = d.S->state;
+    if (starting ? (st == ST_BREAK || st == ST_CAP) : st != ST_RUN) return;
+    float* u = const_cast<float*>(d.u);
+    for (long i = (long)blockIdx.x * VT + threadIdx.x; i < d.n; i += (long)VB * VT) u[i] = d.r[i];
+}
+
+// a system that falls back to plain CG resumes iterating
+__global__ void k_resume(CgScalars* S) { S->state = ST_RUN; }
 
 // the solver scalars of every system, gathered for one copy to the host
 __global__ void k_bgather(const BVec* __restrict__ vs, int count, CgScalars* __restrict__ out) {
@@ -201,43 +234,102 @@ __global__ void k_bgather(const BVec* __restrict__ vs, int count, CgScalars* __r
 }
 
 
+// u = P r for the systems act[0..na) (their BVec at dvec[0..na), on stream st):
+// the block-circulant inverse batched (mode TT_PRECOND_CIRCULANT), or the
+// learned network (TT_PRECOND_LEARNED) batched over runs of systems sharing the
+// network and the valid subapertures, with u = r for the systems in fb (those
+// fallen back to plain CG, indices into act, uploaded at dfb).
+struct PcPlan {
+    int mode = 0;
+    std::vector<std::pair<int, int>> runs;   // learned: [begin, end) of act sharing a network and geometry
+    std::vector<int> fb;                     // fallen back: indices into act
+    DevBuf<int> dfb;
+};
+
+tt_status plan_precond(PcPlan& plan, tt_ctx* const* act, int na, const std::vector<int>& fallback_of_act,
+                       hipStream_t st) {
+    plan.runs.clear();
+    plan.fb.clear();
+    if (plan.mode != TT_PRECOND_LEARNED) return TT_OK;
+    int a = 0;
+    while (a < na) {
+        if (fallback_of_act[a]) {
+            plan.fb.push_back(a++);
+            continue;
+        }
+        int b = a + 1;
+        while (b < na && !fallback_of_act[b] && act[b]->learned == act[a]->learned && act[b]->n == act[a]->n &&
+               act[b]->valid == act[a]->valid)
+            ++b;
+        plan.runs.push_back({a, b});
+        a = b;
+    }
+    if (!plan.fb.empty()) {
+        if (plan.dfb.n < plan.fb.size()) TT_CHECK(plan.dfb.alloc(std::max<size_t>(plan.fb.size(), 64)));
+        TT_HIP(hipMemcpyAsync(plan.dfb.p, plan.fb.data(), sizeof(int) * plan.fb.size(), hipMemcpyHostToDevice, st));
+    }
+    return TT_OK;
+}
+
+tt_status apply_precond(const PcPlan& plan, tt_ctx* const* act, int na, const float* const* pr, float* const* pu,
+                        const BVec* dvec, int starting, hipStream_t st) {
+    if (plan.mode == TT_PRECOND_CIRCULANT) return batch_apply(act, na, pr, pu, 1, nullptr);
+    for (const auto& run : plan.runs)
+        TT_CHECK(learned_apply_batch(*act[run.first]->learned, *act[run.first], pr + run.first, pu + run.first,
+                                     run.second - run.first, st));
+    if (!plan.fb.empty()) {
+        hipLaunchKernelGGL(k_bcopy_ru, dim3(VB, (unsigned)plan.fb.size()), dim3(VT), 0, st, dvec, plan.dfb.p,
+                           starting);
+        TT_HIP(hipGetLastError());
+    }
+    return TT_OK;
+}
+
 // Preconditioned start of the systems in vs (count of them, on stream st):
 // u = P r, ru = r . u, p = u.
-tt_status pc_start(tt_ctx* const* act, int na, const std::vector<const float*>& pr, const std::vector<float*>& pu,
-                   const BVec* dvec, hipStream_t st) {
-    TT_CHECK(batch_apply(act, na, pr.data(), pu.data(), 1, nullptr));
+tt_status pc_start(const PcPlan& plan, tt_ctx* const* act, int na, const std::vector<const float*>& pr,
+                   const std::vector<float*>& pu, const BVec* dvec, hipStream_t st) {
+    TT_CHECK(apply_precond(plan, act, na, pr.data(), pu.data(), dvec, 1, st));
     hipLaunchKernelGGL(k_bdot_ru, dim3(VB, na), dim3(VT), 0, st, dvec, 1);
     hipLaunchKernelGGL(k_bpc_start, dim3(VB, na), dim3(VT), 0, st, dvec);
     TT_HIP(hipGetLastError());
     return TT_OK;
 }
 
-BVec bvec_of(tt_ctx& c, int it0) {
-    return BVec{c.x32.p, c.r32.p, c.p32.p, c.q32.p, c.bu32.p, c.part.p, c.part.p + VB, c.part.p + 2 * VB,
-                cg_scalars(c), (long)c.n_slopes, it0, 0};
+BVec bvec_of(tt_ctx& c, int it0, bool flex) {
+    return BVec{c.x32.p,      c.r32.p,          c.p32.p,          c.q32.p,          c.bu32.p,      c.bu_old32.p,
+                c.part.p,     c.part.p + VB,    c.part.p + 2 * VB, c.part.p + 3 * VB, cg_scalars(c), (long)c.n_slopes,
+                it0,          flex ? 1 : 0};
 }
 
 }  // namespace
 
-// Lockstep FP32 CG (plain, or preconditioned by the block-circulant inverse)
-// over systems[0..count) (contexts already validated: ready, distinct, one
-// device, no mode removal); infos[i] and zeta[i] as tt_solve_frame.  Returns
-// TT_OK, or the first runtime error; per-system outcomes are in infos[i].status.
+// Lockstep FP32 CG (plain, preconditioned by the block-circulant inverse, or
+// flexible with the learned preconditioner) over systems[0..count) (contexts
+// already validated: ready, distinct, one device, no mode removal); infos[i]
+// and zeta[i] as tt_solve_frame.  Returns TT_OK, or the first runtime error;
+// per-system outcomes are in infos[i].status.
 tt_status solve_batched(tt_ctx* const* systems, int count, const float* const* d_s, const double* const* d_x0,
                         double* const* d_zeta, const tt_solve_opts& o, tt_solve_info* infos) {
     if (count == 0) return TT_OK;
-    const bool pc = o.preconditioner == TT_PRECOND_CIRCULANT;
+    const int mode = o.preconditioner;
+    const bool pc = mode != TT_PRECOND_NONE;
+    const bool flex = mode == TT_PRECOND_LEARNED;
+    constexpr int STALL = 256;   // learned: iterations without a new minimum of r.r before the fallback
     std::vector<CgScalars> h(count);
     std::vector<int> have_true(count, 0), done(count, 0), code(count, TT_OK), refinements(count, 0);
+    std::vector<int> fallback(count, 0), fb_iter(count, -1), best_it(count, 0);
+    std::vector<double> best_rr(count, 0.0);
     for (int i = 0; i < count; ++i) {
         tt_ctx& c = *systems[i];
-        if (pc) {
-            TT_CHECK(precond_build(c));
-            if (c.bu32.n < (size_t)c.n_slopes) TT_CHECK(c.bu32.alloc(c.n_slopes));
-        }
+        if (mode == TT_PRECOND_CIRCULANT) TT_CHECK(precond_build(c));
+        if (pc && c.bu32.n < (size_t)c.n_slopes) TT_CHECK(c.bu32.alloc(c.n_slopes));
+        if (flex && c.bu_old32.n < (size_t)c.n_slopes) TT_CHECK(c.bu_old32.alloc(c.n_slopes));
         TT_CHECK(cg_setup(c, d_s[i], d_x0 ? d_x0[i] : nullptr, o, true));
         TT_HIP(hipMemcpyAsync(&h[i], c.scal.p, sizeof(CgScalars), hipMemcpyDeviceToHost, c.stream));
         TT_HIP(hipStreamSynchronize(c.stream));
+        best_rr[i] = h[i].rr_true;
+        best_it[i] = h[i].iter;
         if (h[i].bnorm2 == 0.0 || h[i].rr_true <= h[i].tol2) {
             done[i] = 1;
             have_true[i] = 1;
@@ -250,9 +342,11 @@ tt_status solve_batched(tt_ctx* const* systems, int count, const float* const* d
     TT_CHECK(dS.alloc((size_t)count));
     std::vector<BVec> hv;
     std::vector<tt_ctx*> act;
-    std::vector<int> idx;
+    std::vector<int> idx, fb_act;
     std::vector<const float*> px, pr;
     std::vector<float*> qy, pu;
+    PcPlan plan, plan1;
+    plan.mode = plan1.mode = mode;
     auto gather_active = [&]() {
         for (int i = 0; i < count; ++i)   // iteration cap reached (max_iter 0 included)
             if (!done[i] && h[i].iter >= o.max_iter) {
@@ -266,17 +360,35 @@ tt_status solve_batched(tt_ctx* const* systems, int count, const float* const* d
         qy.clear();
         pr.clear();
         pu.clear();
+        fb_act.clear();
         for (int i = 0; i < count; ++i) {
             if (done[i]) continue;
             tt_ctx& c = *systems[i];
             act.push_back(&c);
             idx.push_back(i);
-            hv.push_back(bvec_of(c, h[i].iter));
+            hv.push_back(bvec_of(c, h[i].iter, flex));
             px.push_back(c.p32.p);
             qy.push_back(c.q32.p);
             pr.push_back(c.r32.p);
             pu.push_back(c.bu32.p);
+            fb_act.push_back(fallback[i]);
         }
+    };
+    // restart system i from its FP64 true residual: r = r64, p = u = P r (u = r
+    // after a fallback); refreshes h[i]
+    auto restart = [&](int i, int it) -> tt_status {
+        tt_ctx& c = *systems[i];
+        TT_CHECK(cg_copy_r64_to_r32(c));
+        tt_ctx* one[1] = {&c};
+        const BVec b1 = bvec_of(c, it, flex);
+        TT_HIP(hipMemcpyAsync(d1.p, &b1, sizeof(BVec), hipMemcpyHostToDevice, c.stream));
+        std::vector<int> f1(1, fallback[i]);
+        if (fallback[i]) hipLaunchKernelGGL(k_resume, dim3(1), dim3(1), 0, c.stream, cg_scalars(c));
+        TT_CHECK(plan_precond(plan1, one, 1, f1, c.stream));
+        TT_CHECK(pc_start(plan1, one, 1, {c.r32.p}, {c.bu32.p}, d1.p, c.stream));
+        TT_HIP(hipMemcpyAsync(&h[i], c.scal.p, sizeof(CgScalars), hipMemcpyDeviceToHost, c.stream));
+        TT_HIP(hipStreamSynchronize(c.stream));
+        return TT_OK;
     };
     // the batched launches go to the stream of the first system still iterating
     // (batch_apply uses it too)
@@ -286,8 +398,25 @@ tt_status solve_batched(tt_ctx* const* systems, int count, const float* const* d
         if (na > 0) {
             const hipStream_t st = act[0]->stream;
             TT_HIP(hipMemcpyAsync(dvec.p, hv.data(), sizeof(BVec) * na, hipMemcpyHostToDevice, st));
-            TT_CHECK(pc_start(act.data(), na, pr, pu, dvec.p, st));
+            TT_CHECK(plan_precond(plan, act.data(), na, fb_act, st));
+            TT_CHECK(pc_start(plan, act.data(), na, pr, pu, dvec.p, st));
             TT_HIP(hipStreamSynchronize(st));
+            if (flex) {   // a network that is not positive on the right-hand side: plain CG from the start
+                std::vector<CgScalars> g(na);
+                hipLaunchKernelGGL(k_bgather, dim3(cdiv(na, 64)), dim3(64), 0, st, dvec.p, na, dS.p);
+                TT_HIP(hipMemcpyAsync(g.data(), dS.p, sizeof(CgScalars) * na, hipMemcpyDeviceToHost, st));
+                TT_HIP(hipStreamSynchronize(st));
+                for (int a = 0; a < na; ++a) {
+                    const int i = idx[a];
+                    h[i] = g[a];
+                    if (h[i].state == ST_BREAK) {
+                        fallback[i] = 1;
+                        fb_iter[i] = h[i].iter;
+                        TT_CHECK(cg_true_residual(*systems[i], d_s[i], true, &h[i]));
+                        TT_CHECK(restart(i, h[i].iter));
+                    }
+                }
+            }
         }
     }
     const int chunk = 16;
@@ -297,12 +426,13 @@ tt_status solve_batched(tt_ctx* const* systems, int count, const float* const* d
         if (na == 0) break;
         const hipStream_t st = act[0]->stream;
         TT_HIP(hipMemcpyAsync(dvec.p, hv.data(), sizeof(BVec) * na, hipMemcpyHostToDevice, st));
+        if (pc) TT_CHECK(plan_precond(plan, act.data(), na, fb_act, st));
         for (int k = 0; k < chunk; ++k) {
             TT_CHECK(batch_apply(act.data(), na, px.data(), qy.data(), 0, nullptr));
             hipLaunchKernelGGL(k_bdot, dim3(VB, na), dim3(VT), 0, st, dvec.p);
             if (pc) {
                 hipLaunchKernelGGL(k_bupdate_xr<true>, dim3(VB, na), dim3(VT), 0, st, dvec.p, k);
-                TT_CHECK(batch_apply(act.data(), na, pr.data(), pu.data(), 1, nullptr));
+                TT_CHECK(apply_precond(plan, act.data(), na, pr.data(), pu.data(), dvec.p, 0, st));
                 hipLaunchKernelGGL(k_bdot_ru, dim3(VB, na), dim3(VT), 0, st, dvec.p, 0);
                 hipLaunchKernelGGL(k_bupdate_p_pc, dim3(VB, na), dim3(VT), 0, st, dvec.p, k, o.max_iter);
             } else {
@@ -320,6 +450,33 @@ tt_status solve_batched(tt_ctx* const* systems, int count, const float* const* d
             tt_ctx& c = *systems[i];
             h[i] = g[a];
             const int it = h[i].iter;
+            // learned preconditioner: fall back to plain CG on a breakdown of the
+            // flexible recurrences or a stall of the recursive residual
+            if (flex && !fallback[i]) {
+                const double rr = h[i].rr[it & 1];
+                if (h[i].state == ST_RUN && rr < best_rr[i]) {
+                    best_rr[i] = rr;
+                    best_it[i] = it;
+                }
+                const bool stall = h[i].state == ST_RUN && it - best_it[i] >= STALL;
+                if (h[i].state == ST_BREAK || stall) {
+                    fallback[i] = 1;
+                    fb_iter[i] = it;
+                    TT_CHECK(cg_true_residual(c, d_s[i], true, &h[i]));
+                    refinements[i]++;
+                    if (h[i].rr_true <= h[i].tol2) {
+                        have_true[i] = 1;
+                        done[i] = 1;
+                        continue;
+                    }
+                    TT_CHECK(restart(i, it));
+                    if (h[i].state == ST_BREAK) {
+                        code[i] = TT_BREAKDOWN;
+                        done[i] = 1;
+                    }
+                    continue;
+                }
+            }
             if (h[i].state == ST_BREAK) {
                 code[i] = TT_BREAKDOWN;
                 done[i] = 1;
@@ -344,18 +501,26 @@ tt_status solve_batched(tt_ctx* const* systems, int count, const float* const* d
                     done[i] = 1;
                 } else {
                     if (pc) {   // restart from the true residual: r = r64, p = u = P r
-                        TT_CHECK(cg_copy_r64_to_r32(c));
-                        tt_ctx* one[1] = {&c};
-                        const BVec b1 = bvec_of(c, it);
-                        TT_HIP(hipMemcpyAsync(d1.p, &b1, sizeof(BVec), hipMemcpyHostToDevice, c.stream));
-                        TT_CHECK(pc_start(one, 1, {c.r32.p}, {c.bu32.p}, d1.p, c.stream));
+                        TT_CHECK(restart(i, it));
+                        if (flex) {   // the replacement is a new minimum of the residual
+                            best_rr[i] = h[i].rr_true;
+                            best_it[i] = it;
+                        }
+                    } else {
+                        // restarted: its scalars on the device are current again
+                        TT_HIP(hipMemcpyAsync(&h[i], c.scal.p, sizeof(CgScalars), hipMemcpyDeviceToHost, c.stream));
+                        TT_HIP(hipStreamSynchronize(c.stream));
                     }
-                    // restarted: its scalars on the device are current again
-                    TT_HIP(hipMemcpyAsync(&h[i], c.scal.p, sizeof(CgScalars), hipMemcpyDeviceToHost, c.stream));
-                    TT_HIP(hipStreamSynchronize(c.stream));
                     if (h[i].state == ST_BREAK) {
-                        code[i] = TT_BREAKDOWN;
-                        done[i] = 1;
+                        if (flex && !fallback[i]) {
+                            fallback[i] = 1;
+                            fb_iter[i] = it;
+                            TT_CHECK(restart(i, it));
+                        }
+                        if (h[i].state == ST_BREAK) {
+                            code[i] = TT_BREAKDOWN;
+                            done[i] = 1;
+                        }
                     }
                 }
             }
@@ -366,6 +531,7 @@ tt_status solve_batched(tt_ctx* const* systems, int count, const float* const* d
         tt_solve_info inf{};
         TT_CHECK(cg_finish(c, d_s[i], d_zeta[i], true, have_true[i] != 0, inf, code[i]));
         inf.refinements = refinements[i];
+        inf.fallback = fb_iter[i];
         if (infos) infos[i] = inf;
     }
     return TT_OK;

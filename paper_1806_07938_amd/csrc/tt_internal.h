@@ -176,6 +176,8 @@ struct tt_ctx {
     DevBuf<unsigned int> bar;           // grid barrier counters
     std::vector<double> host_noise;
 
+    tt_learned* learned = nullptr;      // attached learned preconditioner (not owned)
+    DevBuf<float> bu_old32;             // flexible PCG: the previous u = P r
     Projection proj;
     // copy of the geometry the system was built from (for the projection)
     double d = 0, h_lgs = 0;
@@ -240,6 +242,11 @@ tt_status modes_project_phase(tt_ctx& c, float* phi);
 // project.hip
 tt_status projection_setup(tt_ctx& c, const tt_target* t);
 tt_status projection_apply(tt_ctx& c, const double* zeta, float* phi);
+
+// learned.hip: the learned preconditioner P = K^T K
+tt_status learned_apply_batch(tt_learned& L, const tt_ctx& c, const float* const* d_r, float* const* d_z, int B,
+                              hipStream_t s);
+int learned_channels(const tt_learned* L);
 
 // noalloc.hip: device scratch of tt_matvec_noalloc (address looked up once per device)
 void noalloc_init(int device);

@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libtt.so")
 
 TT_OK, TT_INVALID_ARG, TT_HIP_ERROR, TT_OUT_OF_MEMORY, TT_NOT_CONVERGED, TT_BREAKDOWN, TT_NOT_READY = range(7)
 PREC_F32, PREC_F64, PREC_F16, PREC_BF16 = 0, 1, 2, 3
-PRECOND_NONE, PRECOND_CIRCULANT = 0, 1
+PRECOND_NONE, PRECOND_CIRCULANT, PRECOND_LEARNED = 0, 1, 2
 METHOD_CG, METHOD_MINRES = 0, 1
 SOLVER_PERSISTENT, SOLVER_KERNELS, SOLVER_BATCHED = 0, 1, 2
 MODEL_HUDGIN, MODEL_FRIED = 0, 1
@@ -33,7 +33,9 @@ MODEL_HUDGIN, MODEL_FRIED = 0, 1
 EXPORTED = (
     "tt_create", "tt_destroy", "tt_generate_kernels", "tt_kernels_destroy", "tt_kernels_copy",
     "tt_set_system", "tt_set_noise_xy", "tt_set_mode_removal", "tt_get_system_info", "tt_matvec", "tt_matvec_f64", "tt_matvec_batch",
-    "tt_matvec_noalloc",
+    "tt_matvec_noalloc", "tt_learned_create", "tt_learned_destroy", "tt_learned_weight_count",
+    "tt_learned_get_weights", "tt_learned_set_weights", "tt_learned_apply", "tt_learned_train_step",
+    "tt_learned_train", "tt_set_learned",
     "tt_solve_frame", "tt_solve_batch", "tt_project", "tt_status_string", "tt_last_error", "tt_pupil_mask",
 )
 
@@ -67,7 +69,7 @@ class _SolveOpts(C.Structure):
 class _SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int), ("refinements", C.c_int), ("status", C.c_int),
                 ("rel_residual", C.c_double), ("recursive_residual", C.c_double),
-                ("kernel_ms", C.c_double), ("kernel_launches", C.c_int)]
+                ("kernel_ms", C.c_double), ("kernel_launches", C.c_int), ("fallback", C.c_int)]
 
 
 class _SystemInfo(C.Structure):
@@ -75,6 +77,14 @@ class _SystemInfo(C.Structure):
                 ("n_vphi", C.c_int), ("n_prime", C.c_int), ("proj_pad_L", C.c_int), ("n_layer", C.c_int),
                 ("spectra_bytes_f32", C.c_size_t), ("spectra_bytes_f64", C.c_size_t),
                 ("proj_spectra_bytes", C.c_size_t)]
+
+
+class _TrainOpts(C.Structure):
+    _fields_ = [("n_pairs", C.c_int), ("steps", C.c_int), ("batch", C.c_int), ("lr", C.c_double)]
+
+
+class _TrainInfo(C.Structure):
+    _fields_ = [("objective_first", C.c_double), ("objective_last", C.c_double), ("ms", C.c_double)]
 
 
 _lib = None
@@ -130,6 +140,16 @@ def load(path: str = LIB_PATH):
     lib.tt_matvec.argtypes = [vp, vp, vp]
     lib.tt_matvec_f64.argtypes = [vp, vp, vp]
     lib.tt_matvec_noalloc.argtypes = [vp, vp, vp]
+    lib.tt_learned_create.argtypes = [C.POINTER(vp), C.c_int, C.c_int, C.c_int, C.c_ulonglong]
+    lib.tt_learned_destroy.argtypes = [vp]
+    lib.tt_learned_weight_count.argtypes = [vp, C.POINTER(C.c_size_t)]
+    lib.tt_learned_get_weights.argtypes = [vp, C.POINTER(C.c_float), C.c_size_t]
+    lib.tt_learned_set_weights.argtypes = [vp, C.POINTER(C.c_float), C.c_size_t]
+    lib.tt_learned_apply.argtypes = [vp, vp, vp, vp]
+    lib.tt_learned_train_step.argtypes = [vp, vp, vp, vp, C.c_int, C.c_double, C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double)]
+    lib.tt_learned_train.argtypes = [vp, C.POINTER(vp), C.c_int, C.POINTER(_TrainOpts), C.POINTER(_TrainInfo)]
+    lib.tt_set_learned.argtypes = [vp, vp]
     lib.tt_solve_frame.argtypes = [vp, vp, vp, vp, vp, C.POINTER(_SolveOpts), C.POINTER(_SolveInfo)]
     lib.tt_project.argtypes = [vp, vp, vp]
     lib.tt_solve_batch.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
@@ -179,6 +199,7 @@ class SolveInfo:
     recursive_residual: float
     kernel_ms: float = 0.0
     kernel_launches: int = 0
+    fallback: int = -1
 
 
 class Kernels:
@@ -206,8 +227,8 @@ class Kernels:
             load().tt_kernels_destroy(self._h)
             self._h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()
@@ -333,7 +354,12 @@ class Context:
                                    pphi, C.byref(opts), C.byref(inf))
         _check(st, allow=allow)
         return zeta, phi, SolveInfo(inf.iterations, inf.refinements, inf.status, inf.rel_residual,
-                                    inf.recursive_residual, inf.kernel_ms, inf.kernel_launches)
+                                    inf.recursive_residual, inf.kernel_ms, inf.kernel_launches, inf.fallback)
+
+    def set_learned(self, net):
+        """Attach (or with None detach) the network of TT_PRECOND_LEARNED solves."""
+        _check(load().tt_set_learned(self._h, net._h if net is not None else None))
+        self._learned = net
 
     def project(self, zeta, phi=None):
         import torch
@@ -348,8 +374,82 @@ class Context:
             load().tt_destroy(self._h)
             self._h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Learned:
+    """A learned preconditioner P = K^T K (tt_learned_*)."""
+
+    def __init__(self, n_gs: int, hidden: int = 32, seed: int = 1806, device: int = 0):
+        h = C.c_void_p()
+        _check(load().tt_learned_create(C.byref(h), int(device), int(n_gs), int(hidden), C.c_ulonglong(seed)))
+        self._h = h
+        self.n_gs, self.hidden = n_gs, hidden
+        cnt = C.c_size_t()
+        _check(load().tt_learned_weight_count(self._h, C.byref(cnt)))
+        self.count = cnt.value
+        _track(self)
+
+    def layer_shapes(self):
+        Cc, H = 2 * self.n_gs, self.hidden
+        return [(H, Cc, 3, 3), (H, H, 3, 3), (H, H, 3, 3), (Cc, H, 3, 3)]
+
+    def weights(self):
+        """FP32 master weights as four (out, in, 3, 3) arrays."""
+        out = np.empty(self.count, dtype=np.float32)
+        _check(load().tt_learned_get_weights(self._h, out.ctypes.data_as(C.POINTER(C.c_float)), out.size))
+        ws, o = [], 0
+        for shp in self.layer_shapes():
+            k = int(np.prod(shp))
+            ws.append(out[o:o + k].reshape(shp).copy())
+            o += k
+        return ws
+
+    def set_weights(self, ws):
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(w, dtype=np.float32).ravel() for w in ws]))
+        _check(load().tt_learned_set_weights(self._h, flat.ctypes.data_as(C.POINTER(C.c_float)), flat.size))
+
+    def apply(self, ctx, r, z=None):
+        import torch
+        n = ctx.info["n_slopes"]
+        if z is None:
+            z = torch.empty(n, dtype=torch.float32, device=r.device)
+        _check(load().tt_learned_apply(self._h, ctx._h, _dptr(r, torch.float32, n), _dptr(z, torch.float32, n)))
+        return z
+
+    def train_step(self, ctx, R, E, lr: float):
+        """One step on device pairs R, E (batch, n_slopes) float32; returns (J, t)
+        at the weights used."""
+        import torch
+        n = ctx.info["n_slopes"]
+        assert R.shape == E.shape and R.shape[1] == n
+        J, t = C.c_double(), C.c_double()
+        _check(load().tt_learned_train_step(self._h, ctx._h, _dptr(R, torch.float32), _dptr(E, torch.float32),
+                                            int(R.shape[0]), float(lr), C.byref(J), C.byref(t)))
+        return J.value, t.value
+
+    def train(self, contexts, n_pairs: int = 20000, steps: int = 3000, batch: int = 16, lr: float = 3e-3):
+        """tt_learned_train over contexts sharing a geometry; returns the info dict."""
+        m = len(contexts)
+        arr = (C.c_void_p * m)(*[c._h for c in contexts])
+        opts = _TrainOpts(int(n_pairs), int(steps), int(batch), float(lr))
+        inf = _TrainInfo()
+        _check(load().tt_learned_train(self._h, arr, m, C.byref(opts), C.byref(inf)))
+        return {"objective_first": inf.objective_first, "objective_last": inf.objective_last, "ms": inf.ms}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().tt_learned_destroy(self._h)
+            self._h = None
+
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()
@@ -429,5 +529,5 @@ def solve_batch(contexts, slopes, tol: float = 1e-6, max_iter: int = 20000, prec
     st = load().tt_solve_batch(hs, m, arr(*sp), None, arr(*zp), arr(*pp) if use_phi else None, C.byref(opts), infos)
     _check(st, allow=allow)
     out = [SolveInfo(i.iterations, i.refinements, i.status, i.rel_residual, i.recursive_residual, i.kernel_ms,
-                     i.kernel_launches) for i in list(infos)[:m]]
+                     i.kernel_launches, i.fallback) for i in list(infos)[:m]]
     return zetas, (phis if use_phi else [None] * m), out, st

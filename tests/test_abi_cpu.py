@@ -48,6 +48,13 @@ def test_null_arguments_rejected(lib):
     assert "NULL" in lib.tt_last_error().decode()
     assert lib.tt_matvec(None, None, None) == tt.TT_INVALID_ARG
     assert lib.tt_matvec_noalloc(None, None, None) == tt.TT_INVALID_ARG
+    assert lib.tt_learned_create(None, 0, 6, 32, 0) == tt.TT_INVALID_ARG
+    assert lib.tt_learned_destroy(None) == tt.TT_OK
+    assert lib.tt_learned_apply(None, None, None, None) == tt.TT_INVALID_ARG
+    assert lib.tt_learned_train_step(None, None, None, None, 1, 1e-3, None, None) == tt.TT_INVALID_ARG
+    assert lib.tt_learned_train(None, None, 1, None, None) == tt.TT_INVALID_ARG
+    assert lib.tt_set_learned(None, None) == tt.TT_INVALID_ARG
+    assert lib.tt_learned_weight_count(None, None) == tt.TT_INVALID_ARG
     assert lib.tt_solve_frame(None, None, None, None, None, None, None) == tt.TT_INVALID_ARG
     assert lib.tt_project(None, None, None) == tt.TT_INVALID_ARG
     assert lib.tt_kernels_copy(None, None, 0) == tt.TT_INVALID_ARG
@@ -85,7 +92,8 @@ def test_struct_layouts_match_header():
     text = open(HEADER).read()
     for cname, py in (("tt_geometry", tt._Geometry), ("tt_atmosphere", tt._Atmosphere),
                       ("tt_target", tt._Target), ("tt_solve_opts", tt._SolveOpts),
-                      ("tt_solve_info", tt._SolveInfo), ("tt_system_info", tt._SystemInfo)):
+                      ("tt_solve_info", tt._SolveInfo), ("tt_system_info", tt._SystemInfo),
+                      ("tt_train_opts", tt._TrainOpts), ("tt_train_info", tt._TrainInfo)):
         body = re.search(r"typedef struct \{((?:(?!typedef).)*?)\}\s*" + cname + ";", text, re.S).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         fields = []

@@ -1,0 +1,191 @@
+"""GPU parity of the learned preconditioner (P = K^T K, a masked four-layer
+CNN, trained on (residual, exact solution) pairs) and of flexible CG with it,
+against the oracle (oracle/learned.py, oracle/solve.fpcg).
+
+Bounds.  The network computes with bfloat16 weights (exact: the oracle gets the
+same rounded weights) and activations carried as two bfloat16 terms (relative
+representation error <= 2^-16 per element and layer), FP32 accumulation; over
+the eight convolutions of K^T K the relative max-abs error of P r is bounded
+here by 2e-4.  The training step is compared through J and t (relative 1e-4)
+and the signs of the first Adam update of every weight whose gradient is not
+negligible.  Solves are certified by the oracle's residual and compared with
+the Cholesky solution at the FP32 bar (1e-5)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_helpers import make_system, rel_maxabs, say, torch_dev
+from oracle import learned as Lr
+
+pytestmark = pytest.mark.gpu
+
+
+def _seeded_weights(net, seed, identity=1.0):
+    rng = np.random.default_rng(seed)
+    C = 2 * net.n_gs
+    ws = []
+    for (co, ci, _, _), m in zip(net.layer_shapes(), Lr.weight_masks(C, net.hidden)):
+        w = rng.standard_normal((co, ci, 3, 3)) / np.sqrt(9 * ci)
+        w[:, :, 1, 1] += identity * (np.arange(co)[:, None] % C == np.arange(ci)[None, :] % C)
+        ws.append((w * m).astype(np.float32))
+    return ws
+
+
+@pytest.mark.parametrize("wl_name", ["lgs3_10x10", "tiny5", "lgs6_74x74"])
+def test_learned_apply_matches_oracle(wl_name):
+    import torch
+    from paper_1806_07938_amd import Learned
+    wl = {"lgs3_10x10": W.lgs3_10x10, "tiny5": lambda: W.tiny(n=5, n_gs=2, seed=3),
+          "lgs6_74x74": W.lgs6_74x74}[wl_name]()
+    say(f"learned apply parity on {wl_name}")
+    ctx, k = make_system(wl, target=False)
+    net = Learned(wl.n_gs, 32, seed=7)
+    ws = _seeded_weights(net, 11)
+    net.set_weights(ws)
+    got_w = net.weights()
+    for a, b in zip(got_w, ws):
+        np.testing.assert_array_equal(a, b)
+    rng = np.random.default_rng(12)
+    for trial in range(2):
+        r = rng.standard_normal(wl.n_slopes).astype(np.float32)
+        z = net.apply(ctx, torch.tensor(r, device=torch_dev())).cpu().numpy()
+        ref = Lr.precondition([Lr.bf16_round(w) for w in ws], wl.valid, r.astype(np.float64))
+        err = rel_maxabs(z, ref)
+        say(f"  {wl_name} trial {trial}: rel max-abs error {err:.2e}")
+        assert err < 2e-4
+    net.close()
+    ctx.close()
+    k.close()
+
+
+def test_learned_train_step_matches_oracle():
+    import torch
+    from paper_1806_07938_amd import Learned
+    from oracle.covariance import system_matrix
+    wl = W.lgs3_10x10()
+    ctx, k = make_system(wl, target=False)
+    net = Learned(wl.n_gs, 32, seed=7)
+    ws = _seeded_weights(net, 21)
+    net.set_weights(ws)
+    A = system_matrix(wl)
+    rng = np.random.default_rng(22)
+    B = 8
+    E = rng.standard_normal((B, wl.n_slopes)).astype(np.float32)
+    R = (E.astype(np.float64) @ A).astype(np.float32)
+    dev = torch_dev()
+    lr = 1e-3
+    J, t = net.train_step(ctx, torch.tensor(R, device=dev), torch.tensor(E, device=dev), lr)
+    masks = Lr.weight_masks(2 * wl.n_gs, 32)
+    master = [w.astype(np.float64) for w in ws]
+    used = [Lr.bf16_round(w) * m for w, m in zip(master, masks)]
+    grads, Jo, to = Lr.objective_grad(used, wl.valid, R.astype(np.float64), E.astype(np.float64), masks)
+    say(f"train step: J {J:.6e} (oracle {Jo:.6e}), t {t:.6e} (oracle {to:.6e})")
+    assert abs(J - Jo) < 1e-4 * abs(Jo)
+    assert abs(t - to) < 1e-4 * abs(to)
+    new = net.weights()
+    gmax = max(np.abs(g).max() for g in grads)
+    checked = 0
+    for w0, w1, g, m in zip(ws, new, grads, masks):
+        step = (w1.astype(np.float64) - w0.astype(np.float64)) / lr
+        assert np.all(w1[m == 0] == 0)
+        sig = np.abs(g) > 1e-3 * gmax
+        # first Adam step: w1 - w0 = -lr g / (|g| + 1e-8)
+        assert np.all(np.sign(step[sig]) == -np.sign(g[sig]))
+        assert np.allclose(np.abs(step[sig]), 1.0, atol=2e-3)
+        checked += int(sig.sum())
+    assert checked > 1000
+    net.close()
+    ctx.close()
+    k.close()
+
+
+def _train_c1(steps=1500, n_pairs=20000, batch=16, lr=3e-3, systems=8):
+    from paper_1806_07938_amd import Learned
+    ctxs, ks = [], []
+    for i in range(systems):
+        c, kk = make_system(W.lgs3_10x10_family(i), target=False)
+        ctxs.append(c)
+        ks.append(kk)
+    net = Learned(3, 32, seed=1806)
+    info = net.train(ctxs, n_pairs=n_pairs, steps=steps, batch=batch, lr=lr)
+    for o in ctxs + ks:
+        o.close()
+    return net, info
+
+
+def test_learned_fpcg_c1_converges_and_beats_plain_cg():
+    import torch
+    from paper_1806_07938_amd import tt
+    from oracle.covariance import system_matrix
+    from oracle.solve import cholesky_solve
+    net, info = _train_c1()
+    say(f"C1 training: J {info['objective_first']:.1f} -> {info['objective_last']:.1f} in {info['ms']:.0f} ms")
+    assert info["objective_last"] < info["objective_first"]
+    wl = W.lgs3_10x10()
+    ctx, k = make_system(wl, target=True)
+    ctx.set_learned(net)
+    A = system_matrix(wl)
+    frames = W.turbulent_slopes(wl, frames=3)
+    its_l, its_p = [], []
+    for f in frames:
+        s = f.astype(np.float32)
+        st = torch.tensor(s, device=torch_dev())
+        z, phi, inf = ctx.solve(st, tol=1e-10, solver=tt.SOLVER_BATCHED, preconditioner=tt.PRECOND_LEARNED)
+        _, _, infp = ctx.solve(st, tol=1e-10, solver=tt.SOLVER_BATCHED)
+        zz = z.cpu().numpy()
+        res = np.linalg.norm(s - A @ zz) / np.linalg.norm(s)
+        zref = cholesky_solve(A, s.astype(np.float64))
+        say(f"  learned FPCG: {inf.iterations} iterations (plain CG {infp.iterations}), fallback {inf.fallback}, "
+            f"oracle residual {res:.2e}, zeta err {np.linalg.norm(zz - zref) / np.linalg.norm(zref):.2e}")
+        assert inf.status == tt.TT_OK and res <= 1.01e-10
+        assert np.linalg.norm(zz - zref) / np.linalg.norm(zref) < 1e-5
+        its_l.append(inf.iterations)
+        its_p.append(infp.iterations)
+    assert np.mean(its_l) < np.mean(its_p)
+    ctx.close()
+    k.close()
+    net.close()
+
+
+def test_learned_fallback_to_plain_cg():
+    import torch
+    from paper_1806_07938_amd import Learned, tt
+    from oracle.covariance import system_matrix
+    wl = W.lgs3_10x10()
+    ctx, k = make_system(wl, target=False)
+    net = Learned(wl.n_gs, 32, seed=3)
+    net.set_weights([np.zeros(s, dtype=np.float32) for s in net.layer_shapes()])   # P = 0: r.P r = 0
+    ctx.set_learned(net)
+    s = W.turbulent_slopes(wl)[0].astype(np.float32)
+    z, _, inf = ctx.solve(torch.tensor(s, device=torch_dev()), tol=1e-6, solver=tt.SOLVER_BATCHED,
+                          preconditioner=tt.PRECOND_LEARNED, project=False)
+    A = system_matrix(wl)
+    res = np.linalg.norm(s - A @ z.cpu().numpy()) / np.linalg.norm(s)
+    say(f"fallback at iteration {inf.fallback}, {inf.iterations} iterations, oracle residual {res:.2e}")
+    assert inf.fallback == 0 and inf.status == tt.TT_OK and res <= 1.01e-6
+    ctx.close()
+    k.close()
+    net.close()
+
+
+def test_learned_argument_errors():
+    import torch
+    from paper_1806_07938_amd import Learned, tt
+    wl = W.lgs3_10x10()
+    ctx, k = make_system(wl, target=False)
+    s = torch.tensor(W.turbulent_slopes(wl)[0].astype(np.float32), device=torch_dev())
+    with pytest.raises(tt.TTError) as e:       # no network attached
+        ctx.solve(s, solver=tt.SOLVER_BATCHED, preconditioner=tt.PRECOND_LEARNED, project=False)
+    assert e.value.status == tt.TT_NOT_READY
+    net = Learned(wl.n_gs, 32)
+    ctx.set_learned(net)
+    with pytest.raises(tt.TTError) as e:       # flexible CG runs in the batched solver only
+        ctx.solve(s, solver=tt.SOLVER_PERSISTENT, preconditioner=tt.PRECOND_LEARNED, project=False)
+    assert e.value.status == tt.TT_INVALID_ARG
+    other = Learned(2, 32)
+    with pytest.raises(tt.TTError):            # channel count of another geometry
+        ctx.set_learned(other)
+    with pytest.raises(tt.TTError):
+        Learned(3, 30)                          # hidden must be a multiple of 4
+    for o in (other, net, ctx, k):
+        o.close()

@@ -118,6 +118,22 @@ def lgs3_10x10(pad_L: int = 20) -> Workload:
         noise_var=0.1, pad_L=pad_L, valid=pupil_mask(n, D, obs))
 
 
+def lgs3_10x10_family(index: int, pad_L: int = 20) -> Workload:
+    """Systems of the 10x10 / 3 LGS geometry with a random atmosphere, for
+    training the learned preconditioner: the two layers of lgs3_10x10 with the
+    ground-layer weight uniform in [0.5, 0.9] and r0 uniform in [0.10, 0.25] m
+    (seed SEED + 500 + index).  Index -1 is lgs3_10x10 itself."""
+    if index < 0:
+        return lgs3_10x10(pad_L=pad_L)
+    u = np.random.default_rng(SEED + 500 + int(index)).random(2)
+    w0 = 0.5 + 0.4 * float(u[0])
+    wl = lgs3_10x10(pad_L=pad_L)
+    wl.name = f"lgs3_10x10_v{index}"
+    wl.w = np.array([w0, 1.0 - w0])
+    wl.r0 = 0.10 + 0.15 * float(u[1])
+    return wl
+
+
 def c2_profile(seed: int = SEED, n_layer: int = 35):
     """Synthetic 35-layer profile: geometric altitudes 30 m .. 26.5 km and
     weights proportional to exp(-h / 5 km) (0.75 + 0.5 u), u ~ U(0, 1), normalised."""
