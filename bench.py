@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--batch-solve-frames", type=int, default=0,
                     help="with --batch-only: also time the batched solves (plain and preconditioned CG) with this "
                          "many measured frames of lgs6_74x74 as right-hand sides")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner records")
+    ap.add_argument("--learned-steps", type=int, default=3000, help="optimiser steps of the learned preconditioner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 256 MiB device buffer 3 times (reference kernel for rocprofv3 "
                          "FETCH_SIZE / WRITE_SIZE scale factors)")
@@ -161,7 +163,7 @@ def batch_systems(args):
     return ctxs, keep, time.perf_counter() - t0
 
 
-def batch_solve(args, ctxs, frames, pc):
+def batch_solve(args, ctxs, frames, pc, precision=0):
     """TT_SOLVER_BATCHED over the same systems: one frame each (the measured
     frames of lgs6_74x74 reused in turn as right-hand sides), FP32 CG (plain,
     or preconditioned by the block-circulant inverse when pc) with the FP64
@@ -172,16 +174,18 @@ def batch_solve(args, ctxs, frames, pc):
     from paper_1806_07938_amd.tt import SOLVER_BATCHED, TT_NOT_CONVERGED
     S = [torch.tensor(frames[i % len(frames)], device="cuda:0") for i in range(len(ctxs))]
     t0 = time.perf_counter()
+    prec = precision if precision else 0
     if pc:   # preconditioner spectra, once per system (host FP64), before the untimed batch
         solve_batch(ctxs, S, tol=args.tol, max_iter=0, solver=SOLVER_BATCHED, preconditioner=pc,
-                    allow=(0, TT_NOT_CONVERGED))
+                    allow=(0, TT_NOT_CONVERGED), precision=prec)
     torch.cuda.synchronize()
     pc_setup_s = time.perf_counter() - t0
-    solve_batch(ctxs, S, tol=args.tol, solver=SOLVER_BATCHED, preconditioner=pc, allow=(0, TT_NOT_CONVERGED))
+    solve_batch(ctxs, S, tol=args.tol, solver=SOLVER_BATCHED, preconditioner=pc, allow=(0, TT_NOT_CONVERGED),
+                precision=prec)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, _, infos, st = solve_batch(ctxs, S, tol=args.tol, solver=SOLVER_BATCHED, preconditioner=pc,
-                                  allow=(0, TT_NOT_CONVERGED))
+                                  allow=(0, TT_NOT_CONVERGED), precision=prec)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3
     it = np.array([i.iterations for i in infos], dtype=np.float64)
@@ -189,6 +193,7 @@ def batch_solve(args, ctxs, frames, pc):
         "workload": (f"{len(ctxs)} distinct 74x74 / 6 LGS / 35-layer systems, L={args.batch_pad}, one frame each, "
                      f"solved together (TT_SOLVER_BATCHED: "
                      + ("CG preconditioned by the block-circulant inverse" if pc else "plain CG")
+                     + ({2: " (its spectra stored in FP16)", 3: " (its spectra stored in BF16)"}.get(prec, ""))
                      + f" in lockstep, FP32 + FP64 residual replacement) to rel. residual {args.tol:g}"),
         "systems": len(ctxs), "ms_per_batch": round(wall, 2), "ms_per_solve": round(wall / len(ctxs), 3),
         "preconditioner_setup_s": round(pc_setup_s, 1) if pc else None,
@@ -198,10 +203,11 @@ def batch_solve(args, ctxs, frames, pc):
     }
 
 
-def batch_matvec(args, ctxs, setup_s):
+def batch_matvec(args, ctxs, setup_s, precision=0):
     """tt_matvec_batch over the systems: spectra of all of them streamed once
     per call.  Roofline of the column kernel: algorithmic bytes = the packed
-    FP32 spectra of every system, over its HIP-event duration."""
+    spectra of every system (FP32, or FP16 / BF16 storage plus one FP32 factor
+    per frequency for precision 2 / 3), over its HIP-event duration."""
     import torch
     dev = torch.device("cuda:0")
     from paper_1806_07938_amd import matvec_batch
@@ -209,21 +215,26 @@ def batch_matvec(args, ctxs, setup_s):
     xs = [torch.tensor(rng.standard_normal(c.info["n_slopes"]).astype(np.float32), device=dev) for c in ctxs]
     ys = [torch.empty_like(x) for x in xs]
     for _ in range(3):
-        matvec_batch(ctxs, xs, ys)
+        matvec_batch(ctxs, xs, ys, precision=precision)
     torch.cuda.synchronize()
     phases = []
     t0 = time.perf_counter()
     for _ in range(args.batch_steps):
-        phases.append(matvec_batch(ctxs, xs, ys, timing=True)[1])
+        phases.append(matvec_batch(ctxs, xs, ys, timing=True, precision=precision)[1])
     wall_ms = (time.perf_counter() - t0) * 1e3 / args.batch_steps
     ph = np.array(phases).mean(axis=0)
     spectra = float(sum(c.info["spectra_bytes_f32"] for c in ctxs))
+    if precision:
+        spectra = float(sum(c.info["spectra_bytes_f32"] // 2 + 4 * c.info["pad_L"] * (c.info["pad_L"] // 2 + 1)
+                            for c in ctxs))
     slopes = float(sum(2 * 4 * c.info["n_slopes"] for c in ctxs))
     col_gbs = spectra / (ph[1] * 1e-3) / 1e9
-    traffic = batch_traffic_record() if (args.batch == 64 and args.batch_pad == 256) else None
+    traffic = batch_traffic_record() if (args.batch == 64 and args.batch_pad == 256 and not precision) else None
+    pname = {0: "FP32", 2: "FP16 (per-frequency power-of-two scale)", 3: "BF16"}[precision]
     return {
         "workload": (f"{args.batch} distinct 74x74 / 6 LGS / 35-layer systems (seeded layer weights, r0 in "
-                     f"[0.10, 0.25] m), L={args.batch_pad}, one FP32 product each per call"),
+                     f"[0.10, 0.25] m), L={args.batch_pad}, one product each per call, spectra stored in {pname}, "
+                     "FP32 arithmetic"),
         "systems": args.batch, "pad_L": args.batch_pad, "steps": args.batch_steps,
         "ms_per_call_wall": round(wall_ms, 4),
         "ms_per_call_gpu": round(float(ph.sum()), 4),
@@ -239,6 +250,57 @@ def batch_matvec(args, ctxs, setup_s):
                      "avg_launch_ms": round(float(ph[1]), 4)},
         "setup_s": round(setup_s, 1),
     }
+
+
+def learned_record(wl_of, family, n_systems, steps, frames, tol, label):
+    """Train the learned preconditioner on n_systems systems of one geometry
+    (family(i): random r0 and layer weights; 20000 (r = A e, e) pairs drawn by
+    the library), then solve `frames` of the nominal system wl_of() with
+    flexible CG preconditioned by it and with plain CG, both in the batched
+    solver (one frame per call), and the persistent plain CG."""
+    import torch
+    from paper_1806_07938_amd import Context, Learned, system_from
+    from paper_1806_07938_amd.tt import PRECOND_LEARNED, SOLVER_BATCHED, SOLVER_PERSISTENT, TT_NOT_CONVERGED
+    ctxs, keep = [], []
+    for i in range(n_systems):
+        c = Context(0)
+        keep.append(system_from(c, family(i), target=False))
+        ctxs.append(c)
+    wl = wl_of()
+    net = Learned(wl.n_gs, 32, seed=1806)
+    t0 = time.perf_counter()
+    tinfo = net.train(ctxs, n_pairs=20000, steps=steps, batch=16, lr=3e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    for c in ctxs + keep:
+        c.close()
+    ctx = Context(0)
+    kk = system_from(ctx, wl, target=True)
+    ctx.set_learned(net)
+    S = [torch.tensor(f, device="cuda:0") for f in frames]
+    res = {}
+    allow = (0, TT_NOT_CONVERGED)
+    for name, sv, pcm in (("learned_fpcg", SOLVER_BATCHED, PRECOND_LEARNED), ("batched_plain_cg", SOLVER_BATCHED, 0),
+                          ("persistent_plain_cg", SOLVER_PERSISTENT, 0)):
+        ctx.solve(S[0], tol=tol, solver=sv, preconditioner=pcm, allow=allow)
+        torch.cuda.synchronize()
+        ii = []
+        t0 = time.perf_counter()
+        for s in S:
+            ii.append(ctx.solve(s, tol=tol, solver=sv, preconditioner=pcm, allow=allow)[2])
+        torch.cuda.synchronize()
+        res[name] = {"ms_per_solve": round((time.perf_counter() - t0) * 1e3 / len(S), 3),
+                     "iterations_mean": round(float(np.mean([i.iterations for i in ii])), 1),
+                     "converged": all(i.status == 0 and i.rel_residual <= tol for i in ii),
+                     "fallback": [int(i.fallback) for i in ii] if pcm else None}
+    ctx.close()
+    kk.close()
+    net.close()
+    return {"workload": label, "training": {"systems": n_systems, "pairs": 20000, "steps": steps, "batch": 16,
+                                            "objective_first": round(tinfo["objective_first"], 1),
+                                            "objective_last": round(tinfo["objective_last"], 1),
+                                            "device_ms": round(tinfo["ms"], 1), "wall_s": round(train_s, 2)},
+            "frames": len(S), "tol": tol, **res}
 
 
 def persistent_roofline(infos, wl, info, prec, pc, pad):
@@ -296,7 +358,9 @@ def main():
         del cx, cy
     if args.batch_only:
         bctx, bkeep, bsetup = batch_systems(args)
-        res = {"batch_matvec": batch_matvec(args, bctx, bsetup)}
+        res = {"batch_matvec": batch_matvec(args, bctx, bsetup),
+               "batch_matvec_f16": batch_matvec(args, bctx, bsetup, precision=2),
+               "batch_matvec_bf16": batch_matvec(args, bctx, bsetup, precision=3)}
         if args.batch_solve_frames > 0:
             fr = W.turbulent_slopes(W.lgs6_74x74(), frames=args.batch_solve_frames).astype(np.float32)
             res["batch_solve"] = batch_solve(args, bctx, fr, 0)
@@ -400,11 +464,28 @@ def main():
             if sv == SOLVER_PERSISTENT and mth == CG:
                 side[name]["roofline"] = persistent_roofline(ii, wl, info, p, vpc, args.pad)
         out["variants"] = side
+    if not args.no_learned:
+        c2f = frames[:3]
+        out["learned_74x74"] = learned_record(
+            lambda: W.lgs6_74x74(pad_L=args.pad), lambda i: W.lgs6_74x74_family(i, pad_L=args.pad), 8,
+            args.learned_steps, c2f, args.tol,
+            "learned preconditioner (P = K^T K, 4-layer masked CNN, 32 channels) trained on 8 systems of the "
+            "74x74 / 6 LGS geometry with random r0 and layer weights, then flexible CG on 3 frames of the "
+            f"nominal system to rel. residual {args.tol:g}, against plain CG")
+        c1 = W.lgs3_10x10()
+        out["learned_10x10"] = learned_record(
+            W.lgs3_10x10, W.lgs3_10x10_family, 8, args.learned_steps,
+            W.turbulent_slopes(c1, frames=5).astype(np.float32), 1e-10,
+            "the same at 10x10 / 3 LGS (8 training systems with random r0 and layer weights), 5 frames of "
+            "lgs3_10x10 to rel. residual 1e-10")
     if args.batch > 0:
         bctx, bkeep, bsetup = batch_systems(args)
         out["batch_matvec"] = batch_matvec(args, bctx, bsetup)
+        out["batch_matvec_f16"] = batch_matvec(args, bctx, bsetup, precision=2)
+        out["batch_matvec_bf16"] = batch_matvec(args, bctx, bsetup, precision=3)
         out["batch_solve"] = batch_solve(args, bctx, frames, 0)
         out["batch_solve_pcg"] = batch_solve(args, bctx, frames, 1)
+        out["batch_solve_pcg_f16"] = batch_solve(args, bctx, frames, 1, precision=2)
     torch.cuda.synchronize()
     close_all()
     if not args.no_cpu:

@@ -67,14 +67,19 @@ typedef enum {
                                FP64 operator each time the FP32 residual has
                                dropped by refine_drop); certifies tol in FP64 */
     TT_PREC_F64 = 1,        /* FP64 throughout */
-    TT_PREC_F16 = 2,        /* as TT_PREC_F32, but the column DFT stages of the
-                               2RBT product (the dense contractions over the
-                               first FFT axis, forward and inverse) run on the
-                               matrix cores with FP16 operands (twiddles and data,
-                               the data scaled per column block by a power of two)
-                               and FP32 accumulation; the FP64 refinement still
-                               certifies tol.  TT_SOLVER_PERSISTENT only. */
-    TT_PREC_BF16 = 3        /* as TT_PREC_F16 with BF16 operands */
+    TT_PREC_F16 = 2,        /* reduced precision where the outer method stays exact:
+                               with TT_SOLVER_BATCHED and TT_PRECOND_CIRCULANT the
+                               preconditioner's spectra are stored in FP16 (each
+                               frequency scaled by a power of two; half the bytes)
+                               while the product stays FP32 and the FP64 true
+                               residual certifies tol.  With TT_SOLVER_PERSISTENT
+                               the column DFT stages of the product itself run on
+                               the matrix cores with FP16 operands (data scaled per
+                               column block) and FP32 accumulation: an inexact
+                               operator, which at the conditioning of these systems
+                               does not reach 1e-6 (TT_NOT_CONVERGED, with the FP64
+                               residual of the returned iterate). */
+    TT_PREC_BF16 = 3        /* as TT_PREC_F16 with BF16 (unscaled) */
 } tt_precision;
 
 typedef enum {
@@ -326,6 +331,17 @@ tt_status tt_matvec_noalloc(tt_ctx* ctx, const float* d_x, float* d_y);
  * of the three launches. */
 tt_status tt_matvec_batch(tt_ctx* const* systems, int count, const float* const* d_x,
                           float* const* d_y, float* phase_ms);
+
+/* tt_matvec_batch with the spectra read in `precision` storage: TT_PREC_F32
+ * (the same as tt_matvec_batch), TT_PREC_F16 (each frequency's values scaled by
+ * the power of two that brings its largest magnitude to [2^14, 2^15), rounded
+ * to FP16, restored exactly) or TT_PREC_BF16 (rounded, unscaled); products and
+ * transforms in FP32.  The FP16 / BF16 copies are made once per system from the
+ * FP32 spectra at the first call that needs them (device memory: half the FP32
+ * spectra).  Relative error of the product: the spectra rounding, at most 2^-11
+ * (FP16) or 2^-8 (BF16) of each frequency's largest value. */
+tt_status tt_matvec_batch_prec(tt_ctx* const* systems, int count, const float* const* d_x, float* const* d_y,
+                               int precision, float* phase_ms);
 
 /* Solve W_s (Sigma_ss + Sigma_eta) W_s^T zeta = s by CG (§2.G) and,
  * if d_phi != NULL, project phi = W_phi Sigma_{phi_beta s} zeta (§2.E).

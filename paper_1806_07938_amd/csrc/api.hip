@@ -125,6 +125,7 @@ tt_status set_system_impl(tt_ctx* c, const tt_kernels* k, const double* noise_va
     c->proj.on = false;
     c->tile_S = 0;
     c->pc_ready = false;
+    c->mh_kind[0] = c->mh_kind[1] = 0;
     c->has_nxy = false;
     c->modes = false;
     c->n = k->n;
@@ -194,8 +195,10 @@ tt_status parse_opts(const tt_ctx* c, const tt_solve_opts* opts, tt_solve_opts& 
                "unknown precision");
     TT_REQUIRE(o.solver == TT_SOLVER_PERSISTENT || o.solver == TT_SOLVER_KERNELS || o.solver == TT_SOLVER_BATCHED,
                "unknown solver");
-    TT_REQUIRE(o.solver == TT_SOLVER_PERSISTENT || (o.precision != TT_PREC_F16 && o.precision != TT_PREC_BF16),
-               "TT_PREC_F16 / TT_PREC_BF16 need TT_SOLVER_PERSISTENT");
+    TT_REQUIRE(o.solver == TT_SOLVER_PERSISTENT || (o.precision != TT_PREC_F16 && o.precision != TT_PREC_BF16) ||
+                   (o.solver == TT_SOLVER_BATCHED && o.preconditioner == TT_PRECOND_CIRCULANT),
+               "TT_PREC_F16 / TT_PREC_BF16 need TT_SOLVER_PERSISTENT, or TT_SOLVER_BATCHED with "
+               "TT_PRECOND_CIRCULANT");
     TT_REQUIRE(std::isfinite(o.refine_drop) && o.refine_drop >= 0 && o.refine_drop < 1, "refine_drop in [0, 1)");
     TT_REQUIRE(o.preconditioner == TT_PRECOND_NONE || o.preconditioner == TT_PRECOND_CIRCULANT ||
                    o.preconditioner == TT_PRECOND_LEARNED,
@@ -219,8 +222,7 @@ tt_status parse_opts(const tt_ctx* c, const tt_solve_opts* opts, tt_solve_opts& 
                    (o.solver == TT_SOLVER_PERSISTENT && o.preconditioner == TT_PRECOND_NONE &&
                     (o.precision == TT_PREC_F32 || o.precision == TT_PREC_F64)),
                "TT_METHOD_MINRES needs TT_SOLVER_PERSISTENT, TT_PREC_F32 or TT_PREC_F64 and no preconditioner");
-    TT_REQUIRE(o.solver != TT_SOLVER_BATCHED || o.precision == TT_PREC_F32,
-               "TT_SOLVER_BATCHED needs TT_PREC_F32");
+    TT_REQUIRE(o.solver != TT_SOLVER_BATCHED || o.precision != TT_PREC_F64, "TT_SOLVER_BATCHED computes in FP32");
     TT_REQUIRE(!c->modes || o.solver == TT_SOLVER_KERNELS, "mode removal needs TT_SOLVER_KERNELS");
     return TT_OK;
 }
@@ -270,6 +272,10 @@ tt_status solve_impl(tt_ctx* c, const float* s, const double* x0, double* zeta, 
         TT_CHECK(solve_batched(&c, 1, &s, x0 ? &x0 : nullptr, &zeta, o, &inf));
     TT_CHECK(finish_frame(c, zeta, phi));
     if (info) *info = inf;
+    if (inf.status != TT_OK)
+        tt_set_error(std::string("tt_solve_frame: ") + tt_status_string((tt_status)inf.status) + " after " +
+                     std::to_string(inf.iterations) + " iterations, FP64 relative residual " +
+                     std::to_string(inf.rel_residual));
     return (tt_status)inf.status;
 }
 
@@ -301,6 +307,10 @@ static tt_status batch_impl(tt_ctx* const* systems, int count, const float* cons
             if (infos) infos[i] = inf[i];
             if (inf[i].status == TT_BREAKDOWN) breakdown = true;
             else if (inf[i].status == TT_NOT_CONVERGED) notconv = true;
+            if (inf[i].status != TT_OK)
+                tt_set_error(std::string("tt_solve_batch: frame ") + std::to_string(i) + ": " +
+                             tt_status_string((tt_status)inf[i].status) + " after " +
+                             std::to_string(inf[i].iterations) + " iterations");
         }
         return breakdown ? TT_BREAKDOWN : notconv ? TT_NOT_CONVERGED : TT_OK;
     }
@@ -441,7 +451,12 @@ tt_status tt_matvec_f64(tt_ctx* c, const double* d_x, double* d_y) {
 
 tt_status tt_matvec_batch(tt_ctx* const* systems, int count, const float* const* d_x, float* const* d_y,
                           float* phase_ms) {
-    TT_GUARD(matvec_batch(systems, count, d_x, d_y, phase_ms));
+    TT_GUARD(matvec_batch(systems, count, d_x, d_y, phase_ms, TT_PREC_F32));
+}
+
+tt_status tt_matvec_batch_prec(tt_ctx* const* systems, int count, const float* const* d_x, float* const* d_y,
+                               int precision, float* phase_ms) {
+    TT_GUARD(matvec_batch(systems, count, d_x, d_y, phase_ms, precision));
 }
 
 tt_status tt_solve_frame(tt_ctx* ctx, const float* d_s, const double* d_x0, double* d_zeta, float* d_phi,

@@ -55,6 +55,8 @@ struct BSys {
     c32* T;            // [Lh][C][n]
     c32* U;            // [Lh][S][C][n]
     const float* M;    // [Lh][L][3G^2]
+    const unsigned short* Mh;   // the same in FP16 / BF16 (half-precision storage), or null
+    const float* Mhs;           // [Lh][L] factor restoring each frequency's FP16 values (1 for BF16)
     const float* noise;
     const float* nxy;  // NULL unless the noise has 2x2 blocks
     int n, G, L, n_vs;
@@ -235,6 +237,71 @@ __device__ __forceinline__ void spectra_store(const typename vecf<VEC>::t (&pf)[
                 d[3] = pf[i].w;
             } else {
                 d[0] = pf[i];
+            }
+        }
+        w += dw;
+        const int cy = w >= Pv;
+        w -= cy ? Pv : 0;
+        k += dk + cy;
+    }
+}
+
+// Half-precision spectra (HALF = 1: FP16 scaled per frequency, 2: BF16): the
+// raw 16-bit values of a round are kept in registers with the factor of their
+// frequency and decoded when stored to LDS (FP32 from there on).
+template <int VEC> struct vech;
+template <> struct vech<1> { typedef unsigned short t; };
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+template <> struct vech<4> { typedef u2v t; };
+template <int VEC>
+using ghvec_ptr = const __attribute__((address_space(1))) typename vech<VEC>::t*;
+
+template <int VEC>
+__device__ __forceinline__ void spectra_load_h(typename vech<VEC>::t (&pf)[NPF], float (&pfs)[NPF],
+                                               const unsigned short* Mcol, const float* scol, int base, int Q, int P,
+                                               int S, int h) {
+    const int Pv = P / VEC;
+    const int dk = BT / Pv, dw = BT - dk * Pv;
+    int k = (base + (int)threadIdx.x) / Pv, w = (base + (int)threadIdx.x) - k * Pv;
+    const ghvec_ptr<VEC> g = (ghvec_ptr<VEC>)Mcol;
+    const __attribute__((address_space(1))) float* gs = (const __attribute__((address_space(1))) float*)scol;
+#pragma unroll
+    for (int i = 0; i < NPF; ++i) {
+        if (base + (int)threadIdx.x + i * BT < Q) {
+            pf[i] = g[(S * k + h) * Pv + w];
+            pfs[i] = gs[S * k + h];
+        }
+        w += dw;
+        const int cy = w >= Pv;
+        w -= cy ? Pv : 0;
+        k += dk + cy;
+    }
+}
+
+template <int HALF>
+__device__ __forceinline__ float half_dec(unsigned short b) {
+    if constexpr (HALF == 1) return (float)__builtin_bit_cast(_Float16, b);
+    else return __uint_as_float((unsigned)b << 16);
+}
+
+template <int VEC, int HALF>
+__device__ __forceinline__ void spectra_store_h(const typename vech<VEC>::t (&pf)[NPF], const float (&pfs)[NPF],
+                                                float* Ms, int base, int Q, int P, int rbits) {
+    const int Pv = P / VEC;
+    const int dk = BT / Pv, dw = BT - dk * Pv;
+    int k = (base + (int)threadIdx.x) / Pv, w = (base + (int)threadIdx.x) - k * Pv;
+#pragma unroll
+    for (int i = 0; i < NPF; ++i) {
+        if (base + (int)threadIdx.x + i * BT < Q) {
+            float* d = Ms + (rbits >= 0 ? bitrev(k, rbits) : k) * (P + 1) + w * VEC;
+            const float sc = pfs[i];
+            if constexpr (VEC == 4) {
+                d[0] = half_dec<HALF>((unsigned short)(pf[i].x & 0xffffu)) * sc;
+                d[1] = half_dec<HALF>((unsigned short)(pf[i].x >> 16)) * sc;
+                d[2] = half_dec<HALF>((unsigned short)(pf[i].y & 0xffffu)) * sc;
+                d[3] = half_dec<HALF>((unsigned short)(pf[i].y >> 16)) * sc;
+            } else {
+                d[0] = half_dec<HALF>(pf[i]) * sc;
             }
         }
         w += dw;
@@ -469,7 +536,9 @@ __device__ __forceinline__ void herm_products(const float* Ms, const c32* X, int
 // the next item load under the products and inverse transform of the current.
 // PACK 0: the slope-slope spectra (3 G^2 reals per frequency); PACK 1: the
 // preconditioner's general Hermitian spectra (C^2 reals per frequency)
-template <int VEC, int PACK>
+// HALF: spectra stored in FP32 (0), FP16 scaled per frequency (1) or BF16 (2);
+// the products are FP32 either way.
+template <int VEC, int PACK, int HALF>
 __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, const int* __restrict__ col_sys,
                                                  int total_cols, int S, int Lmax) {
     extern __shared__ __align__(16) char smem_raw[];
@@ -483,12 +552,18 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
     // this item's spectra and input column, prefetched; the system of the next
     // item is looked up one item ahead
     typename vecf<VEC>::t pf[NPF];
+    typename vech<VEC>::t pfh[NPF];
+    float pfs[NPF];
     c32 tp[TPF];
     int si = col_sys[col];
     {
         const BSys& s0 = sys[si];
         const int f20 = col - s0.col0, P0 = PACK ? 4 * s0.G * s0.G : 3 * s0.G * s0.G, Cn0 = 2 * s0.G * s0.n;
-        spectra_load<VEC>(pf, s0.M + (size_t)f20 * s0.L * P0, 0, (s0.L >> sh) * P0 / VEC, P0, S, h);
+        if constexpr (HALF)
+            spectra_load_h<VEC>(pfh, pfs, s0.Mh + (size_t)f20 * s0.L * P0, s0.Mhs + (size_t)f20 * s0.L, 0,
+                                (s0.L >> sh) * P0 / VEC, P0, S, h);
+        else
+            spectra_load<VEC>(pf, s0.M + (size_t)f20 * s0.L * P0, 0, (s0.L >> sh) * P0 / VEC, P0, S, h);
 #pragma unroll
         for (int i = 0; i < TPF; ++i) {
             const int idx = threadIdx.x + i * BT;
@@ -514,6 +589,8 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
         const int hn = (qn >> 3) & hm;
         const BSys& sn = sys[sin_];
         const float* Mn = sn.M;
+        const unsigned short* Mnh = sn.Mh;
+        const float* Mnhs = sn.Mhs;
         const c32* Tn = sn.T;
         const int Ln = sn.L, Gn = sn.G, nn = sn.n, f2n = coln - sn.col0;
 
@@ -574,12 +651,22 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
         }
 
         // this item's spectra to LDS: first round from the registers, then round by round
-        const float* Mcol = s.M + (size_t)f2 * L * P;
         const int rbits = fft ? bits : -1;
-        spectra_store<VEC>(pf, Ms, 0, Q / VEC, P, rbits);
-        for (int base = NPF * BT; base < Q / VEC; base += NPF * BT) {
-            spectra_load<VEC>(pf, Mcol, base, Q / VEC, P, S, h);
-            spectra_store<VEC>(pf, Ms, base, Q / VEC, P, rbits);
+        if constexpr (HALF) {
+            const unsigned short* Mcol = s.Mh + (size_t)f2 * L * P;
+            const float* scol = s.Mhs + (size_t)f2 * L;
+            spectra_store_h<VEC, HALF>(pfh, pfs, Ms, 0, Q / VEC, P, rbits);
+            for (int base = NPF * BT; base < Q / VEC; base += NPF * BT) {
+                spectra_load_h<VEC>(pfh, pfs, Mcol, scol, base, Q / VEC, P, S, h);
+                spectra_store_h<VEC, HALF>(pfh, pfs, Ms, base, Q / VEC, P, rbits);
+            }
+        } else {
+            const float* Mcol = s.M + (size_t)f2 * L * P;
+            spectra_store<VEC>(pf, Ms, 0, Q / VEC, P, rbits);
+            for (int base = NPF * BT; base < Q / VEC; base += NPF * BT) {
+                spectra_load<VEC>(pf, Mcol, base, Q / VEC, P, S, h);
+                spectra_store<VEC>(pf, Ms, base, Q / VEC, P, rbits);
+            }
         }
         __syncthreads();
 
@@ -589,7 +676,11 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
         const int colnn = ((qnn >> 3) >> sh) * 8 + (qnn & 7);
         if (more) {
             const int Pn = PACK ? 4 * Gn * Gn : 3 * Gn * Gn, Cnn = 2 * Gn * nn;
-            spectra_load<VEC>(pf, Mn + (size_t)f2n * Ln * Pn, 0, (Ln >> sh) * Pn / VEC, Pn, S, hn);
+            if constexpr (HALF)
+                spectra_load_h<VEC>(pfh, pfs, Mnh + (size_t)f2n * Ln * Pn, Mnhs + (size_t)f2n * Ln, 0,
+                                    (Ln >> sh) * Pn / VEC, Pn, S, hn);
+            else
+                spectra_load<VEC>(pf, Mn + (size_t)f2n * Ln * Pn, 0, (Ln >> sh) * Pn / VEC, Pn, S, hn);
 #pragma unroll
             for (int i = 0; i < TPF; ++i) {
                 const int idx = threadIdx.x + i * BT;
@@ -686,6 +777,67 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
     }
 }
 
+// FP32 spectra rows (one frequency each, P reals) -> FP16 or BF16 storage.
+// FP16: each row is multiplied by the power of two 2^(15 - e) that brings its
+// largest magnitude m = f 2^e (f in [0.5, 1)) to [2^14, 2^15) and stored with
+// the factor 2^(e - 15) that restores it (exact powers of two); every stored
+// value is then within u m of the exact one, u = 2^-11.  BF16 keeps the FP32
+// exponent range and is stored unscaled (factor 1), u = 2^-8.  Round to nearest
+// even.  With ndiag > 0 the row is the general Hermitian packing of a C x C
+// positive definite block (the preconditioner, C = ndiag, diagonal in slots
+// 0 .. C-1): its diagonal is first raised by d = s m' with s = 1.5 C u and
+// m' = m / (1 - s), which exceeds the Frobenius norm (<= sqrt(2) C u m') of the
+// rounding error of the raised block, so the stored block is still positive
+// definite: the preconditioner stays symmetric positive definite.
+__global__ void k_to_half(const float* __restrict__ M, unsigned short* __restrict__ Mh, float* __restrict__ fac,
+                          long rows, int P, int kind, int ndiag) {
+    const float u = kind == TT_PREC_F16 ? 0x1p-11f : 0x1p-8f;
+    for (long r = blockIdx.x; r < rows; r += gridDim.x) {
+        const float* src = M + r * P;
+        float m = 0.0f;
+        for (int i = threadIdx.x; i < P; i += 64) m = fmaxf(m, fabsf(src[i]));
+        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+        float shift = 0.0f;
+        if (ndiag > 0) {
+            const float sfac = 1.5f * (float)ndiag * u;
+            shift = sfac * m / (1.0f - sfac);
+            m += shift;
+        }
+        float up = 1.0f, back = 1.0f;
+        if (kind == TT_PREC_F16 && m > 0.0f) {
+            int e;
+            frexpf(m, &e);
+            up = ldexpf(1.0f, 15 - e);
+            back = ldexpf(1.0f, e - 15);
+        }
+        for (int i = threadIdx.x; i < P; i += 64) {
+            const float v = (src[i] + (i < ndiag ? shift : 0.0f)) * up;
+            unsigned short b;
+            if (kind == TT_PREC_F16) {
+                b = __builtin_bit_cast(unsigned short, (_Float16)v);
+            } else {
+                const unsigned uu = __float_as_uint(v);
+                b = (unsigned short)((uu + 0x7fffu + ((uu >> 16) & 1u)) >> 16);
+            }
+            Mh[r * P + i] = b;
+        }
+        if (threadIdx.x == 0) fac[r] = back;
+    }
+}
+
+tt_status ensure_half(tt_ctx& c, int op, int kind) {
+    if (c.mh_kind[op] == kind) return TT_OK;
+    const int P = op ? c.C * c.C : packed_reals(c.G);
+    const long rows = (long)c.Lh * c.L;
+    TT_CHECK(c.Mh[op].alloc((size_t)rows * P));
+    TT_CHECK(c.Mhs[op].alloc((size_t)rows));
+    hipLaunchKernelGGL(k_to_half, dim3((unsigned)std::min<long>(rows, 65535)), dim3(64), 0, c.stream,
+                       op ? c.Minv32.p : c.M32.p, c.Mh[op].p, c.Mhs[op].p, rows, P, kind, op ? c.C : 0);
+    TT_HIP(hipGetLastError());
+    c.mh_kind[op] = kind;
+    return TT_OK;
+}
+
 // LDS of one column item past the twiddles: spectra (padded), transform buffer(s)
 size_t col_work_lds(int G, int L, int S, int pack) {
     const int m = L / S, C = 2 * G, P = pack ? C * C : 3 * G * G;
@@ -700,8 +852,11 @@ size_t col_work_lds(int G, int L, int S, int pack) {
 // block-circulant preconditioner u = W_s S2 F^-1 (M_+ + sigma^2)^-1 F S1 W_s^T r,
 // op 1 (spectra built by precond_build; no noise term).
 tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x, float* const* d_y, int op,
-                      float* phase_ms) {
+                      float* phase_ms, int precision) {
     TT_REQUIRE(count >= 0 && count <= 65535, "count must be in [0, 65535]");
+    TT_REQUIRE(precision == TT_PREC_F32 || precision == TT_PREC_F16 || precision == TT_PREC_BF16,
+               "spectra precision must be TT_PREC_F32, TT_PREC_F16 or TT_PREC_BF16");
+    const int half = precision == TT_PREC_F16 ? 1 : precision == TT_PREC_BF16 ? 2 : 0;
     if (count == 0) return TT_OK;
     TT_REQUIRE(systems && d_x && d_y, "NULL argument");
     tt_ctx& c0 = *systems[0];
@@ -752,7 +907,11 @@ tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x
         tt_ctx& c = *systems[i];
         const size_t ucount = (size_t)c.Lh * S * c.C * c.n;
         if (c.bU32.n < ucount) TT_CHECK(c.bU32.alloc(ucount));
+        if (half) TT_CHECK(ensure_half(c, op, precision));
+        // the half copies are built on each system's own stream, the kernels run on the first one's
+        if (half && c.stream != c0.stream) TT_HIP(hipStreamSynchronize(c.stream));
         d[i] = BSys{d_x[i], d_y[i], c.vmap.p, c.tw32.p, c.T32.p, c.bU32.p, op ? c.Minv32.p : c.M32.p,
+                    half ? c.Mh[op].p : nullptr, half ? c.Mhs[op].p : nullptr,
                     op ? nullptr : c.noise32.p, (!op && c.has_nxy) ? c.nxy32.p : nullptr, c.n, c.G, c.L, c.n_vs,
                     cols};
         cols += c.Lh;
@@ -783,8 +942,12 @@ tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x
     bool vec4 = true;
     for (int i = 0; i < count; ++i)
         if (!op && (3 * systems[i]->G * systems[i]->G) % 4) vec4 = false;   // C^2 is always a multiple of 4
-    const void* kcol = op ? (const void*)k_bcol<4, 1>
-                          : (vec4 ? (const void*)k_bcol<4, 0> : (const void*)k_bcol<1, 0>);
+    typedef void (*ColKernel)(const BSys*, const int*, int, int, int);
+    static const ColKernel table[2][2][3] = {
+        {{k_bcol<1, 0, 0>, k_bcol<1, 0, 1>, k_bcol<1, 0, 2>}, {k_bcol<1, 0, 0>, k_bcol<1, 0, 1>, k_bcol<1, 0, 2>}},
+        {{k_bcol<4, 0, 0>, k_bcol<4, 0, 1>, k_bcol<4, 0, 2>}, {k_bcol<4, 1, 0>, k_bcol<4, 1, 1>, k_bcol<4, 1, 2>}}};
+    const ColKernel kc = table[(op || vec4) ? 1 : 0][op ? 1 : 0][half];
+    const void* kcol = (const void*)kc;
     TT_HIP(hipFuncSetAttribute(kcol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
     TT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kcol, BT, lds));
@@ -797,12 +960,7 @@ tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x
     hipLaunchKernelGGL(k_brow_fwd, dim3(fwd_tiles, count), dim3(RBT), 0, c0.stream, dd);
     TT_HIP(hipGetLastError());
     if (phase_ms) TT_HIP(hipEventRecord(c0.bev[1], c0.stream));
-    if (op)
-        hipLaunchKernelGGL((k_bcol<4, 1>), dim3(col_grid), dim3(BT), lds, c0.stream, dd, col_sys, cols, S, Lmax);
-    else if (vec4)
-        hipLaunchKernelGGL((k_bcol<4, 0>), dim3(col_grid), dim3(BT), lds, c0.stream, dd, col_sys, cols, S, Lmax);
-    else
-        hipLaunchKernelGGL((k_bcol<1, 0>), dim3(col_grid), dim3(BT), lds, c0.stream, dd, col_sys, cols, S, Lmax);
+    hipLaunchKernelGGL(kc, dim3(col_grid), dim3(BT), lds, c0.stream, dd, col_sys, cols, S, Lmax);
     TT_HIP(hipGetLastError());
     if (phase_ms) TT_HIP(hipEventRecord(c0.bev[2], c0.stream));
     hipLaunchKernelGGL(k_brow_inv, dim3(inv_tiles, count), dim3(RBT), 0, c0.stream, dd, S);
@@ -816,6 +974,6 @@ tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x
 }
 
 tt_status matvec_batch(tt_ctx* const* systems, int count, const float* const* d_x, float* const* d_y,
-                       float* phase_ms) {
-    return batch_apply(systems, count, d_x, d_y, 0, phase_ms);
+                       float* phase_ms, int precision) {
+    return batch_apply(systems, count, d_x, d_y, 0, phase_ms, precision);
 }

@@ -241,6 +241,7 @@ __global__ void k_bgather(const BVec* __restrict__ vs, int count, CgScalars* __r
 // fallen back to plain CG, indices into act, uploaded at dfb).
 struct PcPlan {
     int mode = 0;
+    int prec = TT_PREC_F32;                  // storage precision of the block-circulant spectra
     std::vector<std::pair<int, int>> runs;   // learned: [begin, end) of act sharing a network and geometry
     std::vector<int> fb;                     // fallen back: indices into act
     DevBuf<int> dfb;
@@ -273,7 +274,7 @@ tt_status plan_precond(PcPlan& plan, tt_ctx* const* act, int na, const std::vect
 
 tt_status apply_precond(const PcPlan& plan, tt_ctx* const* act, int na, const float* const* pr, float* const* pu,
                         const BVec* dvec, int starting, hipStream_t st) {
-    if (plan.mode == TT_PRECOND_CIRCULANT) return batch_apply(act, na, pr, pu, 1, nullptr);
+    if (plan.mode == TT_PRECOND_CIRCULANT) return batch_apply(act, na, pr, pu, 1, nullptr, plan.prec);
     for (const auto& run : plan.runs)
         TT_CHECK(learned_apply_batch(*act[run.first]->learned, *act[run.first], pr + run.first, pu + run.first,
                                      run.second - run.first, st));
@@ -347,6 +348,7 @@ tt_status solve_batched(tt_ctx* const* systems, int count, const float* const* d
     std::vector<float*> qy, pu;
     PcPlan plan, plan1;
     plan.mode = plan1.mode = mode;
+    plan.prec = plan1.prec = o.precision;   // FP16 / BF16: the preconditioner's spectra only
     auto gather_active = [&]() {
         for (int i = 0; i < count; ++i)   // iteration cap reached (max_iter 0 included)
             if (!done[i] && h[i].iter >= o.max_iter) {

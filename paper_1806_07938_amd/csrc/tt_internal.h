@@ -168,6 +168,9 @@ struct tt_ctx {
     DevBuf<unsigned char> bdesc[2];     // batched product / preconditioner: per-system descriptors
     std::vector<unsigned char> bdesc_host[2];   // (kept by the first context of a call)
     hipEvent_t bev[4] = {nullptr, nullptr, nullptr, nullptr};   // batched product phase timing
+    DevBuf<unsigned short> Mh[2];       // batched operators: slope / preconditioner spectra in FP16 or BF16
+    DevBuf<float> Mhs[2];               // their per-frequency factors [Lh][L]
+    int mh_kind[2] = {0, 0};            // tt_precision the half copies hold (0: none)
     DevBuf<float> Minv32;               // circulant preconditioner spectra [Lh][L][C^2] (general Hermitian packing)
     DevBuf<double> Minv64;
     bool pc_ready = false;              // Minv built for the current system
@@ -214,9 +217,10 @@ tt_status matvec_f64(tt_ctx& c, const double* x, double* y, double* part);
 
 // batch.hip
 tt_status matvec_batch(tt_ctx* const* systems, int count, const float* const* d_x, float* const* d_y,
-                       float* phase_ms);
+                       float* phase_ms, int precision);
 tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x, float* const* d_y, int op,
-                      float* phase_ms);   // op 0: the product, op 1: the block-circulant preconditioner
+                      float* phase_ms, int precision = TT_PREC_F32);   // op 0: the product, op 1: the block-circulant
+                                                                       // preconditioner; spectra storage precision
 
 // cg.hip
 tt_status cg_alloc(tt_ctx& c);

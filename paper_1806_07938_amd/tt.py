@@ -33,7 +33,7 @@ MODEL_HUDGIN, MODEL_FRIED = 0, 1
 EXPORTED = (
     "tt_create", "tt_destroy", "tt_generate_kernels", "tt_kernels_destroy", "tt_kernels_copy",
     "tt_set_system", "tt_set_noise_xy", "tt_set_mode_removal", "tt_get_system_info", "tt_matvec", "tt_matvec_f64", "tt_matvec_batch",
-    "tt_matvec_noalloc", "tt_learned_create", "tt_learned_destroy", "tt_learned_weight_count",
+    "tt_matvec_noalloc", "tt_matvec_batch_prec", "tt_learned_create", "tt_learned_destroy", "tt_learned_weight_count",
     "tt_learned_get_weights", "tt_learned_set_weights", "tt_learned_apply", "tt_learned_train_step",
     "tt_learned_train", "tt_set_learned",
     "tt_solve_frame", "tt_solve_batch", "tt_project", "tt_status_string", "tt_last_error", "tt_pupil_mask",
@@ -140,6 +140,8 @@ def load(path: str = LIB_PATH):
     lib.tt_matvec.argtypes = [vp, vp, vp]
     lib.tt_matvec_f64.argtypes = [vp, vp, vp]
     lib.tt_matvec_noalloc.argtypes = [vp, vp, vp]
+    lib.tt_matvec_batch_prec.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(vp), C.POINTER(vp), C.c_int,
+                                         C.POINTER(C.c_float)]
     lib.tt_learned_create.argtypes = [C.POINTER(vp), C.c_int, C.c_int, C.c_int, C.c_ulonglong]
     lib.tt_learned_destroy.argtypes = [vp]
     lib.tt_learned_weight_count.argtypes = [vp, C.POINTER(C.c_size_t)]
@@ -480,10 +482,11 @@ def system_from(ctx: Context, wl, target: bool = True, pad_L: Optional[int] = No
     return k
 
 
-def matvec_batch(contexts, xs, ys=None, timing: bool = False):
+def matvec_batch(contexts, xs, ys=None, timing: bool = False, precision: int = PREC_F32):
     """tt_matvec_batch: ys[i] = A_i xs[i] (device float32 vectors) for every
-    context in one call on the stream of contexts[0].  With timing=True the
-    call waits and also returns the three phase durations in ms."""
+    context in one call on the stream of contexts[0] (tt_matvec_batch_prec with
+    the spectra in FP16 / BF16 storage for those precisions).  With timing=True
+    the call waits and also returns the three phase durations in ms."""
     import torch
     m = len(contexts)
     assert len(xs) == m
@@ -494,7 +497,10 @@ def matvec_batch(contexts, xs, ys=None, timing: bool = False):
     xp = arr(*[_dptr(x, torch.float32, c.info["n_slopes"]) for c, x in zip(contexts, xs)])
     yp = arr(*[_dptr(y, torch.float32, c.info["n_slopes"]) for c, y in zip(contexts, ys)])
     ms = (C.c_float * 3)()
-    _check(load().tt_matvec_batch(hs, m, xp, yp, ms if timing else None))
+    if precision == PREC_F32:
+        _check(load().tt_matvec_batch(hs, m, xp, yp, ms if timing else None))
+    else:
+        _check(load().tt_matvec_batch_prec(hs, m, xp, yp, int(precision), ms if timing else None))
     return (ys, [float(v) for v in ms]) if timing else ys
 
 

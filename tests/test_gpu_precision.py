@@ -72,6 +72,35 @@ def test_full_solve_status_is_honest(c1sys, precision):
         assert info.status == TT_NOT_CONVERGED and info.rel_residual > 1e-6
 
 
+@pytest.mark.parametrize("precision", sorted(FORMS))
+def test_batched_pcg_with_half_preconditioner_spectra_converges(c1sys, precision):
+    """TT_SOLVER_BATCHED + TT_PRECOND_CIRCULANT with FP16 / BF16: only the
+    preconditioner's spectra are stored in reduced precision; the FP32 product
+    and the FP64 residual replacement keep the method exact, so the solve
+    reaches 1e-6 (and 1e-10, config 1's tolerance) like the FP32 form."""
+    import torch
+    from oracle.covariance import system_matrix
+    from oracle.solve import cholesky_solve
+    from paper_1806_07938_amd.tt import PRECOND_CIRCULANT, SOLVER_BATCHED
+    wl, ctx, k = c1sys
+    A = system_matrix(wl)
+    s = W.turbulent_slopes(wl)[0].astype(np.float32)
+    st = torch.tensor(s, device=torch_dev())
+    zref = cholesky_solve(A, s.astype(np.float64))
+    for tol in (1e-6, 1e-10):
+        z, phi, info = ctx.solve(st, tol=tol, precision=precision, solver=SOLVER_BATCHED,
+                                 preconditioner=PRECOND_CIRCULANT)
+        _, _, info32 = ctx.solve(st, tol=tol, solver=SOLVER_BATCHED, preconditioner=PRECOND_CIRCULANT)
+        zz = z.cpu().numpy()
+        res = np.linalg.norm(s - A @ zz) / np.linalg.norm(s)
+        err = np.linalg.norm(zz - zref) / np.linalg.norm(zref)
+        say(f"precision {precision} tol {tol:g}: {info.iterations} iterations (FP32 spectra {info32.iterations}), "
+            f"oracle residual {res:.2e}, zeta error {err:.2e}")
+        assert info.status == 0 and res <= 1.01 * tol
+        if tol == 1e-10:
+            assert err < 1e-5
+
+
 def test_low_precision_needs_persistent_solver(c1sys):
     import torch
     from paper_1806_07938_amd import TTError

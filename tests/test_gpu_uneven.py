@@ -60,3 +60,65 @@ def test_uneven_batched_solves(uneven, pc):
         assert inf.status == 0 and inf.rel_residual <= tol
         sd = s.astype(np.float64)
         assert np.linalg.norm(sd - op(z.cpu().numpy())) <= 1.01 * tol * np.linalg.norm(sd), wl.name
+
+
+# Half-precision spectra storage (tt_matvec_batch_prec).  Each frequency's
+# stored values carry an absolute rounding error of at most u times that
+# frequency's largest value (FP16, scaled to [2^14, 2^15): u = 2^-11; BF16:
+# u = 2^-8), so by Parseval the product error is bounded in 2-norm by
+# C u ||A||_2 ||x||_2 (C channels; a frequency's C x C block has norm <= C times
+# its largest entry, which is <= ||A||_2).  ||A||_2 is under-estimated here by
+# power iteration, which only tightens the check.
+HALF_FORMS = {2: 2.0 ** -11, 3: 2.0 ** -8}
+
+
+def _norm_estimate(op, n, rng, its=30):
+    v = rng.standard_normal(n)
+    lam = 0.0
+    for _ in range(its):
+        w = op(v)
+        lam = np.linalg.norm(w) / np.linalg.norm(v)
+        v = w / np.linalg.norm(w)
+    return lam
+
+
+@pytest.mark.parametrize("precision", sorted(HALF_FORMS), ids=["f16", "bf16"])
+def test_uneven_batched_product_half_spectra(uneven, precision):
+    import torch
+    from paper_1806_07938_amd import matvec_batch
+    wls, systems, ops = uneven
+    dev = torch_dev()
+    rng = np.random.default_rng(23)
+    xs = [rng.standard_normal(wl.n_slopes).astype(np.float32) for wl in wls]
+    ys = matvec_batch([c for c, k in systems], [torch.tensor(x, device=dev) for x in xs], precision=precision)
+    u = HALF_FORMS[precision]
+    for wl, op, x, y in zip(wls, ops, xs, ys):
+        ref = op(x.astype(np.float64))
+        err = np.linalg.norm(y.cpu().numpy() - ref)
+        bound = 2 * wl.n_gs * u * _norm_estimate(op, wl.n_slopes, rng) * np.linalg.norm(x)
+        say(f"{wl.name} precision {precision}: |dy| / (C u |A| |x|) = {err / bound:.3e}, "
+            f"rel max-abs {rel_maxabs(y.cpu().numpy(), ref):.2e}")
+        assert err <= bound
+
+
+@pytest.mark.parametrize("precision", sorted(HALF_FORMS), ids=["f16", "bf16"])
+def test_uneven_batched_pcg_half_spectra(uneven, precision):
+    """Batched PCG whose block-circulant preconditioner streams FP16 / BF16
+    spectra: the product stays FP32, so every frame still reaches the
+    tolerance, certified by the FP64 residual and by the oracle's operator."""
+    import torch
+    from paper_1806_07938_amd import solve_batch
+    from paper_1806_07938_amd.tt import PRECOND_CIRCULANT, SOLVER_BATCHED
+    wls, systems, ops = uneven
+    dev = torch_dev()
+    S = [W.turbulent_slopes(wl)[0].astype(np.float32) for wl in wls]
+    tol = 1e-6
+    zs, _, infos, st = solve_batch([c for c, k in systems], [torch.tensor(s, device=dev) for s in S], tol=tol,
+                                   solver=SOLVER_BATCHED, preconditioner=PRECOND_CIRCULANT, precision=precision)
+    assert st == 0
+    for wl, op, s, z, inf in zip(wls, ops, S, zs, infos):
+        zz = z.cpu().numpy()
+        res = np.linalg.norm(s - op(zz)) / np.linalg.norm(s)
+        say("uneven pcg precision", precision, wl.name, "iterations", inf.iterations, "rel", inf.rel_residual,
+            "oracle", res)
+        assert inf.status == 0 and inf.rel_residual <= tol and res <= 1.01 * tol
