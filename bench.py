@@ -59,10 +59,13 @@ def parse():
     ap.add_argument("--batch-pad", type=int, default=256, help="FFT side L of the batched systems")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--batch-only", action="store_true", help="run only the batched-product measurement")
+    ap.add_argument("--uneven", type=int, default=64, help="uneven systems in the uneven batched measurement (0: skip)")
     ap.add_argument("--batch-solve-frames", type=int, default=0,
                     help="with --batch-only: also time the batched solves (plain and preconditioned CG) with this "
                          "many measured frames of lgs6_74x74 as right-hand sides")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner records")
+    ap.add_argument("--learned-only", action="store_true", help="run only the learned-preconditioner records")
+    ap.add_argument("--no-multi", action="store_true", help="skip the many-frames-of-one-system records")
     ap.add_argument("--learned-steps", type=int, default=3000, help="optimiser steps of the learned preconditioner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 256 MiB device buffer 3 times (reference kernel for rocprofv3 "
@@ -146,6 +149,70 @@ def batch_traffic_record():
         return None
 
 
+def _uneven_frame(i):
+    import workloads as W
+    return W.turbulent_slopes(W.uneven_family(i))[0].astype(np.float32)
+
+
+def batch_uneven(args):
+    """args.uneven systems of workloads.uneven_family (grids 40 / 60 / 74 / 84 in
+    turn, 4-8 LGS, 10-35 layers, noise 0.01-0.5 rad^2, L the power of two >= 2n):
+    the batched product (with the column kernel's roofline) and one measured
+    frame per system solved together by lockstep plain CG."""
+    import multiprocessing as mp
+    import torch
+    import workloads as W
+    from paper_1806_07938_amd import Context, system_from
+    ctxs, keep = [], []
+    t0 = time.perf_counter()
+    for i in range(args.uneven):
+        c = Context(0)
+        keep.append(system_from(c, W.uneven_family(i), target=False))
+        ctxs.append(c)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with mp.get_context("fork").Pool(workers) as pool:
+        frames = pool.map(_uneven_frame, range(args.uneven))
+    grids = sorted({c.info["n"] for c in ctxs})
+    label = (f"{args.uneven} uneven systems (grids {'/'.join(map(str, grids))}, 4-8 LGS, 10-35 layers, noise "
+             "0.01-0.5 rad^2, r0 0.10-0.25 m, L = 128 / 256)")
+    out = {"batch_matvec_uneven": batch_matvec(args, ctxs, setup_s, label=label),
+           "batch_solve_uneven": batch_solve(args, ctxs, frames, 0, label=label)}
+    for c in ctxs + keep:
+        c.close()
+    return out
+
+
+def multi_rhs(args, ctx, frames, pc):
+    """All frames of the nominal system solved together: the base context and
+    len(frames) - 1 views sharing its spectra (tt_create_view), lockstep CG
+    (TT_SOLVER_BATCHED), plain or preconditioned by the block-circulant inverse."""
+    import torch
+    from paper_1806_07938_amd import solve_batch
+    from paper_1806_07938_amd.tt import SOLVER_BATCHED, TT_NOT_CONVERGED
+    views = [ctx.view() for _ in range(len(frames) - 1)]
+    S = [torch.tensor(f, device="cuda:0") for f in frames]
+    allow = (0, TT_NOT_CONVERGED)
+    solve_batch([ctx] + views, S, tol=args.tol, solver=SOLVER_BATCHED, preconditioner=pc, allow=allow)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, infos, st = solve_batch([ctx] + views, S, tol=args.tol, solver=SOLVER_BATCHED, preconditioner=pc,
+                                  allow=allow)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    for v in views:
+        v.close()
+    it = np.array([i.iterations for i in infos], dtype=np.float64)
+    return {"workload": (f"{len(frames)} frames of the 74x74 / 6 LGS system (L={args.pad}) solved together on one "
+                         "system and its views (shared spectra), lockstep "
+                         + ("CG preconditioned by the block-circulant inverse" if pc else "plain CG")
+                         + f" to rel. residual {args.tol:g}"),
+            "frames": len(frames), "ms_per_batch": round(wall, 2), "ms_per_solve": round(wall / len(frames), 3),
+            "iterations_mean": round(float(it.mean()), 1), "iterations_max": int(it.max()),
+            "all_converged": bool(st == 0 and all(i.status == 0 and i.rel_residual <= args.tol for i in infos))}
+
+
 def batch_systems(args):
     """args.batch distinct 74x74 / 6 LGS systems (seeded layer weights and r0,
     L = args.batch_pad); returns (contexts, kernel objects, set-up seconds)."""
@@ -163,7 +230,7 @@ def batch_systems(args):
     return ctxs, keep, time.perf_counter() - t0
 
 
-def batch_solve(args, ctxs, frames, pc, precision=0):
+def batch_solve(args, ctxs, frames, pc, precision=0, label=None):
     """TT_SOLVER_BATCHED over the same systems: one frame each (the measured
     frames of lgs6_74x74 reused in turn as right-hand sides), FP32 CG (plain,
     or preconditioned by the block-circulant inverse when pc) with the FP64
@@ -173,6 +240,8 @@ def batch_solve(args, ctxs, frames, pc, precision=0):
     from paper_1806_07938_amd import solve_batch
     from paper_1806_07938_amd.tt import SOLVER_BATCHED, TT_NOT_CONVERGED
     S = [torch.tensor(frames[i % len(frames)], device="cuda:0") for i in range(len(ctxs))]
+    if label:   # one right-hand side per system (frames[i] belongs to ctxs[i])
+        assert len(frames) == len(ctxs)
     t0 = time.perf_counter()
     prec = precision if precision else 0
     if pc:   # preconditioner spectra, once per system (host FP64), before the untimed batch
@@ -190,8 +259,8 @@ def batch_solve(args, ctxs, frames, pc, precision=0):
     wall = (time.perf_counter() - t0) * 1e3
     it = np.array([i.iterations for i in infos], dtype=np.float64)
     return {
-        "workload": (f"{len(ctxs)} distinct 74x74 / 6 LGS / 35-layer systems, L={args.batch_pad}, one frame each, "
-                     f"solved together (TT_SOLVER_BATCHED: "
+        "workload": ((label or f"{len(ctxs)} distinct 74x74 / 6 LGS / 35-layer systems, L={args.batch_pad}")
+                     + ", one frame each, solved together (TT_SOLVER_BATCHED: "
                      + ("CG preconditioned by the block-circulant inverse" if pc else "plain CG")
                      + ({2: " (its spectra stored in FP16)", 3: " (its spectra stored in BF16)"}.get(prec, ""))
                      + f" in lockstep, FP32 + FP64 residual replacement) to rel. residual {args.tol:g}"),
@@ -203,7 +272,7 @@ def batch_solve(args, ctxs, frames, pc, precision=0):
     }
 
 
-def batch_matvec(args, ctxs, setup_s, precision=0):
+def batch_matvec(args, ctxs, setup_s, precision=0, label=None):
     """tt_matvec_batch over the systems: spectra of all of them streamed once
     per call.  Roofline of the column kernel: algorithmic bytes = the packed
     spectra of every system (FP32, or FP16 / BF16 storage plus one FP32 factor
@@ -232,13 +301,13 @@ def batch_matvec(args, ctxs, setup_s, precision=0):
     traffic = batch_traffic_record() if (args.batch == 64 and args.batch_pad == 256 and not precision) else None
     pname = {0: "FP32", 2: "FP16 (per-frequency power-of-two scale)", 3: "BF16"}[precision]
     return {
-        "workload": (f"{args.batch} distinct 74x74 / 6 LGS / 35-layer systems (seeded layer weights, r0 in "
-                     f"[0.10, 0.25] m), L={args.batch_pad}, one product each per call, spectra stored in {pname}, "
-                     "FP32 arithmetic"),
-        "systems": args.batch, "pad_L": args.batch_pad, "steps": args.batch_steps,
+        "workload": ((label or f"{args.batch} distinct 74x74 / 6 LGS / 35-layer systems (seeded layer weights, r0 "
+                      f"in [0.10, 0.25] m), L={args.batch_pad}")
+                     + f", one product each per call, spectra stored in {pname}, FP32 arithmetic"),
+        "systems": len(ctxs), "pad_L": args.batch_pad if not label else "per system", "steps": args.batch_steps,
         "ms_per_call_wall": round(wall_ms, 4),
         "ms_per_call_gpu": round(float(ph.sum()), 4),
-        "us_per_system_product": round(float(ph.sum()) * 1e3 / args.batch, 3),
+        "us_per_system_product": round(float(ph.sum()) * 1e3 / len(ctxs), 3),
         "phase_ms": {"row_fwd": round(float(ph[0]), 4), "col": round(float(ph[1]), 4),
                      "row_inv": round(float(ph[2]), 4)},
         "algorithmic_bytes": {"spectra": int(spectra), "slopes_in_out": int(slopes)},
@@ -301,6 +370,23 @@ def learned_record(wl_of, family, n_systems, steps, frames, tol, label):
                                             "objective_last": round(tinfo["objective_last"], 1),
                                             "device_ms": round(tinfo["ms"], 1), "wall_s": round(train_s, 2)},
             "frames": len(S), "tol": tol, **res}
+
+
+def learned_records(args, W, frames):
+    c1 = W.lgs3_10x10()
+    return {
+        "learned_74x74": learned_record(
+            lambda: W.lgs6_74x74(pad_L=args.pad), lambda i: W.lgs6_74x74_family(i, pad_L=args.pad), 8,
+            args.learned_steps, frames[:3], args.tol,
+            "learned preconditioner (P = K^T K, 4-layer masked CNN, 32 channels) trained on 8 systems of the "
+            "74x74 / 6 LGS geometry with random r0 and layer weights, then flexible CG on 3 frames of the "
+            f"nominal system to rel. residual {args.tol:g}, against plain CG"),
+        "learned_10x10": learned_record(
+            W.lgs3_10x10, W.lgs3_10x10_family, 8, args.learned_steps,
+            W.turbulent_slopes(c1, frames=5).astype(np.float32), 1e-10,
+            "the same at 10x10 / 3 LGS (8 training systems with random r0 and layer weights), 5 frames of "
+            "lgs3_10x10 to rel. residual 1e-10"),
+    }
 
 
 def persistent_roofline(infos, wl, info, prec, pc, pad):
@@ -371,6 +457,12 @@ def main():
         return
     wl = W.lgs6_74x74(pad_L=args.pad)
     frames = W.turbulent_slopes(wl, frames=args.frames).astype(np.float32)
+    if args.learned_only:
+        res = learned_records(args, W, frames)
+        torch.cuda.synchronize()
+        close_all()
+        print(json.dumps(res), flush=True)
+        return
 
     ctx = Context(0)
     torch.cuda.synchronize()
@@ -464,20 +556,11 @@ def main():
             if sv == SOLVER_PERSISTENT and mth == CG:
                 side[name]["roofline"] = persistent_roofline(ii, wl, info, p, vpc, args.pad)
         out["variants"] = side
+    if not args.no_multi:
+        out["multi_rhs"] = multi_rhs(args, ctx, frames, 0)
+        out["multi_rhs_pcg"] = multi_rhs(args, ctx, frames, 1)
     if not args.no_learned:
-        c2f = frames[:3]
-        out["learned_74x74"] = learned_record(
-            lambda: W.lgs6_74x74(pad_L=args.pad), lambda i: W.lgs6_74x74_family(i, pad_L=args.pad), 8,
-            args.learned_steps, c2f, args.tol,
-            "learned preconditioner (P = K^T K, 4-layer masked CNN, 32 channels) trained on 8 systems of the "
-            "74x74 / 6 LGS geometry with random r0 and layer weights, then flexible CG on 3 frames of the "
-            f"nominal system to rel. residual {args.tol:g}, against plain CG")
-        c1 = W.lgs3_10x10()
-        out["learned_10x10"] = learned_record(
-            W.lgs3_10x10, W.lgs3_10x10_family, 8, args.learned_steps,
-            W.turbulent_slopes(c1, frames=5).astype(np.float32), 1e-10,
-            "the same at 10x10 / 3 LGS (8 training systems with random r0 and layer weights), 5 frames of "
-            "lgs3_10x10 to rel. residual 1e-10")
+        out.update(learned_records(args, W, frames))
     if args.batch > 0:
         bctx, bkeep, bsetup = batch_systems(args)
         out["batch_matvec"] = batch_matvec(args, bctx, bsetup)
@@ -486,6 +569,10 @@ def main():
         out["batch_solve"] = batch_solve(args, bctx, frames, 0)
         out["batch_solve_pcg"] = batch_solve(args, bctx, frames, 1)
         out["batch_solve_pcg_f16"] = batch_solve(args, bctx, frames, 1, precision=2)
+        for c in bctx + bkeep:
+            c.close()
+    if args.uneven > 0:
+        out.update(batch_uneven(args))
     torch.cuda.synchronize()
     close_all()
     if not args.no_cpu:

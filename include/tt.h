@@ -232,6 +232,18 @@ typedef struct {
 tt_status tt_create(tt_ctx** out, int device, void* stream);
 tt_status tt_destroy(tt_ctx* ctx);
 
+/* A view of a configured context: it shares the base's system (spectra, index
+ * maps, noise, twiddles, and the block-circulant preconditioner spectra if
+ * already built) and owns its stream (`stream`, a hipStream_t, NULL = the null
+ * stream), solver vectors and transform buffers.  Several frames of one system
+ * solved together (tt_solve_batch over the base and its views with
+ * TT_SOLVER_BATCHED: multiple right-hand sides, e.g. the columns of an offline
+ * reconstructor) then stream one copy of the spectra.  A view has no target
+ * (its solves take d_phi = NULL) and cannot set a system, noise blocks or mode
+ * removal; the base can do none of these, and tt_destroy refuses it, while it
+ * has live views.  Views of views are refused. */
+tt_status tt_create_view(tt_ctx** out, tt_ctx* base, void* stream);
+
 /* Valid-subaperture rule of the aperture masks (§2.F): subaperture (i, j) of
  * the n x n grid laid over [-D/2, D/2]^2 is valid when at least half of its
  * area lies inside the annular pupil of outer diameter D and inner diameter

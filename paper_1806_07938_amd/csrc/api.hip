@@ -56,6 +56,76 @@ tt_status create_impl(tt_ctx** out, int device, void* stream) {
     return TT_OK;
 }
 
+// A context sharing the system of `base` (spectra, maps, noise, twiddles, and
+// the block-circulant preconditioner spectra if built) with its own stream,
+// solver vectors and transform buffers.
+tt_status view_impl(tt_ctx** out, tt_ctx* base, void* stream) {
+    TT_REQUIRE(out && base, "NULL argument");
+    *out = nullptr;
+    if (!base->ready) {
+        tt_set_error("tt_create_view: the base context has no system");
+        return TT_NOT_READY;
+    }
+    TT_REQUIRE(!base->view_of, "the base is itself a view (take a view of its base)");
+    TT_REQUIRE(!base->modes, "mode removal is not supported on views");
+    TT_CHECK(use_device(base->device));
+    tt_ctx* c = new tt_ctx();
+    c->device = base->device;
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+    c->num_cu = base->num_cu;
+    c->n = base->n;
+    c->G = base->G;
+    c->C = base->C;
+    c->L = base->L;
+    c->Lh = base->Lh;
+    c->n_vs = base->n_vs;
+    c->n_slopes = base->n_slopes;
+    c->n_layer = base->n_layer;
+    c->model = base->model;
+    c->d = base->d;
+    c->h_lgs = base->h_lgs;
+    c->lgs = base->lgs;
+    c->gs = base->gs;
+    c->h = base->h;
+    c->w = base->w;
+    c->r0 = base->r0;
+    c->L0 = base->L0;
+    c->valid = base->valid;
+    c->host_noise = base->host_noise;
+    c->M32.share(base->M32);
+    c->M64.share(base->M64);
+    c->vmap.share(base->vmap);
+    c->vidx.share(base->vidx);
+    c->noise32.share(base->noise32);
+    c->noise64.share(base->noise64);
+    c->has_nxy = base->has_nxy;
+    if (base->has_nxy) {
+        c->nxy32.share(base->nxy32);
+        c->nxy64.share(base->nxy64);
+    }
+    c->tw32.share(base->tw32);
+    c->tw64.share(base->tw64);
+    if (base->pc_ready) {
+        c->Minv32.share(base->Minv32);
+        c->Minv64.share(base->Minv64);
+        c->pc_ready = true;
+    }
+    c->learned = base->learned;
+    const size_t tsz = (size_t)c->Lh * c->C * c->n;
+    tt_status st = TT_OK;
+    if ((st = c->T32.alloc(tsz)) != TT_OK || (st = c->U32.alloc(tsz)) != TT_OK || (st = c->T64.alloc(tsz)) != TT_OK ||
+        (st = c->U64.alloc(tsz)) != TT_OK || (st = cg_alloc(*c)) != TT_OK ||
+        (st = hipStreamSynchronize(c->stream) == hipSuccess ? TT_OK : TT_HIP_ERROR) != TT_OK) {
+        delete c;
+        return st;
+    }
+    c->view_of = base;
+    base->n_views++;
+    c->ready = true;
+    *out = c;
+    return TT_OK;
+}
+
 tt_status generate_impl(tt_ctx* c, const tt_geometry* g, const tt_atmosphere* a, tt_kernels** out) {
     TT_REQUIRE(c && g && a && out, "NULL argument");
     *out = nullptr;
@@ -120,6 +190,8 @@ tt_status set_system_impl(tt_ctx* c, const tt_kernels* k, const double* noise_va
                           const tt_target* target) {
     TT_REQUIRE(c && k, "NULL argument");
     TT_REQUIRE(k->device == c->device, "kernels were generated on another device");
+    TT_REQUIRE(!c->view_of, "a view shares its base's system and cannot set one");
+    TT_REQUIRE(c->n_views == 0, "the context has live views sharing its system (destroy them first)");
     TT_CHECK(use_device(c->device));
     c->ready = false;
     c->proj.on = false;
@@ -330,11 +402,18 @@ tt_status tt_create(tt_ctx** out, int device, void* stream) { TT_GUARD(create_im
 
 tt_status tt_destroy(tt_ctx* ctx) {
     if (!ctx) return TT_OK;
+    if (ctx->n_views > 0) {
+        tt_set_error("tt_destroy: the context still has " + std::to_string(ctx->n_views) + " live views");
+        return TT_INVALID_ARG;
+    }
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->view_of) ctx->view_of->n_views--;
     delete ctx;
     return TT_OK;
 }
+
+tt_status tt_create_view(tt_ctx** out, tt_ctx* base, void* stream) { TT_GUARD(view_impl(out, base, stream)); }
 
 tt_status tt_generate_kernels(tt_ctx* ctx, const tt_geometry* geom, const tt_atmosphere* atm, tt_kernels** out) {
     TT_GUARD(generate_impl(ctx, geom, atm, out));
@@ -366,6 +445,7 @@ tt_status tt_set_noise_xy(tt_ctx* c, const double* cov_xy) {
         tt_set_error("tt_set_noise_xy: no system set");
         return TT_NOT_READY;
     }
+    TT_REQUIRE(!c->view_of && c->n_views == 0, "the noise of a system shared with views cannot change");
     TT_CHECK(use_device(c->device));
     if (!cov_xy) {
         c->has_nxy = false;
@@ -392,6 +472,7 @@ tt_status tt_set_mode_removal(tt_ctx* c, int on) {
         tt_set_error("tt_set_mode_removal: no system set");
         return TT_NOT_READY;
     }
+    TT_REQUIRE(!c->view_of && c->n_views == 0, "mode removal is not supported with views");
     TT_CHECK(use_device(c->device));
     if (!on) {
         c->modes = false;

@@ -45,14 +45,22 @@ template <typename T>
 struct DevBuf {
     T* p = nullptr;
     size_t n = 0;
+    bool own = true;   // false: a view of another buffer (a context view shares its base's system)
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && own) (void)hipFree(p);
         p = nullptr;
         n = 0;
+        own = true;
+    }
+    void share(const DevBuf& o) {
+        release();
+        p = o.p;
+        n = o.n;
+        own = false;
     }
     tt_status alloc(size_t count) {
         release();
@@ -180,6 +188,8 @@ struct tt_ctx {
     std::vector<double> host_noise;
 
     tt_learned* learned = nullptr;      // attached learned preconditioner (not owned)
+    tt_ctx* view_of = nullptr;          // a view: the context whose system it shares
+    int n_views = 0;                    // live views of this context
     DevBuf<float> bu_old32;             // flexible PCG: the previous u = P r
     Projection proj;
     // copy of the geometry the system was built from (for the projection)

@@ -33,7 +33,7 @@ MODEL_HUDGIN, MODEL_FRIED = 0, 1
 EXPORTED = (
     "tt_create", "tt_destroy", "tt_generate_kernels", "tt_kernels_destroy", "tt_kernels_copy",
     "tt_set_system", "tt_set_noise_xy", "tt_set_mode_removal", "tt_get_system_info", "tt_matvec", "tt_matvec_f64", "tt_matvec_batch",
-    "tt_matvec_noalloc", "tt_matvec_batch_prec", "tt_learned_create", "tt_learned_destroy", "tt_learned_weight_count",
+    "tt_matvec_noalloc", "tt_matvec_batch_prec", "tt_create_view", "tt_learned_create", "tt_learned_destroy", "tt_learned_weight_count",
     "tt_learned_get_weights", "tt_learned_set_weights", "tt_learned_apply", "tt_learned_train_step",
     "tt_learned_train", "tt_set_learned",
     "tt_solve_frame", "tt_solve_batch", "tt_project", "tt_status_string", "tt_last_error", "tt_pupil_mask",
@@ -99,7 +99,8 @@ _exit_hook = False
 
 
 def _close_open_handles():
-    for h in list(_open_handles):
+    # views before the contexts they share a system with
+    for h in sorted(list(_open_handles), key=lambda o: 0 if getattr(o, "_base", None) is not None else 1):
         try:
             h.close()
         except Exception:
@@ -130,6 +131,7 @@ def load(path: str = LIB_PATH):
     vp = C.c_void_p
     lib.tt_create.argtypes = [C.POINTER(vp), C.c_int, vp]
     lib.tt_destroy.argtypes = [vp]
+    lib.tt_create_view.argtypes = [C.POINTER(vp), vp, vp]
     lib.tt_generate_kernels.argtypes = [vp, C.POINTER(_Geometry), C.POINTER(_Atmosphere), C.POINTER(vp)]
     lib.tt_kernels_destroy.argtypes = [vp]
     lib.tt_kernels_copy.argtypes = [vp, C.POINTER(C.c_double), C.c_size_t]
@@ -358,6 +360,21 @@ class Context:
         return zeta, phi, SolveInfo(inf.iterations, inf.refinements, inf.status, inf.rel_residual,
                                     inf.recursive_residual, inf.kernel_ms, inf.kernel_launches, inf.fallback)
 
+    def view(self, stream=None):
+        """tt_create_view: a context sharing this one's system, with its own
+        stream (default: torch's current stream) and solver buffers."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        h = C.c_void_p()
+        _check(load().tt_create_view(C.byref(h), self._h, C.c_void_p(sp)))
+        v = Context.__new__(Context)
+        v._h, v.device, v._keep, v._stream_obj, v._base = h, self.device, [], stream, self
+        v.info = dict(self.info, n_vphi=0, n_prime=0, proj_pad_L=0)
+        _track(v)
+        return v
+
     def set_learned(self, net):
         """Attach (or with None detach) the network of TT_PRECOND_LEARNED solves."""
         _check(load().tt_set_learned(self._h, net._h if net is not None else None))
@@ -373,8 +390,9 @@ class Context:
 
     def close(self):
         if getattr(self, "_h", None):
-            load().tt_destroy(self._h)
+            _check(load().tt_destroy(self._h))
             self._h = None
+            self._base = None
 
     def __del__(self, _finalizing=sys.is_finalizing):
         if _finalizing():

@@ -150,3 +150,42 @@ def test_batched_pcg_four_way_split():
     for wl, s, z, inf in zip(wls, S, zs, infos):
         say("batched pcg, four-way split", wl.name, "L", wl.pad_L, "iterations", inf.iterations)
         _check_frame(wl, s.cpu().numpy(), z.cpu().numpy(), 1e-8, inf)
+
+
+def test_views_solve_many_frames_of_one_system():
+    """Several right-hand sides of one system (context views sharing its
+    spectra) solved together by the batched solver: every frame certified by
+    the oracle's dense residual, and equal to the same frame solved alone by
+    the batched solver on the base context (the systems of a lockstep batch
+    do not interact: bitwise equal)."""
+    import torch
+    from oracle.covariance import system_matrix
+    from paper_1806_07938_amd import solve_batch
+    from paper_1806_07938_amd.tt import PRECOND_CIRCULANT, SOLVER_BATCHED, TTError
+    wl = W.lgs3_10x10()
+    base, k = make_system(wl, target=True)
+    views = [base.view() for _ in range(5)]
+    frames = W.turbulent_slopes(wl, seed=77, frames=6).astype(np.float32)
+    dev = torch_dev()
+    S = [torch.tensor(f, device=dev) for f in frames]
+    A = system_matrix(wl)
+    for pc in (0, PRECOND_CIRCULANT):
+        zs, phis, infos, st = solve_batch([base] + views, S, tol=1e-8, solver=SOLVER_BATCHED, preconditioner=pc)
+        assert st == 0 and all(p is None for p in phis)
+        for i, (f, z, inf) in enumerate(zip(frames, zs, infos)):
+            zz = z.cpu().numpy()
+            res = np.linalg.norm(f - A @ zz) / np.linalg.norm(f)
+            say(f"view {i} pc {pc}: {inf.iterations} iterations, oracle residual {res:.2e}")
+            assert inf.status == 0 and res <= 1.01e-8
+            z1, _, inf1 = views[0].solve(S[i], tol=1e-8, solver=SOLVER_BATCHED, preconditioner=pc, project=False) \
+                if i else base.solve(S[i], tol=1e-8, solver=SOLVER_BATCHED, preconditioner=pc, project=False)
+            assert np.array_equal(z1.cpu().numpy(), zz) and inf1.iterations == inf.iterations
+    # the base cannot change or go away while views share its system
+    with pytest.raises(TTError):
+        base.close()
+    with pytest.raises(TTError):
+        base.set_mode_removal(True)
+    for v in views:
+        v.close()
+    base.close()
+    k.close()

@@ -122,3 +122,35 @@ def test_uneven_batched_pcg_half_spectra(uneven, precision):
         say("uneven pcg precision", precision, wl.name, "iterations", inf.iterations, "rel", inf.rel_residual,
             "oracle", res)
         assert inf.status == 0 and inf.rel_residual <= tol and res <= 1.01 * tol
+
+
+def test_uneven_64_system_batch(uneven):
+    """64 uneven systems (uneven_family 0..63: grids 40 / 60 / 74 / 84, 4-8 LGS,
+    10-35 layers) solved together by lockstep plain CG: every frame certified by
+    its FP64 true residual, and the first four (the systems the oracle operators
+    of this module belong to) by the oracle's operator.  Right-hand sides are
+    seeded white noise (the solver's correctness does not depend on their
+    statistics; the benchmark uses measured frames)."""
+    import torch
+    from paper_1806_07938_amd import solve_batch
+    from paper_1806_07938_amd.tt import SOLVER_BATCHED
+    wls4, systems4, ops = uneven
+    dev = torch_dev()
+    wls = wls4 + [W.uneven_family(i) for i in range(4, 64)]
+    systems = systems4 + [make_system(wl, target=False) for wl in wls[4:]]
+    rng = np.random.default_rng(64)
+    S = [rng.standard_normal(wl.n_slopes).astype(np.float32) for wl in wls]
+    tol = 1e-6
+    zs, _, infos, st = solve_batch([c for c, k in systems], [torch.tensor(s, device=dev) for s in S], tol=tol,
+                                   solver=SOLVER_BATCHED)
+    its = [inf.iterations for inf in infos]
+    say(f"64 uneven systems: status {st}, iterations {min(its)}-{max(its)}, max rel residual "
+        f"{max(inf.rel_residual for inf in infos):.2e}")
+    assert st == 0
+    assert all(inf.status == 0 and inf.rel_residual <= tol for inf in infos)
+    for op, s, z in zip(ops, S[:4], zs[:4]):
+        res = np.linalg.norm(s - op(z.cpu().numpy())) / np.linalg.norm(s)
+        assert res <= 1.01 * tol
+    for c, k in systems[4:]:
+        c.close()
+        k.close()
