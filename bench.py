@@ -555,6 +555,30 @@ def main():
                           "converged": all(i.status == 0 and i.rel_residual <= args.tol for i in ii)}
             if sv == SOLVER_PERSISTENT and mth == CG:
                 side[name]["roofline"] = persistent_roofline(ii, wl, info, p, vpc, args.pad)
+        # the 160-point axes of the precision configuration: the same system at
+        # L = 160, plain CG (persistent) and CG preconditioned by the block-circulant
+        # inverse with its spectra stored in FP16 (batched solver, one frame per call)
+        from paper_1806_07938_amd.tt import SOLVER_BATCHED
+        wl160 = W.lgs6_74x74(pad_L=160)
+        c160 = Context(0)
+        k160 = system_from(c160, wl160, target=True)
+        for name, p, sv, vpc in (("f32_persistent_plain_cg_L160", PREC_F32, SOLVER_PERSISTENT, PRECOND_NONE),
+                                 ("f16_spectra_batched_circulant_pcg_L160", PREC_F16, SOLVER_BATCHED,
+                                  PRECOND_CIRCULANT)):
+            allow = (0, TT_NOT_CONVERGED)
+            c160.solve(S[0], tol=args.tol, precision=p, solver=sv, preconditioner=vpc, allow=allow)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ii = [c160.solve(S[k], tol=args.tol, precision=p, solver=sv, preconditioner=vpc, allow=allow)[2]
+                  for k in range(3)]
+            torch.cuda.synchronize()
+            side[name] = {"ms_per_solve": round((time.perf_counter() - t0) * 1e3 / 3, 3),
+                          "iterations_mean": round(float(np.mean([i.iterations for i in ii])), 1),
+                          "status": [int(i.status) for i in ii],
+                          "rel_residual": [float(f"{i.rel_residual:.3e}") for i in ii],
+                          "converged": all(i.status == 0 and i.rel_residual <= args.tol for i in ii)}
+        c160.close()
+        k160.close()
         out["variants"] = side
     if not args.no_multi:
         out["multi_rhs"] = multi_rhs(args, ctx, frames, 0)

@@ -183,6 +183,10 @@ typedef struct {
                                      last one (0 -> 1e-3) */
     int preconditioner;           /* tt_preconditioner (0: none) */
     int method;                   /* tt_method (0: CG) */
+    int graph;                    /* TT_SOLVER_BATCHED: nonzero replays each chunk of 16
+                                     lockstep iterations from a captured HIP graph while the
+                                     set of iterating systems is unchanged (same kernels and
+                                     results as launching them one by one, 0) */
 } tt_solve_opts;
 
 typedef struct {
@@ -351,9 +355,27 @@ tt_status tt_matvec_batch(tt_ctx* const* systems, int count, const float* const*
  * transforms in FP32.  The FP16 / BF16 copies are made once per system from the
  * FP32 spectra at the first call that needs them (device memory: half the FP32
  * spectra).  Relative error of the product: the spectra rounding, at most 2^-11
- * (FP16) or 2^-8 (BF16) of each frequency's largest value. */
+ * (FP16) or 2^-8 (BF16) of each frequency's largest value.  split: the
+ * frequency split of the column kernel (1, 2 or 4, see tt_tune_batch; the batch
+ * must admit it), or 0 for the tuned or default one. */
 tt_status tt_matvec_batch_prec(tt_ctx* const* systems, int count, const float* const* d_x, float* const* d_y,
-                               int precision, float* phase_ms);
+                               int precision, int split, float* phase_ms);
+
+/* Autotuner of the batched column kernel.  The column items of the batched
+ * product (op 0) and of the batched block-circulant preconditioner (op 1) each
+ * own one of S classes of frequencies f1 = S k + h of a column; S trades LDS
+ * per item (items resident per compute unit) against the inverse shares
+ * written.  This times one call for each S in {1, 2, 4} that every system of
+ * the batch admits (S divides L, L / 4 >= n / 2 for S = 4, LDS limits), on
+ * seeded vectors with spectra stored in `precision` (TT_PREC_F32 / F16 / BF16),
+ * 2 warm-up and 5 timed calls each, and keeps the fastest S for later
+ * tt_matvec_batch(_prec) calls and batched solves with exactly these systems
+ * in this order (stored in systems[0]).  best_split (may be NULL) receives it;
+ * ms_per_split (3 floats, may be NULL) the mean call time in ms for S = 1, 2, 4
+ * (-1: not admitted).  Synchronous; allocates two vectors per system for the
+ * duration of the call. */
+tt_status tt_tune_batch(tt_ctx* const* systems, int count, int op, int precision, int* best_split,
+                        float* ms_per_split);
 
 /* Solve W_s (Sigma_ss + Sigma_eta) W_s^T zeta = s by CG (§2.G) and,
  * if d_phi != NULL, project phi = W_phi Sigma_{phi_beta s} zeta (§2.E).

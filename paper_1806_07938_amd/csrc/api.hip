@@ -259,6 +259,7 @@ tt_status parse_opts(const tt_ctx* c, const tt_solve_opts* opts, tt_solve_opts& 
     o.refine_drop = 1e-3;
     o.preconditioner = TT_PRECOND_NONE;
     o.method = TT_METHOD_CG;
+    o.graph = 0;
     if (opts) o = *opts;
     TT_REQUIRE(std::isfinite(o.tol) && o.tol >= 0, "tol must be >= 0");
     TT_REQUIRE(o.max_iter >= 0, "max_iter must be >= 0");
@@ -535,9 +536,15 @@ tt_status tt_matvec_batch(tt_ctx* const* systems, int count, const float* const*
     TT_GUARD(matvec_batch(systems, count, d_x, d_y, phase_ms, TT_PREC_F32));
 }
 
+tt_status tt_tune_batch(tt_ctx* const* systems, int count, int op, int precision, int* best_split,
+                        float* ms_per_split) {
+    TT_GUARD(tune_batch(systems, count, op, precision, best_split, ms_per_split));
+}
+
 tt_status tt_matvec_batch_prec(tt_ctx* const* systems, int count, const float* const* d_x, float* const* d_y,
-                               int precision, float* phase_ms) {
-    TT_GUARD(matvec_batch(systems, count, d_x, d_y, phase_ms, precision));
+                               int precision, int split, float* phase_ms) {
+    TT_REQUIRE(split == 0 || split == 1 || split == 2 || split == 4, "split must be 0, 1, 2 or 4");
+    TT_GUARD(batch_apply(systems, count, d_x, d_y, 0, phase_ms, precision, split));
 }
 
 tt_status tt_solve_frame(tt_ctx* ctx, const float* d_s, const double* d_x0, double* d_zeta, float* d_phi,

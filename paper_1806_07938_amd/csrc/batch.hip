@@ -851,8 +851,19 @@ size_t col_work_lds(int G, int L, int S, int pack) {
 // Host side of tt_matvec_batch (see include/tt.h), op 0, and of the batched
 // block-circulant preconditioner u = W_s S2 F^-1 (M_+ + sigma^2)^-1 F S1 W_s^T r,
 // op 1 (spectra built by precond_build; no noise term).
+// Frequency splits S a batch admits: S divides every L, and with S = 4 the
+// folded column length L / 4 must reach n / 2 (one fold).
+bool split_ok(tt_ctx* const* systems, int count, int S) {
+    for (int i = 0; i < count; ++i) {
+        const tt_ctx& c = *systems[i];
+        if (c.L % S) return false;
+        if (S == 4 && 2 * (c.L / 4) < c.n) return false;
+    }
+    return true;
+}
+
 tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x, float* const* d_y, int op,
-                      float* phase_ms, int precision) {
+                      float* phase_ms, int precision, int S_force, HostMirror<unsigned char>* desc) {
     TT_REQUIRE(count >= 0 && count <= 65535, "count must be in [0, 65535]");
     TT_REQUIRE(precision == TT_PREC_F32 || precision == TT_PREC_F16 || precision == TT_PREC_BF16,
                "spectra precision must be TT_PREC_F32, TT_PREC_F16 or TT_PREC_BF16");
@@ -882,6 +893,14 @@ tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x
         if (systems[i]->L % 4) S = std::min(S, 2);
         if (systems[i]->L % 2) S = 1;
     }
+    if (S_force) {
+        TT_REQUIRE(S_force == 1 || S_force == 2 || S_force == 4, "frequency split must be 1, 2 or 4");
+        TT_REQUIRE(split_ok(systems, count, S_force), "frequency split not admitted by the batch");
+        S = S_force;
+    } else if (c0.tuned_S[op] && c0.tuned_for[op].size() == (size_t)count &&
+               std::equal(systems, systems + count, c0.tuned_for[op].begin())) {
+        S = c0.tuned_S[op];   // chosen by tt_tune_batch for this batch
+    }
     size_t work = 0;
     int Lmax = 0, fwd_tiles = 0, inv_tiles = 0;
     for (int i = 0; i < count; ++i) {
@@ -905,11 +924,15 @@ tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x
     int cols = 0;
     for (int i = 0; i < count; ++i) {
         tt_ctx& c = *systems[i];
-        const size_t ucount = (size_t)c.Lh * S * c.C * c.n;
+        // column shares sized for the largest split, so a later call with another
+        // split never moves the buffer a captured launch writes
+        const size_t ucount = (size_t)c.Lh * 4 * c.C * c.n;
         if (c.bU32.n < ucount) TT_CHECK(c.bU32.alloc(ucount));
-        if (half) TT_CHECK(ensure_half(c, op, precision));
-        // the half copies are built on each system's own stream, the kernels run on the first one's
-        if (half && c.stream != c0.stream) TT_HIP(hipStreamSynchronize(c.stream));
+        // the half copies are built once, on each system's own stream; the kernels run on the first one's
+        if (half && c.mh_kind[op] != precision) {
+            TT_CHECK(ensure_half(c, op, precision));
+            if (c.stream != c0.stream) TT_HIP(hipStreamSynchronize(c.stream));
+        }
         d[i] = BSys{d_x[i], d_y[i], c.vmap.p, c.tw32.p, c.T32.p, c.bU32.p, op ? c.Minv32.p : c.M32.p,
                     half ? c.Mh[op].p : nullptr, half ? c.Mhs[op].p : nullptr,
                     op ? nullptr : c.noise32.p, (!op && c.has_nxy) ? c.nxy32.p : nullptr, c.n, c.G, c.L, c.n_vs,
@@ -924,8 +947,9 @@ tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x
         for (int i = 0, k = 0; i < count; ++i)
             for (int f2 = 0; f2 < systems[i]->Lh; ++f2) cs[k++] = i;
     }
-    DevBuf<unsigned char>& db = c0.bdesc[op];
-    std::vector<unsigned char>& dh = c0.bdesc_host[op];
+    HostMirror<unsigned char>& mir = desc ? *desc : c0.bdesc[op];
+    DevBuf<unsigned char>& db = mir.dev;
+    std::vector<unsigned char>& dh = mir.host;
     if (db.n < hb.size()) {
         TT_CHECK(db.alloc(hb.size()));
         dh.clear();
@@ -970,6 +994,68 @@ tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x
         TT_HIP(hipEventSynchronize(c0.bev[3]));
         for (int k = 0; k < 3; ++k) TT_HIP(hipEventElapsedTime(&phase_ms[k], c0.bev[k], c0.bev[k + 1]));
     }
+    return TT_OK;
+}
+
+// Autotuner of the batched column kernel: times the product (op 0) or the
+// block-circulant preconditioner (op 1) of this batch with every frequency
+// split S in {1, 2, 4} the batch admits (LDS limits included) on seeded
+// vectors, 2 warm-up and 5 timed calls each (HIP events, the three phases
+// summed), and keeps the fastest for later calls with exactly these systems in
+// this order.  ms[0..2]: mean call time for S = 1, 2, 4 (-1: not admitted).
+tt_status tune_batch(tt_ctx* const* systems, int count, int op, int precision, int* best_S, float* ms) {
+    TT_REQUIRE(count >= 1 && systems, "NULL or empty batch");
+    TT_REQUIRE(op == 0 || op == 1, "op must be 0 (product) or 1 (preconditioner)");
+    tt_ctx& c0 = *systems[0];
+    TT_HIP(hipSetDevice(c0.device));
+    std::vector<DevBuf<float>> xs(count), ys(count);
+    std::vector<const float*> px(count);
+    std::vector<float*> py(count);
+    for (int i = 0; i < count; ++i) {
+        TT_REQUIRE(systems[i] && systems[i]->ready, "system without a configured system");
+        const size_t n = (size_t)systems[i]->n_slopes;
+        TT_CHECK(xs[i].alloc(n));
+        TT_CHECK(ys[i].alloc(n));
+        std::vector<float> h(n);
+        uint32_t st = 0x9E3779B9u ^ (uint32_t)i;
+        for (auto& v : h) {   // xorshift32, uniform in [-1, 1)
+            st ^= st << 13;
+            st ^= st >> 17;
+            st ^= st << 5;
+            v = (float)((double)st / 2147483648.0 - 1.0);
+        }
+        TT_HIP(hipMemcpy(xs[i].p, h.data(), n * sizeof(float), hipMemcpyHostToDevice));
+        px[i] = xs[i].p;
+        py[i] = ys[i].p;
+    }
+    const int cand[3] = {1, 2, 4};
+    int best = 0;
+    float best_ms = 0.0f;
+    for (int k = 0; k < 3; ++k) {
+        float t = -1.0f;
+        if (split_ok(systems, count, cand[k])) {
+            float ph[3];
+            tt_status s = TT_OK;
+            for (int r = 0; r < 2 && s == TT_OK; ++r)
+                s = batch_apply(systems, count, px.data(), py.data(), op, nullptr, precision, cand[k]);
+            double sum = 0.0;
+            for (int r = 0; r < 5 && s == TT_OK; ++r) {
+                s = batch_apply(systems, count, px.data(), py.data(), op, ph, precision, cand[k]);
+                sum += (double)ph[0] + ph[1] + ph[2];
+            }
+            if (s == TT_OK) t = (float)(sum / 5.0);
+            else if (s != TT_INVALID_ARG) return s;   // an LDS or size limit only excludes the candidate
+        }
+        if (ms) ms[k] = t;
+        if (t > 0.0f && (best == 0 || t < best_ms)) {
+            best = cand[k];
+            best_ms = t;
+        }
+    }
+    TT_REQUIRE(best > 0, "no frequency split fits this batch");
+    c0.tuned_S[op] = best;
+    c0.tuned_for[op].assign(systems, systems + count);
+    if (best_S) *best_S = best;
     return TT_OK;
 }
 

@@ -25,6 +25,7 @@
 #include "cg_common.h"
 
 #include <algorithm>
+#include <memory>
 
 tt_status cg_replace(tt_ctx& c, const float* s, bool f32, int it, bool* converged, CgScalars* hS);
 
@@ -272,12 +273,19 @@ tt_status plan_precond(PcPlan& plan, tt_ctx* const* act, int na, const std::vect
     return TT_OK;
 }
 
+// desc / tables: the descriptor and pointer tables the launches read (null: the
+// shared defaults; a caller capturing the launches passes its own, one table
+// per run of the learned network)
 tt_status apply_precond(const PcPlan& plan, tt_ctx* const* act, int na, const float* const* pr, float* const* pu,
-                        const BVec* dvec, int starting, hipStream_t st) {
-    if (plan.mode == TT_PRECOND_CIRCULANT) return batch_apply(act, na, pr, pu, 1, nullptr, plan.prec);
-    for (const auto& run : plan.runs)
+                        const BVec* dvec, int starting, hipStream_t st, HostMirror<unsigned char>* desc = nullptr,
+                        std::vector<std::unique_ptr<HostMirror<float*>>>* tables = nullptr) {
+    if (plan.mode == TT_PRECOND_CIRCULANT) return batch_apply(act, na, pr, pu, 1, nullptr, plan.prec, 0, desc);
+    while (tables && tables->size() < plan.runs.size()) tables->emplace_back(new HostMirror<float*>());
+    for (size_t r = 0; r < plan.runs.size(); ++r) {
+        const auto& run = plan.runs[r];
         TT_CHECK(learned_apply_batch(*act[run.first]->learned, *act[run.first], pr + run.first, pu + run.first,
-                                     run.second - run.first, st));
+                                     run.second - run.first, st, tables ? (*tables)[r].get() : nullptr));
+    }
     if (!plan.fb.empty()) {
         hipLaunchKernelGGL(k_bcopy_ru, dim3(VB, (unsigned)plan.fb.size()), dim3(VT), 0, st, dvec, plan.dfb.p,
                            starting);
@@ -422,6 +430,23 @@ tt_status solve_batched(tt_ctx* const* systems, int count, const float* const* d
         }
     }
     const int chunk = 16;
+    // HIP graph of one chunk (opts.graph): captured at the second chunk with an
+    // unchanged set of iterating systems (the first one, launched eagerly, has
+    // uploaded every descriptor and grown every buffer the chunk uses) and
+    // replayed while the set stays the same; the per-chunk descriptors (the
+    // iteration indices) are uploaded before each replay.
+    hipGraphExec_t gexec = nullptr;
+    std::vector<int> g_idx, g_seen;
+    // the tables the chunk's launches read, owned by this solve: the restarts of
+    // single systems between chunks use the shared ones and cannot overwrite them
+    HostMirror<unsigned char> gdesc[2];
+    std::vector<std::unique_ptr<HostMirror<float*>>> gtab;
+    struct GraphGuard {
+        hipGraphExec_t* e;
+        ~GraphGuard() {
+            if (*e) (void)hipGraphExecDestroy(*e);
+        }
+    } gguard{&gexec};
     while (true) {
         gather_active();
         const int na = (int)act.size();
@@ -429,18 +454,86 @@ tt_status solve_batched(tt_ctx* const* systems, int count, const float* const* d
         const hipStream_t st = act[0]->stream;
         TT_HIP(hipMemcpyAsync(dvec.p, hv.data(), sizeof(BVec) * na, hipMemcpyHostToDevice, st));
         if (pc) TT_CHECK(plan_precond(plan, act.data(), na, fb_act, st));
-        for (int k = 0; k < chunk; ++k) {
-            TT_CHECK(batch_apply(act.data(), na, px.data(), qy.data(), 0, nullptr));
-            hipLaunchKernelGGL(k_bdot, dim3(VB, na), dim3(VT), 0, st, dvec.p);
-            if (pc) {
-                hipLaunchKernelGGL(k_bupdate_xr<true>, dim3(VB, na), dim3(VT), 0, st, dvec.p, k);
-                TT_CHECK(apply_precond(plan, act.data(), na, pr.data(), pu.data(), dvec.p, 0, st));
-                hipLaunchKernelGGL(k_bdot_ru, dim3(VB, na), dim3(VT), 0, st, dvec.p, 0);
-                hipLaunchKernelGGL(k_bupdate_p_pc, dim3(VB, na), dim3(VT), 0, st, dvec.p, k, o.max_iter);
+        bool replay = false, capture = false;
+        if (o.graph) {
+            if (gexec && g_idx == idx && fb_act == g_seen) {
+                replay = true;
             } else {
-                hipLaunchKernelGGL(k_bupdate_xr<false>, dim3(VB, na), dim3(VT), 0, st, dvec.p, k);
-                hipLaunchKernelGGL(k_bupdate_p, dim3(VB, na), dim3(VT), 0, st, dvec.p, k, o.max_iter);
+                if (gexec) {
+                    TT_HIP(hipGraphExecDestroy(gexec));
+                    gexec = nullptr;
+                }
+                capture = !g_idx.empty() && g_idx == idx && fb_act == g_seen;
+                g_idx = idx;
+                g_seen = fb_act;
             }
+        }
+        // graph mode: the chunk runs on a capturable stream of the first system
+        // (the context's own stream may be the null stream), ordered after the
+        // uploads above and before the gather below by events
+        hipStream_t run_st = st;
+        struct StreamSwap {
+            tt_ctx* c;
+            hipStream_t orig;
+            ~StreamSwap() {
+                if (c) c->stream = orig;
+            }
+        } swap{nullptr, st};
+        if (o.graph) {
+            tt_ctx& c0 = *act[0];
+            if (!c0.gstream) TT_HIP(hipStreamCreateWithFlags(&c0.gstream, hipStreamNonBlocking));
+            for (auto& e : c0.gev)
+                if (!e) TT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            TT_HIP(hipEventRecord(c0.gev[0], st));
+            TT_HIP(hipStreamWaitEvent(c0.gstream, c0.gev[0], 0));
+            run_st = c0.gstream;
+            swap.c = &c0;
+            c0.stream = run_st;   // batch_apply launches on the first system's stream
+        }
+        if (capture) TT_HIP(hipStreamBeginCapture(run_st, hipStreamCaptureModeRelaxed));
+        // a failure while capturing ends the capture before it is returned
+        struct CaptureGuard {
+            hipStream_t s;
+            bool on;
+            ~CaptureGuard() {
+                if (on) {
+                    hipGraph_t g = nullptr;
+                    if (hipStreamEndCapture(s, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+                }
+            }
+        } cguard{run_st, capture};
+        HostMirror<unsigned char>* d0 = o.graph ? &gdesc[0] : nullptr;
+        HostMirror<unsigned char>* d1 = o.graph ? &gdesc[1] : nullptr;
+        std::vector<std::unique_ptr<HostMirror<float*>>>* tabs = o.graph ? &gtab : nullptr;
+        for (int k = 0; k < chunk && !replay; ++k) {
+            TT_CHECK(batch_apply(act.data(), na, px.data(), qy.data(), 0, nullptr, TT_PREC_F32, 0, d0));
+            hipLaunchKernelGGL(k_bdot, dim3(VB, na), dim3(VT), 0, run_st, dvec.p);
+            if (pc) {
+                hipLaunchKernelGGL(k_bupdate_xr<true>, dim3(VB, na), dim3(VT), 0, run_st, dvec.p, k);
+                TT_CHECK(apply_precond(plan, act.data(), na, pr.data(), pu.data(), dvec.p, 0, run_st, d1, tabs));
+                hipLaunchKernelGGL(k_bdot_ru, dim3(VB, na), dim3(VT), 0, run_st, dvec.p, 0);
+                hipLaunchKernelGGL(k_bupdate_p_pc, dim3(VB, na), dim3(VT), 0, run_st, dvec.p, k, o.max_iter);
+            } else {
+                hipLaunchKernelGGL(k_bupdate_xr<false>, dim3(VB, na), dim3(VT), 0, run_st, dvec.p, k);
+                hipLaunchKernelGGL(k_bupdate_p, dim3(VB, na), dim3(VT), 0, run_st, dvec.p, k, o.max_iter);
+            }
+        }
+        if (capture) {
+            hipGraph_t graph = nullptr;
+            cguard.on = false;
+            TT_HIP(hipStreamEndCapture(run_st, &graph));
+            const hipError_t e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            TT_HIP(e);
+            replay = true;
+        }
+        if (replay) TT_HIP(hipGraphLaunch(gexec, run_st));
+        if (o.graph) {
+            tt_ctx& c0 = *act[0];
+            c0.stream = st;
+            swap.c = nullptr;
+            TT_HIP(hipEventRecord(c0.gev[1], run_st));
+            TT_HIP(hipStreamWaitEvent(st, c0.gev[1], 0));
         }
         hipLaunchKernelGGL(k_bgather, dim3(cdiv(na, 64)), dim3(64), 0, st, dvec.p, na, dS.p);
         TT_HIP(hipGetLastError());

@@ -51,9 +51,10 @@ int rup(int a, int b) { return (a + b - 1) / b * b; }
 // ---------------------------------------------------------------------------
 // convolution: out[b][o][y][x] = sum_{i, ky, kx} W[o][i][ky][kx] in[b][i][y + ky - 1][x + kx - 1]
 // W as a bfloat16 operand [16 MT rows][KP], k = (ky 3 + kx) cinp + i, zero padded.
-// One wave per block: 16 pixels (x0 .. x0 + 15) of row y of map b, all output
-// channels.  The three input rows it reads (with one column of halo on each
-// side) are staged in LDS as hi / lo bfloat16, channel fastest.
+// A block of CR waves covers 16 pixels (x0 .. x0 + 15) of CR consecutive rows
+// of map b, one row per wave, all output channels.  The CR + 2 input rows it
+// reads (one column of halo on each side) are staged once in LDS as hi / lo
+// bfloat16, channel fastest, and so is the weight operand.
 // ---------------------------------------------------------------------------
 struct ConvArgs {
     const float* in;            // [B][cin][n][n]
@@ -65,20 +66,23 @@ struct ConvArgs {
 
 constexpr int CMAXP = 32;      // largest padded channel count
 constexpr int TW = 18;         // tile width: 16 pixels + halo
+constexpr int CR = 4;          // grid rows (waves) per block
+constexpr int KPMAX = 9 * CMAXP;
 
 template <int MT>
-__global__ __launch_bounds__(64) void k_conv(ConvArgs a) {
-    __shared__ __align__(16) unsigned short th[3 * TW * CMAXP];
-    __shared__ __align__(16) unsigned short tl[3 * TW * CMAXP];
-    const int lane = threadIdx.x;
-    const int x0 = blockIdx.x * 16, y = blockIdx.y, b = blockIdx.z;
+__global__ __launch_bounds__(64 * CR) void k_conv(ConvArgs a) {
+    __shared__ __align__(16) unsigned short th[(CR + 2) * TW * CMAXP];
+    __shared__ __align__(16) unsigned short tl[(CR + 2) * TW * CMAXP];
+    __shared__ __align__(16) unsigned short ws[16 * MT * KPMAX];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int x0 = blockIdx.x * 16, y0 = blockIdx.y * CR, b = blockIdx.z;
     const int n = a.n, cinp = a.cinp;
     const float* inb = a.in + (long)b * a.cin * n * n;
-    for (int idx = lane; idx < 3 * TW * cinp; idx += 64) {
+    for (int idx = tid; idx < (CR + 2) * TW * cinp; idx += 64 * CR) {
         const int col = idx % TW;
-        const int r = (idx / TW) % 3;
-        const int c = idx / (3 * TW);
-        const int yy = y - 1 + r, xx = x0 - 1 + col;
+        const int r = (idx / TW) % (CR + 2);
+        const int c = idx / ((CR + 2) * TW);
+        const int yy = y0 - 1 + r, xx = x0 - 1 + col;
         float v = 0.0f;
         if (c < a.cin && yy >= 0 && yy < n && xx >= 0 && xx < n) v = inb[((long)c * n + yy) * n + xx];
         const unsigned short hi = bf16_rne(v);
@@ -86,23 +90,31 @@ __global__ __launch_bounds__(64) void k_conv(ConvArgs a) {
         th[(r * TW + col) * cinp + c] = hi;
         tl[(r * TW + col) * cinp + c] = lo;
     }
+    {
+        const uint4* src = reinterpret_cast<const uint4*>(a.w);
+        uint4* dst = reinterpret_cast<uint4*>(ws);
+        for (int i = tid; i < 16 * MT * a.KP / 8; i += 64 * CR) dst[i] = src[i];
+    }
     __syncthreads();
+    const int y = y0 + wave;
+    if (y >= n) return;
     const int kq = lane >> 4, lc = lane & 15;
     f32x4 acc[MT];
     for (int m = 0; m < MT; ++m) acc[m] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int nk = a.KP / 16;
+#pragma unroll 3
     for (int s = 0; s < nk; ++s) {
         const int k0 = 16 * s + 4 * kq;
         const int tap = k0 / cinp, c0 = k0 - tap * cinp;
         i16x4 bh = {0, 0, 0, 0}, bl = {0, 0, 0, 0};
         if (tap < 9) {
             const int ky = tap / 3, kx = tap - 3 * ky;
-            const int o = (ky * TW + lc + kx) * cinp + c0;
+            const int o = ((wave + ky) * TW + lc + kx) * cinp + c0;
             bh = *reinterpret_cast<const i16x4*>(&th[o]);
             bl = *reinterpret_cast<const i16x4*>(&tl[o]);
         }
         for (int m = 0; m < MT; ++m) {
-            const i16x4 av = *reinterpret_cast<const i16x4*>(&a.w[(long)(16 * m + lc) * a.KP + k0]);
+            const i16x4 av = *reinterpret_cast<const i16x4*>(&ws[(16 * m + lc) * a.KP + k0]);
             acc[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bh, acc[m], 0, 0, 0);
             acc[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bl, acc[m], 0, 0, 0);
         }
@@ -562,11 +574,15 @@ tt_status conv(const tt_learned& L, int l, bool adj, const float* in, float* out
         a.cout = L.cin[l];
         a.KP = L.KPa[l];
     }
-    const dim3 grid(cdiv(n, 16), n, B);
+    if (a.KP > KPMAX || a.cinp > CMAXP) {
+        tt_set_error("convolution layer too wide");
+        return TT_INVALID_ARG;
+    }
+    const dim3 grid(cdiv(n, 16), cdiv(n, CR), B);
     if (a.cout <= 16)
-        hipLaunchKernelGGL(k_conv<1>, grid, dim3(64), 0, s, a);
+        hipLaunchKernelGGL(k_conv<1>, grid, dim3(64 * CR), 0, s, a);
     else
-        hipLaunchKernelGGL(k_conv<2>, grid, dim3(64), 0, s, a);
+        hipLaunchKernelGGL(k_conv<2>, grid, dim3(64 * CR), 0, s, a);
     TT_HIP(hipGetLastError());
     return TT_OK;
 }
@@ -580,12 +596,14 @@ static size_t apply_floats(const tt_learned& L, int B, int n) { return (size_t)2
 
 // z_b = K^T K r_b for B vectors of one geometry (vmap / vidx of ctx), on stream s.
 tt_status learned_apply_batch(tt_learned& L, const tt_ctx& c, const float* const* d_r, float* const* d_z, int B,
-                              hipStream_t s) {
+                              hipStream_t s, HostMirror<float*>* table) {
     TT_REQUIRE(c.C == L.C, "the network's channel count differs from the system's 2 n_gs");
     TT_CHECK(grow(L.maps, apply_floats(L, B, c.n)));
-    if (L.ptrs.n < (size_t)(2 * B + 2)) {
-        TT_CHECK(L.ptrs.alloc((size_t)2 * B + 2));
-        L.ptrs_host.clear();
+    DevBuf<float*>& tdev = table ? table->dev : L.ptrs;
+    std::vector<float*>& thost = table ? table->host : L.ptrs_host;
+    if (tdev.n < (size_t)(2 * B + 2)) {
+        TT_CHECK(tdev.alloc((size_t)2 * B + 2));
+        thost.clear();
     }
     const int n = c.n;
     const size_t half = (size_t)B * std::max(L.C, L.H) * n * n;
@@ -596,12 +614,12 @@ tt_status learned_apply_batch(tt_learned& L, const tt_ctx& c, const float* const
         hp[b] = const_cast<float*>(d_r[b]);
         hp[B + b] = d_z[b];
     }
-    if (hp != L.ptrs_host) {
-        L.ptrs_host = hp;
-        TT_HIP(hipMemcpyAsync(L.ptrs.p, L.ptrs_host.data(), sizeof(float*) * 2 * B, hipMemcpyHostToDevice, s));
+    if (hp != thost) {
+        thost = hp;
+        TT_HIP(hipMemcpyAsync(tdev.p, thost.data(), sizeof(float*) * 2 * B, hipMemcpyHostToDevice, s));
     }
     const unsigned gx = std::min<unsigned>(cdiv((size_t)c.C * n * n, 256), 1024);
-    hipLaunchKernelGGL(k_scatter, dim3(gx, B), dim3(256), 0, s, L.ptrs.p, c.vmap.p, m0, c.C, n, c.n_vs);
+    hipLaunchKernelGGL(k_scatter, dim3(gx, B), dim3(256), 0, s, tdev.p, c.vmap.p, m0, c.C, n, c.n_vs);
     TT_HIP(hipGetLastError());
     TT_CHECK(conv(L, 0, false, m0, m1, B, n, nullptr, s));
     TT_CHECK(conv(L, 1, false, m1, m0, B, n, nullptr, s));
@@ -611,7 +629,7 @@ tt_status learned_apply_batch(tt_learned& L, const tt_ctx& c, const float* const
     TT_CHECK(conv(L, 2, true, m1, m0, B, n, nullptr, s));
     TT_CHECK(conv(L, 1, true, m0, m1, B, n, nullptr, s));
     TT_CHECK(conv(L, 0, true, m1, m0, B, n, nullptr, s));
-    hipLaunchKernelGGL(k_gather, dim3(gx, B), dim3(256), 0, s, m0, c.vidx.p, L.ptrs.p + B, c.C, n, c.n_vs);
+    hipLaunchKernelGGL(k_gather, dim3(gx, B), dim3(256), 0, s, m0, c.vidx.p, tdev.p + B, c.C, n, c.n_vs);
     TT_HIP(hipGetLastError());
     return TT_OK;
 }

@@ -81,6 +81,16 @@ struct DevBuf {
     }
 };
 
+// Device copy of a host table that a launch reads (descriptors, pointer
+// tables), re-uploaded only when the host table changes.  A caller that replays
+// captured launches keeps its own: another call with different contents then
+// cannot overwrite (or reallocate) what the captured launches read.
+template <typename T>
+struct HostMirror {
+    DevBuf<T> dev;
+    std::vector<T> host;
+};
+
 // ---------------------------------------------------------------------------
 // complex helpers
 // ---------------------------------------------------------------------------
@@ -171,14 +181,18 @@ struct tt_ctx {
     int tile_S = 0, tile_elem = 0;      // split and element size the tiles were built for
     int tile_mf = -1;                   // column-transform mode the fragments were built for
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipStream_t gstream = nullptr;      // batched solver's graph chunks (a capturable stream), made on first use
+    hipEvent_t gev[2] = {nullptr, nullptr};
     DevBuf<c32> bU32;                   // batched product: column shares [Lh][S][C][n]
     DevBuf<float> bu32;                 // batched preconditioned CG: u = P r
-    DevBuf<unsigned char> bdesc[2];     // batched product / preconditioner: per-system descriptors
-    std::vector<unsigned char> bdesc_host[2];   // (kept by the first context of a call)
+    HostMirror<unsigned char> bdesc[2]; // batched product / preconditioner: per-system descriptors
+                                        // (kept by the first context of a call)
     hipEvent_t bev[4] = {nullptr, nullptr, nullptr, nullptr};   // batched product phase timing
     DevBuf<unsigned short> Mh[2];       // batched operators: slope / preconditioner spectra in FP16 or BF16
     DevBuf<float> Mhs[2];               // their per-frequency factors [Lh][L]
     int mh_kind[2] = {0, 0};            // tt_precision the half copies hold (0: none)
+    int tuned_S[2] = {0, 0};            // batched product / preconditioner: frequency split chosen by
+    std::vector<const tt_ctx*> tuned_for[2];   // tt_tune_batch for this exact batch (this context first)
     DevBuf<float> Minv32;               // circulant preconditioner spectra [Lh][L][C^2] (general Hermitian packing)
     DevBuf<double> Minv64;
     bool pc_ready = false;              // Minv built for the current system
@@ -203,8 +217,9 @@ struct tt_ctx {
     tt_ctx(const tt_ctx&) = delete;
     tt_ctx& operator=(const tt_ctx&) = delete;
     ~tt_ctx() {
-        for (hipEvent_t e : {ev0, ev1, bev[0], bev[1], bev[2], bev[3]})
+        for (hipEvent_t e : {ev0, ev1, bev[0], bev[1], bev[2], bev[3], gev[0], gev[1]})
             if (e) (void)hipEventDestroy(e);
+        if (gstream) (void)hipStreamDestroy(gstream);
     }
 };
 
@@ -229,8 +244,11 @@ tt_status matvec_f64(tt_ctx& c, const double* x, double* y, double* part);
 tt_status matvec_batch(tt_ctx* const* systems, int count, const float* const* d_x, float* const* d_y,
                        float* phase_ms, int precision);
 tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x, float* const* d_y, int op,
-                      float* phase_ms, int precision = TT_PREC_F32);   // op 0: the product, op 1: the block-circulant
-                                                                       // preconditioner; spectra storage precision
+                      float* phase_ms, int precision = TT_PREC_F32,   // op 0: the product, op 1: the block-circulant
+                      int S_force = 0,                                // preconditioner; spectra storage precision;
+                      HostMirror<unsigned char>* desc = nullptr);     // frequency split (0: tuned or default);
+                                                                      // descriptor table (null: the first system's)
+tt_status tune_batch(tt_ctx* const* systems, int count, int op, int precision, int* best_S, float* ms);
 
 // cg.hip
 tt_status cg_alloc(tt_ctx& c);
@@ -259,7 +277,7 @@ tt_status projection_apply(tt_ctx& c, const double* zeta, float* phi);
 
 // learned.hip: the learned preconditioner P = K^T K
 tt_status learned_apply_batch(tt_learned& L, const tt_ctx& c, const float* const* d_r, float* const* d_z, int B,
-                              hipStream_t s);
+                              hipStream_t s, HostMirror<float*>* table = nullptr);   // null: the network's table
 int learned_channels(const tt_learned* L);
 
 // noalloc.hip: device scratch of tt_matvec_noalloc (address looked up once per device)

@@ -33,7 +33,7 @@ MODEL_HUDGIN, MODEL_FRIED = 0, 1
 EXPORTED = (
     "tt_create", "tt_destroy", "tt_generate_kernels", "tt_kernels_destroy", "tt_kernels_copy",
     "tt_set_system", "tt_set_noise_xy", "tt_set_mode_removal", "tt_get_system_info", "tt_matvec", "tt_matvec_f64", "tt_matvec_batch",
-    "tt_matvec_noalloc", "tt_matvec_batch_prec", "tt_create_view", "tt_learned_create", "tt_learned_destroy", "tt_learned_weight_count",
+    "tt_matvec_noalloc", "tt_matvec_batch_prec", "tt_create_view", "tt_tune_batch", "tt_learned_create", "tt_learned_destroy", "tt_learned_weight_count",
     "tt_learned_get_weights", "tt_learned_set_weights", "tt_learned_apply", "tt_learned_train_step",
     "tt_learned_train", "tt_set_learned",
     "tt_solve_frame", "tt_solve_batch", "tt_project", "tt_status_string", "tt_last_error", "tt_pupil_mask",
@@ -63,7 +63,8 @@ class _Target(C.Structure):
 
 class _SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("precision", C.c_int), ("solver", C.c_int),
-                ("refine_drop", C.c_double), ("preconditioner", C.c_int), ("method", C.c_int)]
+                ("refine_drop", C.c_double), ("preconditioner", C.c_int), ("method", C.c_int),
+                ("graph", C.c_int)]
 
 
 class _SolveInfo(C.Structure):
@@ -132,6 +133,7 @@ def load(path: str = LIB_PATH):
     lib.tt_create.argtypes = [C.POINTER(vp), C.c_int, vp]
     lib.tt_destroy.argtypes = [vp]
     lib.tt_create_view.argtypes = [C.POINTER(vp), vp, vp]
+    lib.tt_tune_batch.argtypes = [C.POINTER(vp), C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_float)]
     lib.tt_generate_kernels.argtypes = [vp, C.POINTER(_Geometry), C.POINTER(_Atmosphere), C.POINTER(vp)]
     lib.tt_kernels_destroy.argtypes = [vp]
     lib.tt_kernels_copy.argtypes = [vp, C.POINTER(C.c_double), C.c_size_t]
@@ -142,7 +144,7 @@ def load(path: str = LIB_PATH):
     lib.tt_matvec.argtypes = [vp, vp, vp]
     lib.tt_matvec_f64.argtypes = [vp, vp, vp]
     lib.tt_matvec_noalloc.argtypes = [vp, vp, vp]
-    lib.tt_matvec_batch_prec.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(vp), C.POINTER(vp), C.c_int,
+    lib.tt_matvec_batch_prec.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(vp), C.POINTER(vp), C.c_int, C.c_int,
                                          C.POINTER(C.c_float)]
     lib.tt_learned_create.argtypes = [C.POINTER(vp), C.c_int, C.c_int, C.c_int, C.c_ulonglong]
     lib.tt_learned_destroy.argtypes = [vp]
@@ -337,7 +339,7 @@ class Context:
     def solve(self, s, x0=None, zeta=None, phi=None, project: bool = True, tol: float = 1e-6,
               max_iter: int = 20000, precision: int = PREC_F32, solver: int = SOLVER_PERSISTENT,
               refine_drop: float = 1e-3, preconditioner: int = PRECOND_NONE, method: int = METHOD_CG,
-              allow=(TT_OK,)):
+              allow=(TT_OK,), graph: bool = False):
         """Solve for zeta (float64) and, if a target is set and project, phi (float32)."""
         import torch
         n = self.info["n_slopes"]
@@ -351,7 +353,7 @@ class Context:
         else:
             phi = None
         opts = _SolveOpts(float(tol), int(max_iter), int(precision), int(solver), float(refine_drop),
-                          int(preconditioner), int(method))
+                          int(preconditioner), int(method), 1 if graph else 0)
         inf = _SolveInfo()
         px0 = _dptr(x0, torch.float64, n) if x0 is not None else None
         st = load().tt_solve_frame(self._h, _dptr(s, torch.float32, n), px0, _dptr(zeta, torch.float64, n),
@@ -500,7 +502,7 @@ def system_from(ctx: Context, wl, target: bool = True, pad_L: Optional[int] = No
     return k
 
 
-def matvec_batch(contexts, xs, ys=None, timing: bool = False, precision: int = PREC_F32):
+def matvec_batch(contexts, xs, ys=None, timing: bool = False, precision: int = PREC_F32, split: int = 0):
     """tt_matvec_batch: ys[i] = A_i xs[i] (device float32 vectors) for every
     context in one call on the stream of contexts[0] (tt_matvec_batch_prec with
     the spectra in FP16 / BF16 storage for those precisions).  With timing=True
@@ -515,16 +517,27 @@ def matvec_batch(contexts, xs, ys=None, timing: bool = False, precision: int = P
     xp = arr(*[_dptr(x, torch.float32, c.info["n_slopes"]) for c, x in zip(contexts, xs)])
     yp = arr(*[_dptr(y, torch.float32, c.info["n_slopes"]) for c, y in zip(contexts, ys)])
     ms = (C.c_float * 3)()
-    if precision == PREC_F32:
+    if precision == PREC_F32 and not split:
         _check(load().tt_matvec_batch(hs, m, xp, yp, ms if timing else None))
     else:
-        _check(load().tt_matvec_batch_prec(hs, m, xp, yp, int(precision), ms if timing else None))
+        _check(load().tt_matvec_batch_prec(hs, m, xp, yp, int(precision), int(split), ms if timing else None))
     return (ys, [float(v) for v in ms]) if timing else ys
+
+
+def tune_batch(contexts, op: int = 0, precision: int = PREC_F32):
+    """tt_tune_batch: choose the batched column kernel's frequency split for this
+    batch; returns (best split, {split: mean ms per call or None})."""
+    m = len(contexts)
+    hs = (C.c_void_p * m)(*[c._h for c in contexts])
+    best = C.c_int()
+    ms = (C.c_float * 3)()
+    _check(load().tt_tune_batch(hs, m, int(op), int(precision), C.byref(best), ms))
+    return best.value, {s: (float(v) if v > 0 else None) for s, v in zip((1, 2, 4), ms)}
 
 
 def solve_batch(contexts, slopes, tol: float = 1e-6, max_iter: int = 20000, precision: int = PREC_F32,
                 solver: int = SOLVER_PERSISTENT, refine_drop: float = 1e-3, preconditioner: int = PRECOND_NONE,
-                method: int = METHOD_CG, allow=(TT_OK,)):
+                method: int = METHOD_CG, allow=(TT_OK,), graph: bool = False):
     """tt_solve_batch: frame i (device float32 slopes) on contexts[i]; returns
     (zetas, phis, infos, status).  phis[i] is None without a target."""
     import torch
@@ -547,7 +560,7 @@ def solve_batch(contexts, slopes, tol: float = 1e-6, max_iter: int = 20000, prec
     arr = C.c_void_p * max(m, 1)
     hs = arr(*[c._h for c in contexts])
     opts = _SolveOpts(float(tol), int(max_iter), int(precision), int(solver), float(refine_drop),
-                      int(preconditioner), int(method))
+                      int(preconditioner), int(method), 1 if graph else 0)
     infos = (_SolveInfo * max(m, 1))()
     use_phi = all(p is not None for p in pp) and m > 0
     st = load().tt_solve_batch(hs, m, arr(*sp), None, arr(*zp), arr(*pp) if use_phi else None, C.byref(opts), infos)

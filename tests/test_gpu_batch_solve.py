@@ -189,3 +189,37 @@ def test_views_solve_many_frames_of_one_system():
         v.close()
     base.close()
     k.close()
+
+
+@pytest.mark.parametrize("pc", [0, 1, 2], ids=["cg", "circulant", "learned"])
+def test_graph_replayed_chunks_equal_eager_launches(pc):
+    """opts.graph: the lockstep chunks replayed from a captured HIP graph give
+    bitwise the results of launching the same kernels one by one (many replays
+    per solve, with the solver's own synchronisations between them), for plain
+    CG, the block-circulant PCG and flexible CG with a learned network."""
+    import torch
+    from paper_1806_07938_amd import Learned, solve_batch
+    from paper_1806_07938_amd.tt import SOLVER_BATCHED
+    wls = [W.lgs3_10x10(), W.lgs3_10x10_family(0), W.lgs3_10x10_family(1)]
+    systems = [make_system(wl, target=False) for wl in wls]
+    ctxs = [c for c, k in systems]
+    net = None
+    if pc == 2:
+        net = Learned(3, 32, seed=5)
+        net.train(ctxs, n_pairs=2000, steps=200, batch=8, lr=3e-3)
+        for c in ctxs:
+            c.set_learned(net)
+    dev = torch_dev()
+    S = [torch.tensor(W.turbulent_slopes(wl, seed=9)[0].astype(np.float32), device=dev) for wl in wls]
+    ze, _, ie, st_e = solve_batch(ctxs, S, tol=1e-9, solver=SOLVER_BATCHED, preconditioner=pc)
+    zg, _, ig, st_g = solve_batch(ctxs, S, tol=1e-9, solver=SOLVER_BATCHED, preconditioner=pc, graph=True)
+    assert st_e == st_g == 0
+    for a, b, x, y in zip(ze, zg, ie, ig):
+        say(f"pc {pc}: eager {x.iterations} iterations, graph {y.iterations}")
+        assert x.iterations == y.iterations and x.iterations > 3 * 16
+        assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+    for c, k in systems:
+        c.close()
+        k.close()
+    if net is not None:
+        net.close()

@@ -154,3 +154,37 @@ def test_uneven_64_system_batch(uneven):
     for c, k in systems[4:]:
         c.close()
         k.close()
+
+
+@pytest.mark.parametrize("split", [1, 2, 4])
+def test_uneven_batched_product_every_split(uneven, split):
+    """The column kernel with each frequency split (S = 1: whole columns, 2, 4:
+    folded columns, L / 4 < n for some systems) against the oracle operators."""
+    import torch
+    from paper_1806_07938_amd import matvec_batch
+    wls, systems, ops = uneven
+    dev = torch_dev()
+    rng = np.random.default_rng(31 + split)
+    xs = [rng.standard_normal(wl.n_slopes).astype(np.float32) for wl in wls]
+    ys = matvec_batch([c for c, k in systems], [torch.tensor(x, device=dev) for x in xs], split=split)
+    for wl, op, x, y in zip(wls, ops, xs, ys):
+        err = rel_maxabs(y.cpu().numpy(), op(x.astype(np.float64)))
+        say(f"split {split} {wl.name}: rel max-abs {err:.2e}")
+        assert err < 3e-6, wl.name
+
+
+def test_tuned_split_is_used_and_exact(uneven):
+    import torch
+    from paper_1806_07938_amd import matvec_batch
+    from paper_1806_07938_amd.tt import tune_batch
+    wls, systems, ops = uneven
+    ctxs = [c for c, k in systems]
+    best, ms = tune_batch(ctxs, op=0)
+    say(f"tuned split {best}, ms per split {ms}")
+    assert best in (1, 2, 4) and ms[best] is not None and ms[best] == min(v for v in ms.values() if v)
+    dev = torch_dev()
+    rng = np.random.default_rng(41)
+    xs = [rng.standard_normal(wl.n_slopes).astype(np.float32) for wl in wls]
+    ys = matvec_batch(ctxs, [torch.tensor(x, device=dev) for x in xs])
+    for op, x, y in zip(ops, xs, ys):
+        assert rel_maxabs(y.cpu().numpy(), op(x.astype(np.float64))) < 3e-6
