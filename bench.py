@@ -177,7 +177,8 @@ def batch_uneven(args):
     grids = sorted({c.info["n"] for c in ctxs})
     label = (f"{args.uneven} uneven systems (grids {'/'.join(map(str, grids))}, 4-8 LGS, 10-35 layers, noise "
              "0.01-0.5 rad^2, r0 0.10-0.25 m, L = 128 / 256)")
-    out = {"batch_matvec_uneven": batch_matvec(args, ctxs, setup_s, label=label),
+    out = {"batch_tuning_uneven": tune(ctxs, 0),
+           "batch_matvec_uneven": batch_matvec(args, ctxs, setup_s, label=label, split=0),
            "batch_solve_uneven": batch_solve(args, ctxs, frames, 0, label=label)}
     for c in ctxs + keep:
         c.close()
@@ -250,11 +251,11 @@ def batch_solve(args, ctxs, frames, pc, precision=0, label=None):
     torch.cuda.synchronize()
     pc_setup_s = time.perf_counter() - t0
     solve_batch(ctxs, S, tol=args.tol, solver=SOLVER_BATCHED, preconditioner=pc, allow=(0, TT_NOT_CONVERGED),
-                precision=prec)
+                precision=prec, graph=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, _, infos, st = solve_batch(ctxs, S, tol=args.tol, solver=SOLVER_BATCHED, preconditioner=pc,
-                                  allow=(0, TT_NOT_CONVERGED), precision=prec)
+                                  allow=(0, TT_NOT_CONVERGED), precision=prec, graph=True)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3
     it = np.array([i.iterations for i in infos], dtype=np.float64)
@@ -263,7 +264,8 @@ def batch_solve(args, ctxs, frames, pc, precision=0, label=None):
                      + ", one frame each, solved together (TT_SOLVER_BATCHED: "
                      + ("CG preconditioned by the block-circulant inverse" if pc else "plain CG")
                      + ({2: " (its spectra stored in FP16)", 3: " (its spectra stored in BF16)"}.get(prec, ""))
-                     + f" in lockstep, FP32 + FP64 residual replacement) to rel. residual {args.tol:g}"),
+                     + f" in lockstep, chunks replayed from HIP graphs, FP32 + FP64 residual replacement) to rel. "
+                     f"residual {args.tol:g}"),
         "systems": len(ctxs), "ms_per_batch": round(wall, 2), "ms_per_solve": round(wall / len(ctxs), 3),
         "preconditioner_setup_s": round(pc_setup_s, 1) if pc else None,
         "iterations_mean": round(float(it.mean()), 1), "iterations_max": int(it.max()),
@@ -272,7 +274,14 @@ def batch_solve(args, ctxs, frames, pc, precision=0, label=None):
     }
 
 
-def batch_matvec(args, ctxs, setup_s, precision=0, label=None):
+def tune(ctxs, op=0):
+    """tt_tune_batch on the batch: the chosen frequency split and the timing table."""
+    from paper_1806_07938_amd.tt import tune_batch
+    best, ms = tune_batch(ctxs, op=op)
+    return {"split": best, "ms_per_call_by_split": {str(k): (round(v, 4) if v else None) for k, v in ms.items()}}
+
+
+def batch_matvec(args, ctxs, setup_s, precision=0, label=None, split=2):
     """tt_matvec_batch over the systems: spectra of all of them streamed once
     per call.  Roofline of the column kernel: algorithmic bytes = the packed
     spectra of every system (FP32, or FP16 / BF16 storage plus one FP32 factor
@@ -284,12 +293,12 @@ def batch_matvec(args, ctxs, setup_s, precision=0, label=None):
     xs = [torch.tensor(rng.standard_normal(c.info["n_slopes"]).astype(np.float32), device=dev) for c in ctxs]
     ys = [torch.empty_like(x) for x in xs]
     for _ in range(3):
-        matvec_batch(ctxs, xs, ys, precision=precision)
+        matvec_batch(ctxs, xs, ys, precision=precision, split=split)
     torch.cuda.synchronize()
     phases = []
     t0 = time.perf_counter()
     for _ in range(args.batch_steps):
-        phases.append(matvec_batch(ctxs, xs, ys, timing=True, precision=precision)[1])
+        phases.append(matvec_batch(ctxs, xs, ys, timing=True, precision=precision, split=split)[1])
     wall_ms = (time.perf_counter() - t0) * 1e3 / args.batch_steps
     ph = np.array(phases).mean(axis=0)
     spectra = float(sum(c.info["spectra_bytes_f32"] for c in ctxs))
@@ -298,13 +307,16 @@ def batch_matvec(args, ctxs, setup_s, precision=0, label=None):
                             for c in ctxs))
     slopes = float(sum(2 * 4 * c.info["n_slopes"] for c in ctxs))
     col_gbs = spectra / (ph[1] * 1e-3) / 1e9
-    traffic = batch_traffic_record() if (args.batch == 64 and args.batch_pad == 256 and not precision) else None
+    # the recorded counters are those of the frequency split 2
+    traffic = batch_traffic_record() if (args.batch == 64 and args.batch_pad == 256 and not precision and split == 2
+                                         and not label) else None
     pname = {0: "FP32", 2: "FP16 (per-frequency power-of-two scale)", 3: "BF16"}[precision]
     return {
         "workload": ((label or f"{args.batch} distinct 74x74 / 6 LGS / 35-layer systems (seeded layer weights, r0 "
                       f"in [0.10, 0.25] m), L={args.batch_pad}")
                      + f", one product each per call, spectra stored in {pname}, FP32 arithmetic"),
         "systems": len(ctxs), "pad_L": args.batch_pad if not label else "per system", "steps": args.batch_steps,
+        "frequency_split": split or "tuned",
         "ms_per_call_wall": round(wall_ms, 4),
         "ms_per_call_gpu": round(float(ph.sum()), 4),
         "us_per_system_product": round(float(ph.sum()) * 1e3 / len(ctxs), 3),
@@ -351,12 +363,13 @@ def learned_record(wl_of, family, n_systems, steps, frames, tol, label):
     allow = (0, TT_NOT_CONVERGED)
     for name, sv, pcm in (("learned_fpcg", SOLVER_BATCHED, PRECOND_LEARNED), ("batched_plain_cg", SOLVER_BATCHED, 0),
                           ("persistent_plain_cg", SOLVER_PERSISTENT, 0)):
-        ctx.solve(S[0], tol=tol, solver=sv, preconditioner=pcm, allow=allow)
+        gr = sv == SOLVER_BATCHED
+        ctx.solve(S[0], tol=tol, solver=sv, preconditioner=pcm, allow=allow, graph=gr)
         torch.cuda.synchronize()
         ii = []
         t0 = time.perf_counter()
         for s in S:
-            ii.append(ctx.solve(s, tol=tol, solver=sv, preconditioner=pcm, allow=allow)[2])
+            ii.append(ctx.solve(s, tol=tol, solver=sv, preconditioner=pcm, allow=allow, graph=gr)[2])
         torch.cuda.synchronize()
         res[name] = {"ms_per_solve": round((time.perf_counter() - t0) * 1e3 / len(S), 3),
                      "iterations_mean": round(float(np.mean([i.iterations for i in ii])), 1),
@@ -444,9 +457,11 @@ def main():
         del cx, cy
     if args.batch_only:
         bctx, bkeep, bsetup = batch_systems(args)
-        res = {"batch_matvec": batch_matvec(args, bctx, bsetup),
-               "batch_matvec_f16": batch_matvec(args, bctx, bsetup, precision=2),
-               "batch_matvec_bf16": batch_matvec(args, bctx, bsetup, precision=3)}
+        res = {"batch_tuning": tune(bctx, 0)}
+        sp = res["batch_tuning"]["split"]
+        res.update({"batch_matvec": batch_matvec(args, bctx, bsetup, split=sp),
+                    "batch_matvec_f16": batch_matvec(args, bctx, bsetup, precision=2, split=sp),
+                    "batch_matvec_bf16": batch_matvec(args, bctx, bsetup, precision=3, split=sp)})
         if args.batch_solve_frames > 0:
             fr = W.turbulent_slopes(W.lgs6_74x74(), frames=args.batch_solve_frames).astype(np.float32)
             res["batch_solve"] = batch_solve(args, bctx, fr, 0)
@@ -587,9 +602,11 @@ def main():
         out.update(learned_records(args, W, frames))
     if args.batch > 0:
         bctx, bkeep, bsetup = batch_systems(args)
-        out["batch_matvec"] = batch_matvec(args, bctx, bsetup)
-        out["batch_matvec_f16"] = batch_matvec(args, bctx, bsetup, precision=2)
-        out["batch_matvec_bf16"] = batch_matvec(args, bctx, bsetup, precision=3)
+        out["batch_tuning"] = tune(bctx, 0)
+        sp = out["batch_tuning"]["split"]
+        out["batch_matvec"] = batch_matvec(args, bctx, bsetup, split=sp)
+        out["batch_matvec_f16"] = batch_matvec(args, bctx, bsetup, precision=2, split=sp)
+        out["batch_matvec_bf16"] = batch_matvec(args, bctx, bsetup, precision=3, split=sp)
         out["batch_solve"] = batch_solve(args, bctx, frames, 0)
         out["batch_solve_pcg"] = batch_solve(args, bctx, frames, 1)
         out["batch_solve_pcg_f16"] = batch_solve(args, bctx, frames, 1, precision=2)
