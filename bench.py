@@ -327,7 +327,8 @@ def batch_matvec(args, ctxs, setup_s, precision=0, label=None, split=2):
         "roofline": {"bound": "hbm", "achieved": round(col_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(col_gbs / HBM_PEAK_GBS, 4), "traffic": round(traffic) if traffic else None,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
-                     "kernel": "k_bcol (batched column transforms and per-frequency products)",
+                     "kernel": ("k_bcolt (batched column transforms and per-frequency products, spectra slot-major, "
+                                "direct loads to LDS; power-of-two L)"),
                      "avg_launch_ms": round(float(ph[1]), 4)},
         "setup_s": round(setup_s, 1),
     }

@@ -198,6 +198,8 @@ tt_status set_system_impl(tt_ctx* c, const tt_kernels* k, const double* noise_va
     c->tile_S = 0;
     c->pc_ready = false;
     c->mh_kind[0] = c->mh_kind[1] = 0;
+    c->mt_ready[0] = c->mt_ready[1] = false;
+    c->mht_kind[0] = c->mht_kind[1] = 0;
     c->has_nxy = false;
     c->modes = false;
     c->n = k->n;

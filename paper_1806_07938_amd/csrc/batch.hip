@@ -39,6 +39,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 
 namespace {
 
@@ -57,6 +58,9 @@ struct BSys {
     const float* M;    // [Lh][L][3G^2]
     const unsigned short* Mh;   // the same in FP16 / BF16 (half-precision storage), or null
     const float* Mhs;           // [Lh][L] factor restoring each frequency's FP16 values (1 for BF16)
+    const float* Mt;            // power-of-two L: M slot-major, [Lh][P][L], frequencies bit-reversed (k_bcolt)
+    const unsigned short* Mht;  // the same for Mh
+    const float* Mhst;          // and for Mhs, [Lh][L] bit-reversed
     const float* noise;
     const float* nxy;  // NULL unless the noise has 2x2 blocks
     int n, G, L, n_vs;
@@ -101,8 +105,13 @@ __device__ inline c32 mul_pi(c32 a) { return c32{-a.y, a.x}; }   // a (+i)
 template <bool PAD>
 __device__ __forceinline__ int pidx(int i) { return PAD ? i + (i >> 4) : i; }
 
-template <int NT, bool PAD>
-__device__ void fft_dif(c32* A, const c32* tws, int C, int bits, int L, int nin) {
+struct NoHook {
+    __device__ void operator()() const {}
+};
+
+// hook() runs after every pass (the column kernel issues direct loads there)
+template <int NT, bool PAD, typename Hook = NoHook>
+__device__ void fft_dif(c32* A, const c32* tws, int C, int bits, int L, int nin, Hook hook = Hook()) {
     const int m = 1 << bits;
     int H = m >> 1, lH = bits - 1;
     bool first = true;
@@ -130,6 +139,7 @@ __device__ void fft_dif(c32* A, const c32* tws, int C, int bits, int L, int nin)
             A[i3] = cmulc(csub(t2, t3), w2);
         }
         lds_barrier();
+        hook();
         H >>= 2;
         lH -= 2;
         first = false;
@@ -145,6 +155,7 @@ __device__ void fft_dif(c32* A, const c32* tws, int C, int bits, int L, int nin)
             A[j1] = csub(u, v);
         }
         lds_barrier();
+        hook();
     }
 }
 
@@ -152,8 +163,8 @@ __device__ void fft_dif(c32* A, const c32* tws, int C, int bits, int L, int nin)
 // in place: radix-2 decimation in time, bit-reversed input, natural output; a
 // first single stage when bits is odd, then two stages per pass (half spans h
 // and 2h on the entries j, j + h, j + 2h, j + 3h of a block of 4h).
-template <int NT, bool PAD>
-__device__ void fft_dit_inv(c32* A, const c32* tws, int C, int bits, int L) {
+template <int NT, bool PAD, typename Hook = NoHook>
+__device__ void fft_dit_inv(c32* A, const c32* tws, int C, int bits, int L, Hook hook = Hook()) {
     const int m = 1 << bits;
     int h = 1, lh = 0;
     if (bits & 1) {
@@ -164,6 +175,7 @@ __device__ void fft_dit_inv(c32* A, const c32* tws, int C, int bits, int L) {
             A[j1] = csub(u, v);
         }
         lds_barrier();
+        hook();
         h = 2;
         lh = 1;
     }
@@ -186,6 +198,7 @@ __device__ void fft_dit_inv(c32* A, const c32* tws, int C, int bits, int L) {
             A[i3] = csub(t1, u3);
         }
         lds_barrier();
+        hook();
         h <<= 2;
         lh += 2;
     }
@@ -201,6 +214,14 @@ template <> struct vecf<4> { typedef float t __attribute__((ext_vector_type(4)))
 template <int VEC>
 using gvec_ptr = const __attribute__((address_space(1))) typename vecf<VEC>::t*;
 
+// An empty use of a loaded value on every path: the wait for its load is then
+// placed here, by count, whether or not the value is used afterwards (a value
+// used under a branch only leaves its load pending on the other path, and a
+// later reuse of its registers would then wait for every memory operation).
+template <typename T>
+__device__ __forceinline__ void keep(const T& v) { asm volatile("" ::"v"(v)); }
+__device__ __forceinline__ void keep(const c32& v) { asm volatile("" ::"v"(v.x), "v"(v.y)); }
+
 template <int VEC>
 __device__ __forceinline__ void spectra_load(typename vecf<VEC>::t (&pf)[NPF], const float* Mcol, int base, int Q,
                                              int P, int S, int h) {
@@ -210,7 +231,10 @@ __device__ __forceinline__ void spectra_load(typename vecf<VEC>::t (&pf)[NPF], c
     const gvec_ptr<VEC> g = (gvec_ptr<VEC>)Mcol;
 #pragma unroll
     for (int i = 0; i < NPF; ++i) {
-        if (base + (int)threadIdx.x + i * BT < Q) pf[i] = g[(S * k + h) * Pv + w];
+        // unconditional (an in-range vector past the end of the round): no branch
+        // between the loads, so the waits on them count exactly
+        const bool ok = base + (int)threadIdx.x + i * BT < Q;
+        pf[i] = g[ok ? (S * k + h) * Pv + w : h * Pv];
         w += dw;
         const int cy = w >= Pv;
         w -= cy ? Pv : 0;
@@ -228,6 +252,7 @@ __device__ __forceinline__ void spectra_store(const typename vecf<VEC>::t (&pf)[
     int k = (base + (int)threadIdx.x) / Pv, w = (base + (int)threadIdx.x) - k * Pv;
 #pragma unroll
     for (int i = 0; i < NPF; ++i) {
+        keep(pf[i]);
         if (base + (int)threadIdx.x + i * BT < Q) {
             float* d = Ms + (rbits >= 0 ? bitrev(k, rbits) : k) * (P + 1) + w * VEC;
             if constexpr (VEC == 4) {
@@ -267,10 +292,9 @@ __device__ __forceinline__ void spectra_load_h(typename vech<VEC>::t (&pf)[NPF],
     const __attribute__((address_space(1))) float* gs = (const __attribute__((address_space(1))) float*)scol;
 #pragma unroll
     for (int i = 0; i < NPF; ++i) {
-        if (base + (int)threadIdx.x + i * BT < Q) {
-            pf[i] = g[(S * k + h) * Pv + w];
-            pfs[i] = gs[S * k + h];
-        }
+        const bool ok = base + (int)threadIdx.x + i * BT < Q;
+        pf[i] = g[ok ? (S * k + h) * Pv + w : h * Pv];
+        pfs[i] = gs[ok ? S * k + h : h];
         w += dw;
         const int cy = w >= Pv;
         w -= cy ? Pv : 0;
@@ -292,6 +316,8 @@ __device__ __forceinline__ void spectra_store_h(const typename vech<VEC>::t (&pf
     int k = (base + (int)threadIdx.x) / Pv, w = (base + (int)threadIdx.x) - k * Pv;
 #pragma unroll
     for (int i = 0; i < NPF; ++i) {
+        keep(pf[i]);
+        keep(pfs[i]);
         if (base + (int)threadIdx.x + i * BT < Q) {
             float* d = Ms + (rbits >= 0 ? bitrev(k, rbits) : k) * (P + 1) + w * VEC;
             const float sc = pfs[i];
@@ -559,16 +585,16 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
     {
         const BSys& s0 = sys[si];
         const int f20 = col - s0.col0, P0 = PACK ? 4 * s0.G * s0.G : 3 * s0.G * s0.G, Cn0 = 2 * s0.G * s0.n;
+#pragma unroll
+        for (int i = 0; i < TPF; ++i) {
+            const int idx = threadIdx.x + i * BT;
+            tp[i] = gload(s0.T + (size_t)f20 * Cn0 + (idx < Cn0 ? idx : 0));
+        }
         if constexpr (HALF)
             spectra_load_h<VEC>(pfh, pfs, s0.Mh + (size_t)f20 * s0.L * P0, s0.Mhs + (size_t)f20 * s0.L, 0,
                                 (s0.L >> sh) * P0 / VEC, P0, S, h);
         else
             spectra_load<VEC>(pf, s0.M + (size_t)f20 * s0.L * P0, 0, (s0.L >> sh) * P0 / VEC, P0, S, h);
-#pragma unroll
-        for (int i = 0; i < TPF; ++i) {
-            const int idx = threadIdx.x + i * BT;
-            if (idx < Cn0) tp[i] = gload(s0.T + (size_t)f20 * Cn0 + idx);
-        }
     }
     int qn = q + gridDim.x;
     int coln = ((qn >> 3) >> sh) * 8 + (qn & 7);
@@ -619,6 +645,7 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
 #pragma unroll
                 for (int i = 0; i < TPF; ++i, wk.next()) {
                     const int idx = threadIdx.x + i * BT;
+                    keep(tp[i]);
                     if (idx < C * n && (wk.c >= m) == (pass == 1)) fold(tp[i], wk.r, wk.c, pass == 1);
                 }
                 for (int idx = threadIdx.x + TPF * BT; idx < C * n; idx += BT, wk.next())
@@ -676,16 +703,17 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
         const int colnn = ((qnn >> 3) >> sh) * 8 + (qnn & 7);
         if (more) {
             const int Pn = PACK ? 4 * Gn * Gn : 3 * Gn * Gn, Cnn = 2 * Gn * nn;
+            // the input column first: the next item's first step waits for it alone
+#pragma unroll
+            for (int i = 0; i < TPF; ++i) {
+                const int idx = threadIdx.x + i * BT;
+                tp[i] = gload(Tn + (size_t)f2n * Cnn + (idx < Cnn ? idx : 0));
+            }
             if constexpr (HALF)
                 spectra_load_h<VEC>(pfh, pfs, Mnh + (size_t)f2n * Ln * Pn, Mnhs + (size_t)f2n * Ln, 0,
                                     (Ln >> sh) * Pn / VEC, Pn, S, hn);
             else
                 spectra_load<VEC>(pf, Mn + (size_t)f2n * Ln * Pn, 0, (Ln >> sh) * Pn / VEC, Pn, S, hn);
-#pragma unroll
-            for (int i = 0; i < TPF; ++i) {
-                const int idx = threadIdx.x + i * BT;
-                if (idx < Cnn) tp[i] = gload(Tn + (size_t)f2n * Cnn + idx);
-            }
             if (colnn < total_cols) sinn = col_sys[colnn];
         }
 
@@ -777,6 +805,435 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
     }
 }
 
+// ---------------------------------------------------------------------------
+// Column kernel for batches whose every L is a power of two.  There the
+// spectra of a column are kept slot-major with the column's L frequencies in
+// bit-reversed order ([Lh][P][L], built once per system by k_slot_major), so
+// the m frequencies S k + h of item h are one contiguous run of every slot
+// row, at bitrev_s(h) m, already in the order of the m-point FFT's output.
+// An item's spectra (P runs of m values) go from HBM to LDS by direct loads
+// (global_load_lds_dwordx4: each lane moves 16 bytes, one wave fills 1 KB of
+// LDS), issued by every wave as soon as the previous item's products are
+// done: they land under that item's inverse transform and this item's input
+// fold and forward transform, with no registers held and no copy through the
+// vector ALU.  The products read value j of position p at j m + p (the lanes
+// of a wave on consecutive positions: no bank conflicts).  The input column of
+// the next item loads into registers during this item's forward transform;
+// one wait on all vector memory operations before the products covers both.
+constexpr unsigned WAIT_VM0 = 0x0F70;   // s_waitcnt vmcnt(0), lgkmcnt and expcnt not waited
+constexpr int TPFT = 3;                 // entries of the input column held per thread (C n <= 1536 without waits)
+
+__device__ __forceinline__ int bitrev_split(int h, int sh) {   // bit reversal of h < 2^sh, sh <= 2
+    return sh == 2 ? (((h & 1) << 1) | (h >> 1)) : h;
+}
+
+template <int HALF>
+__device__ __forceinline__ float sdec(const void* M, int i) {
+    if constexpr (HALF == 0) return static_cast<const float*>(M)[i];
+    else return half_dec<HALF>(static_cast<const unsigned short*>(M)[i]);
+}
+
+// sensor_products on the slot-major LDS layout: value j of position p at j m + p
+template <int HALF>
+__device__ __forceinline__ void sensor_products_t(const void* Ms, const c32* X, int m, int G, int g, int p, c32& yx,
+                                                  c32& yy) {
+    c32 ax = c32{0.f, 0.f}, ay = c32{0.f, 0.f};
+    for (int hh = 0; hh < G; ++hh) {
+        const c32 xh = X[pidx<true>(2 * hh * m + p)], yh = X[pidx<true>((2 * hh + 1) * m + p)];
+        c32 mxx, mxy, myy;
+        if (hh == g) {
+            mxx = c32{sdec<HALF>(Ms, 3 * g * m + p), 0.f};
+            mxy = c32{sdec<HALF>(Ms, (3 * g + 1) * m + p), 0.f};
+            myy = c32{sdec<HALF>(Ms, (3 * g + 2) * m + p), 0.f};
+        } else {
+            const int lo = g < hh ? g : hh, hi = g < hh ? hh : g;
+            const int b = (3 * G + 6 * (lo * (2 * G - lo - 1) / 2 + (hi - lo - 1))) * m + p;
+            const float sg = g < hh ? 1.f : -1.f;
+            mxx = c32{sdec<HALF>(Ms, b), sg * sdec<HALF>(Ms, b + m)};
+            mxy = c32{sdec<HALF>(Ms, b + 2 * m), sg * sdec<HALF>(Ms, b + 3 * m)};
+            myy = c32{sdec<HALF>(Ms, b + 4 * m), sg * sdec<HALF>(Ms, b + 5 * m)};
+        }
+        ax = cadd(ax, cadd(cmul(mxx, xh), cmul(mxy, yh)));
+        ay = cadd(ay, cadd(cmul(mxy, xh), cmul(myy, yh)));
+    }
+    yx = ax;
+    yy = ay;
+}
+
+// herm_entry / herm_products on the slot-major LDS layout
+template <int HALF>
+__device__ __forceinline__ c32 herm_entry_t(const void* Ms, int m, int p, int C, int a, int b) {
+    if (a == b) return c32{sdec<HALF>(Ms, a * m + p), 0.f};
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    const int k = lo * C - lo * (lo + 1) / 2 + hi - lo - 1;
+    const float im = sdec<HALF>(Ms, (C + 2 * k + 1) * m + p);
+    return c32{sdec<HALF>(Ms, (C + 2 * k) * m + p), a < b ? im : -im};
+}
+
+template <int HALF>
+__device__ __forceinline__ void herm_products_t(const void* Ms, const c32* X, int m, int C, int g, int p, c32& y0,
+                                                c32& y1) {
+    c32 a0 = c32{0.f, 0.f}, a1 = c32{0.f, 0.f};
+    for (int q = 0; q < C; ++q) {
+        const c32 xq = X[pidx<true>(q * m + p)];
+        a0 = cadd(a0, cmul(herm_entry_t<HALF>(Ms, m, p, C, 2 * g, q), xq));
+        a1 = cadd(a1, cmul(herm_entry_t<HALF>(Ms, m, p, C, 2 * g + 1, q), xq));
+    }
+    y0 = a0;
+    y1 = a1;
+}
+
+__device__ __forceinline__ c32 cfma(c32 acc, c32 a, c32 b) {   // acc + a b
+    return c32{acc.x + a.x * b.x - a.y * b.y, acc.y + a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ c32 cfmac(c32 acc, c32 a, c32 b) {  // acc + conj(a) b
+    return c32{acc.x + a.x * b.x + a.y * b.y, acc.y + a.x * b.y - a.y * b.x};
+}
+
+// Pins the accumulators updated so far: the products that feed them are issued
+// before it, so the spectra values they read do not stay live past it (the
+// compiler would otherwise load far ahead and run out of registers).
+__device__ __forceinline__ void pin4(c32& a, c32& b, c32& c, c32& d) {
+    asm volatile("" : "+v"(a.x), "+v"(a.y), "+v"(b.x), "+v"(b.y), "+v"(c.x), "+v"(c.y), "+v"(d.x), "+v"(d.y)::"memory");
+}
+__device__ __forceinline__ void pin2(c32& a, c32& b) {
+    asm volatile("" : "+v"(a.x), "+v"(a.y), "+v"(b.x), "+v"(b.y)::"memory");
+}
+
+// All 2G outputs of position p, one thread per position, in place: X_c is read
+// from and Y_c written to pidx(c M + p) (M a multiple of 16, so that index is
+// c (M + M / 16) + pidx(p)); no other thread touches position p.  Slope
+// spectra: real 2x2 blocks (g, g); blocks (lo, hi) stored once and used for
+// (lo, hi) and, conjugated, for (hi, lo).  G and M are compile-time, so every
+// LDS offset is an immediate of one base address.  f: the FP16 factor.
+template <int G, int M, int HALF>
+__device__ __forceinline__ void products_pos(const void* Ms, c32* A, int p, float f) {
+    constexpr int MP = M + M / 16, NP = G * (G - 1) / 2;
+    c32* Ap = A + (p + (p >> 4));
+    c32 x[2 * G], y[2 * G];
+#pragma unroll
+    for (int c = 0; c < 2 * G; ++c) x[c] = Ap[c * MP];
+    auto v = [&](int j) { return sdec<HALF>(Ms, j * M + p); };
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const float xx = v(3 * g), xy = v(3 * g + 1), yy = v(3 * g + 2);
+        const c32 a = x[2 * g], b = x[2 * g + 1];
+        y[2 * g] = c32{xx * a.x + xy * b.x, xx * a.y + xy * b.y};
+        y[2 * g + 1] = c32{xy * a.x + yy * b.x, xy * a.y + yy * b.y};
+        pin2(y[2 * g], y[2 * g + 1]);
+    }
+    // pairs (lo, hi) in storage order, the next pair's six values loading under this pair's products
+    float cur[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) cur[i] = v(3 * G + i);
+    int lo = 0, hi = 1;
+#pragma unroll
+    for (int t = 0; t < NP; ++t) {
+        float nxt[6];
+        if (t + 1 < NP) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) nxt[i] = v(3 * G + 6 * (t + 1) + i);
+        }
+        const c32 mxx = c32{cur[0], cur[1]}, mxy = c32{cur[2], cur[3]}, myy = c32{cur[4], cur[5]};
+        y[2 * lo] = cfma(cfma(y[2 * lo], mxx, x[2 * hi]), mxy, x[2 * hi + 1]);
+        y[2 * lo + 1] = cfma(cfma(y[2 * lo + 1], mxy, x[2 * hi]), myy, x[2 * hi + 1]);
+        y[2 * hi] = cfmac(cfmac(y[2 * hi], mxx, x[2 * lo]), mxy, x[2 * lo + 1]);
+        y[2 * hi + 1] = cfmac(cfmac(y[2 * hi + 1], mxy, x[2 * lo]), myy, x[2 * lo + 1]);
+        pin4(y[2 * lo], y[2 * lo + 1], y[2 * hi], y[2 * hi + 1]);
+        if (t + 1 < NP) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) cur[i] = nxt[i];
+        }
+        if (++hi == G) {
+            ++lo;
+            hi = lo + 1;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 2 * G; ++c) Ap[c * MP] = HALF == 1 ? c32{y[c].x * f, y[c].y * f} : y[c];
+}
+
+// the same for the preconditioner's general Hermitian C x C blocks (C^2 reals;
+// the C (C - 1) / 2 entries above the diagonal in storage order, four at a time)
+template <int C, int M, int HALF>
+__device__ __forceinline__ void products_pos_herm(const void* Ms, c32* A, int p, float f) {
+    constexpr int MP = M + M / 16, NE = C * (C - 1) / 2;
+    c32* Ap = A + (p + (p >> 4));
+    c32 x[C], y[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) x[c] = Ap[c * MP];
+    auto v = [&](int j) { return sdec<HALF>(Ms, j * M + p); };
+#pragma unroll
+    for (int a = 0; a < C; ++a) {
+        const float d = v(a);
+        y[a] = c32{d * x[a].x, d * x[a].y};
+    }
+    int a = 0, b = 1;
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+        const c32 hv = c32{v(C + 2 * k), v(C + 2 * k + 1)};
+        y[a] = cfma(y[a], hv, x[b]);
+        y[b] = cfmac(y[b], hv, x[a]);
+        pin2(y[a], y[b]);
+        if (++b == C) {
+            ++a;
+            b = a + 1;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) Ap[c * MP] = HALF == 1 ? c32{y[c].x * f, y[c].y * f} : y[c];
+}
+
+// products of every position of an item, one thread per position, for G in
+// [4, 6] and m in {64, 128} (the columns of L = 256 split in 2 or 4, and of
+// L = 128 split in 2); false for other sizes, the caller then uses tasks (with
+// G >= 7 the accumulators of one position no longer fit the registers of four
+// waves per SIMD)
+template <int PACK, int HALF>
+__device__ __forceinline__ bool products_fixed(const void* Ms, c32* A, const float* fac, int m, int G) {
+    if ((m != 64 && m != 128) || G < 4 || G > 6) return false;
+    for (int p = threadIdx.x; p < m; p += BT) {
+        const float f = HALF == 1 ? fac[p] : 1.f;
+#define TT_POS(g, mm)                                                            \
+    if (G == g && m == mm) {                                                     \
+        if constexpr (PACK == 0) products_pos<g, mm, HALF>(Ms, A, p, f);          \
+        else products_pos_herm<2 * g, mm, HALF>(Ms, A, p, f);                     \
+    }
+        TT_POS(4, 64) TT_POS(5, 64) TT_POS(6, 64) TT_POS(4, 128) TT_POS(5, 128) TT_POS(6, 128)
+#undef TT_POS
+    }
+    return true;
+}
+
+// One direct load: 16 bytes from g (per lane) to LDS at lds + 16 lane (lds
+// uniform over the wave).  Written as inline assembly so that the compiler
+// neither adds waits on it (it would make every later LDS access and workgroup
+// barrier wait for the whole transfer) nor reorders memory accesses across it;
+// the kernel waits for it explicitly (vmcnt) before reading the spectra.
+typedef __attribute__((address_space(3))) char lchar;
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void dma16(const void* g, const void* lds) {
+    const unsigned a = __builtin_amdgcn_readfirstlane((unsigned)(size_t)(const lchar*)lds);
+    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(a), "v"(g) : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
+// LDS (bytes from the start of dynamic shared memory): twiddles at 0, the
+// transform buffer at offA, the FP16 factors at offF, the spectra at offM; the
+// host sizes each region for the largest system of the batch, so the direct
+// loads of the next item never reach the buffers the current item still uses.
+template <int PACK, int HALF>
+__global__ __launch_bounds__(BT, 4) void k_bcolt(const BSys* __restrict__ sys, const int* __restrict__ col_sys,
+                                                  int total_cols, int S, int offA, int offF, int offM) {
+    extern __shared__ __align__(16) char smem_raw[];
+    typedef typename std::conditional<HALF != 0, unsigned short, float>::type E;
+    constexpr int PER = 16 / (int)sizeof(E);   // values per lane of one direct load
+    const int sh = S == 4 ? 2 : S - 1, hm = S - 1;   // S is 1, 2 or 4
+    const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+    int q = blockIdx.x;
+    int col = ((q >> 3) >> sh) * 8 + (q & 7), h = (q >> 3) & hm;
+    if (col >= total_cols) return;
+    c32* tws = reinterpret_cast<c32*>(smem_raw);
+    c32* A = reinterpret_cast<c32*>(smem_raw + offA);
+    float* fac = reinterpret_cast<float*>(smem_raw + offF);
+    char* Ms = smem_raw + offM;
+
+    // direct loads of item (column cl, share hh) of system s: P runs of m values,
+    // 16 bytes a lane, chunk c of the item landing at Ms + 16 c.  Issued round by
+    // round (one direct load per wave, BT / 64 KB per round: chunk c0 + r BT,
+    // the same position BT / cpr rows on) between the passes of the transforms,
+    // so that the transfer is spread over the time to the next products.
+    const E* dg = nullptr;
+    const char* dl = nullptr;
+    int dc = 0, dchunks = 0;
+    size_t dstep = 0;
+    auto dma_begin = [&](const BSys& s, int cl, int hh) {
+        const int f2 = cl - s.col0, L = s.L, m = L >> sh, P = PACK ? 4 * s.G * s.G : 3 * s.G * s.G;
+        const int run = bitrev_split(hh, sh) * m, lcpr = __builtin_ctz(m / PER);
+        const int c0 = wave * 64 + lane, j0 = c0 >> lcpr, pp = (c0 - (j0 << lcpr)) * PER;
+        dg = (HALF ? (const E*)s.Mht : (const E*)s.Mt) + ((size_t)f2 * P * L + run + (size_t)j0 * L + pp);
+        dstep = (size_t)(BT >> lcpr) * L;
+        dl = Ms + wave * 1024;
+        dc = c0;
+        dchunks = P * m / PER;
+        if constexpr (HALF == 1) {   // the m factors of these frequencies
+            const float* fs = s.Mhst + ((size_t)f2 * L + run);
+            for (int c = c0; c - lane < m / 4; c += BT)
+                if (c < m / 4) dma16(fs + 4 * c, fac + 4 * (size_t)c);
+        }
+    };
+    auto dma_rounds = [&](int k) {
+        for (int i = 0; i < k; ++i) {
+            if (dc - lane >= dchunks) return;   // uniform over the wave
+            if (dc < dchunks) dma16(dg, dl);
+            dc += BT;
+            dg += dstep;
+            dl += BT * 16;
+        }
+    };
+    auto hook = [&]() { dma_rounds(2); };
+
+    c32 tp[TPFT];
+    int si = col_sys[col];
+    {
+        const BSys& s0 = sys[si];
+        const int f20 = col - s0.col0, Cn0 = 2 * s0.G * s0.n;
+#pragma unroll
+        for (int i = 0; i < TPFT; ++i) {
+            const int idx = threadIdx.x + i * BT;
+            tp[i] = gload(s0.T + (size_t)f20 * Cn0 + (idx < Cn0 ? idx : 0));
+        }
+        __builtin_amdgcn_s_waitcnt(WAIT_VM0);   // (the compiler then counts no load pending at the first fold)
+        dma_begin(s0, col, h);
+        dma_rounds(1 << 20);
+    }
+    int qn = q + gridDim.x;
+    int coln = ((qn >> 3) >> sh) * 8 + (qn & 7);
+    int sin_ = coln < total_cols ? col_sys[coln] : 0;
+    int prevL = -1;
+    while (true) {
+        const BSys& s = sys[si];
+        const int f2 = col - s.col0;
+        const int n = s.n, G = s.G, C = 2 * G, L = s.L, m = L >> sh;
+        int bits = 0;
+        while ((1 << bits) < m) ++bits;
+        const bool more = coln < total_cols;
+        const int hn = (qn >> 3) & hm;
+        const BSys& sn = sys[sin_];
+
+        __syncthreads();   // the previous item's last reads of A and of the twiddles are done
+        if (L != prevL) {
+            for (int i = threadIdx.x; i < L; i += BT) tws[i] = gload(s.tw + i);
+            prevL = L;
+            __syncthreads();
+        }
+        // twisted input column folded to length m (entry a < n to a mod m, m >= n / 2)
+        {
+            const c32* Tc = s.T + (size_t)f2 * C * n;
+            auto fold = [&](c32 v, int c, int a, bool add) {
+                int hw = h * a;   // < 2L
+                if (hw >= L) hw -= L;
+                if (h) v = cmulc(v, tws[hw]);   // w_L^{h a}
+                const int li = pidx<true>(c * m + (add ? a - m : a));
+                A[li] = add ? cadd(A[li], v) : v;
+            };
+            for (int pass = 0; pass < (n > m ? 2 : 1); ++pass) {
+                if (pass) __syncthreads();
+                Walk wk(n);
+#pragma unroll
+                for (int i = 0; i < TPFT; ++i, wk.next()) {
+                    const int idx = threadIdx.x + i * BT;
+                    keep(tp[i]);
+                    if (idx < C * n && (wk.c >= m) == (pass == 1)) fold(tp[i], wk.r, wk.c, pass == 1);
+                }
+                for (int idx = threadIdx.x + TPFT * BT; idx < C * n; idx += BT, wk.next())
+                    if ((wk.c >= m) == (pass == 1)) fold(gload(Tc + idx), wk.r, wk.c, pass == 1);
+            }
+        }
+        dma_rounds(2);
+        // the next item's input column loads under this item's transforms
+        int sinn = 0, qnn = qn + gridDim.x;
+        const int colnn = ((qnn >> 3) >> sh) * 8 + (qnn & 7);
+        if (more) {
+            const int f2n = coln - sn.col0, Cnn = 2 * sn.G * sn.n;
+#pragma unroll
+            for (int i = 0; i < TPFT; ++i) {
+                const int idx = threadIdx.x + i * BT;
+                tp[i] = gload(sn.T + (size_t)f2n * Cnn + (idx < Cnn ? idx : 0));
+            }
+            if (colnn < total_cols) sinn = col_sys[colnn];
+        }
+        __syncthreads();
+        fft_dif<BT, true>(A, tws, C, bits, L, n < m ? n : m, hook);   // X at bit-reversed positions
+        dma_rounds(1 << 20);                     // the rest of this item's spectra
+        __builtin_amdgcn_s_waitcnt(WAIT_VM0);   // this wave's direct loads (and the next input column) are done
+        __syncthreads();                         // ... and every other wave's
+
+        // per-frequency products: one thread per position (in place) for the usual sizes, else
+        // task (g, p) gives the x and y outputs of sensor g at position p
+        c32 yx[TMAX], yy[TMAX];
+        const bool fixed = products_fixed<PACK, HALF>(Ms, A, fac, m, G);
+        if (!fixed) {
+            Walk wk(m);
+            const bool wave_uniform = (m & 63) == 0;   // the 64 tasks of a wave share g
+#pragma unroll
+            for (int it = 0; it < TMAX; ++it, wk.next()) {
+                const int task = threadIdx.x + it * BT;
+                yx[it] = yy[it] = c32{0.f, 0.f};
+                if (task < m * G) {
+                    const int g = wave_uniform ? __builtin_amdgcn_readfirstlane(wk.r) : wk.r;
+                    if constexpr (PACK == 0) sensor_products_t<HALF>(Ms, A, m, G, g, wk.c, yx[it], yy[it]);
+                    else herm_products_t<HALF>(Ms, A, m, C, g, wk.c, yx[it], yy[it]);
+                    if constexpr (HALF == 1) {
+                        const float f = fac[wk.c];
+                        yx[it] = c32{yx[it].x * f, yx[it].y * f};
+                        yy[it] = c32{yy[it].x * f, yy[it].y * f};
+                    }
+                }
+            }
+        }
+        __syncthreads();   // every read of the spectra and of X is done
+        if (more) {
+            dma_begin(sn, coln, hn);
+            dma_rounds(2);
+        }
+        if (!fixed) {
+            Walk wk(m);
+#pragma unroll
+            for (int it = 0; it < TMAX; ++it, wk.next()) {
+                const int task = threadIdx.x + it * BT;
+                if (task < m * G) {
+                    const int ix = (2 * wk.r) * m + wk.c;
+                    A[pidx<true>(ix)] = yx[it];
+                    A[pidx<true>(ix + m)] = yy[it];
+                }
+            }
+            __syncthreads();
+        }
+
+        // this item's share of the inverse column transform, rows a < n
+        fft_dit_inv<BT, true>(A, tws, C, bits, L, hook);
+        {
+            c32* Uo = s.U + ((size_t)f2 * S + h) * C * n;
+            Walk wk(n);
+            for (int idx = threadIdx.x; idx < C * n; idx += BT, wk.next()) {
+                const int a = wk.c;   // V at a mod m, a < n <= 2m
+                c32 v = A[pidx<true>(wk.r * m + (a < m ? a : a - m))];
+                if (h) {
+                    int hw = h * a;
+                    if (hw >= L) hw -= L;
+                    v = cmul(v, tws[hw]);   // w_L^{-h a}
+                }
+                gstore(Uo + idx, v);
+            }
+        }
+        dma_rounds(2);
+        if (!more) break;
+        q = qn;
+        col = coln;
+        h = hn;
+        si = sin_;
+        qn = qnn;
+        coln = colnn;
+        sin_ = sinn;
+    }
+}
+
+// dst[((f2 P + j) L + r] = src[(f2 L + bitrev(r)) P + j]: one system's spectra
+// [Lh][L][P] to the slot-major bit-reversed layout (P = 1: the factors)
+template <typename T>
+__global__ void k_slot_major(const T* __restrict__ src, T* __restrict__ dst, int Lh, int L, int P, int bits) {
+    const long total = (long)Lh * P * L;
+    for (long d = blockIdx.x * (long)blockDim.x + threadIdx.x; d < total; d += (long)gridDim.x * blockDim.x) {
+        const int r = (int)(d % L);
+        const long fj = d / L;
+        const int j = (int)(fj % P);
+        const long f2 = fj / P;
+        dst[d] = src[(f2 * L + bitrev(r, bits)) * P + j];
+    }
+}
+
 // FP32 spectra rows (one frequency each, P reals) -> FP16 or BF16 storage.
 // FP16: each row is multiplied by the power of two 2^(15 - e) that brings its
 // largest magnitude m = f 2^e (f in [0.5, 1)) to [2^14, 2^15) and stored with
@@ -835,6 +1292,44 @@ tt_status ensure_half(tt_ctx& c, int op, int kind) {
                        op ? c.Minv32.p : c.M32.p, c.Mh[op].p, c.Mhs[op].p, rows, P, kind, op ? c.C : 0);
     TT_HIP(hipGetLastError());
     c.mh_kind[op] = kind;
+    return TT_OK;
+}
+
+// The context whose spectra of operator op a context uses: a view reads its
+// base's (unless it built its own preconditioner), and so do the copies made
+// from them, which are then built once for the base and all its views.
+tt_ctx& spectra_owner(tt_ctx& c, int op) {
+    tt_ctx* b = c.view_of;
+    if (b && (op ? b->Minv32.p == c.Minv32.p : b->M32.p == c.M32.p)) return *b;
+    return c;
+}
+
+// the slot-major bit-reversed copies read by k_bcolt (power-of-two L), built on first use
+tt_status ensure_slot_major(tt_ctx& c, int op, int half_kind) {
+    const int P = op ? c.C * c.C : packed_reals(c.G);
+    int bits = 0;
+    while ((1 << bits) < c.L) ++bits;
+    const size_t vals = (size_t)c.Lh * c.L * P;
+    const unsigned grid = (unsigned)std::min<size_t>((vals + 255) / 256, 65535);
+    if (!half_kind && !c.mt_ready[op]) {
+        TT_CHECK(c.Mt32[op].alloc(vals));
+        hipLaunchKernelGGL(k_slot_major<float>, dim3(grid), dim3(256), 0, c.stream, op ? c.Minv32.p : c.M32.p,
+                           c.Mt32[op].p, c.Lh, c.L, P, bits);
+        TT_HIP(hipGetLastError());
+        c.mt_ready[op] = true;
+    }
+    if (half_kind && c.mht_kind[op] != half_kind) {
+        TT_CHECK(ensure_half(c, op, half_kind));
+        TT_CHECK(c.Mht[op].alloc(vals));
+        TT_CHECK(c.Mhst[op].alloc((size_t)c.Lh * c.L));
+        hipLaunchKernelGGL(k_slot_major<unsigned short>, dim3(grid), dim3(256), 0, c.stream, c.Mh[op].p, c.Mht[op].p,
+                           c.Lh, c.L, P, bits);
+        TT_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_slot_major<float>, dim3((unsigned)std::min<size_t>((c.Lh * (size_t)c.L + 255) / 256, 65535)),
+                           dim3(256), 0, c.stream, c.Mhs[op].p, c.Mhst[op].p, c.Lh, c.L, 1, bits);
+        TT_HIP(hipGetLastError());
+        c.mht_kind[op] = half_kind;
+    }
     return TT_OK;
 }
 
@@ -901,19 +1396,31 @@ tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x
                std::equal(systems, systems + count, c0.tuned_for[op].begin())) {
         S = c0.tuned_S[op];   // chosen by tt_tune_batch for this batch
     }
-    size_t work = 0;
+    // k_bcolt (spectra slot-major, direct loads to LDS) when every L is a power of
+    // two and an item's run of one spectra row is at least 16 bytes; else k_bcol
+    const int ebytes = half ? 2 : 4;
+    bool slot = true;
+    for (int i = 0; i < count; ++i)
+        if (!is_pow2(systems[i]->L) || (systems[i]->L / S) * ebytes < 16) slot = false;
+    size_t work = 0, a_max = 0, f_max = 0, m_max = 0;
     int Lmax = 0, fwd_tiles = 0, inv_tiles = 0;
+    auto a16 = [](size_t b) { return (b + 15) & ~size_t(15); };
     for (int i = 0; i < count; ++i) {
         const tt_ctx& c = *systems[i];
         TT_REQUIRE((long)(c.L / S) * c.G <= (long)TMAX * BT,
                    "system too large for the batched product: (L / S) * n_gs must be <= " +
                        std::to_string(TMAX * BT));
+        const size_t m = (size_t)(c.L / S), P = op ? (size_t)c.C * c.C : (size_t)packed_reals(c.G);
         work = std::max(work, col_work_lds(c.G, c.L, S, op));
+        a_max = std::max(a_max, a16(((size_t)c.C * m + (size_t)c.C * m / 16 + 1) * sizeof(c32)));
+        f_max = std::max(f_max, half == 1 ? a16(m * sizeof(float)) : size_t(0));
+        m_max = std::max(m_max, a16(P * m * ebytes));
         Lmax = std::max(Lmax, c.L);
         fwd_tiles = std::max(fwd_tiles, c.C * (int)cdiv(c.n, row_tile_fwd(c.L)));
         inv_tiles = std::max(inv_tiles, c.C * (int)cdiv(c.n, row_tile_inv(c.L)));
     }
-    const size_t lds = (((size_t)Lmax * sizeof(c32) + 15) & ~size_t(15)) + work;
+    const size_t off_a = a16((size_t)Lmax * sizeof(c32)), off_f = off_a + a_max, off_m = off_f + f_max;
+    const size_t lds = slot ? off_m + m_max : off_a + work;
     TT_REQUIRE(lds <= 160 * 1024, "system too large for the batched product: " + std::to_string(lds) +
                                       " bytes of LDS per column item");
     TT_HIP(hipSetDevice(c0.device));
@@ -928,13 +1435,19 @@ tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x
         // split never moves the buffer a captured launch writes
         const size_t ucount = (size_t)c.Lh * 4 * c.C * c.n;
         if (c.bU32.n < ucount) TT_CHECK(c.bU32.alloc(ucount));
-        // the half copies are built once, on each system's own stream; the kernels run on the first one's
-        if (half && c.mh_kind[op] != precision) {
-            TT_CHECK(ensure_half(c, op, precision));
-            if (c.stream != c0.stream) TT_HIP(hipStreamSynchronize(c.stream));
+        // the half and slot-major copies are built once, on the owning system's stream; the kernels run on
+        // the first one's
+        tt_ctx& o = spectra_owner(c, op);
+        const bool build = slot ? (half ? o.mht_kind[op] != precision : !o.mt_ready[op])
+                                : (half && o.mh_kind[op] != precision);
+        if (build) {
+            TT_CHECK(slot ? ensure_slot_major(o, op, half ? precision : 0) : ensure_half(o, op, precision));
+            if (o.stream != c0.stream) TT_HIP(hipStreamSynchronize(o.stream));
         }
         d[i] = BSys{d_x[i], d_y[i], c.vmap.p, c.tw32.p, c.T32.p, c.bU32.p, op ? c.Minv32.p : c.M32.p,
-                    half ? c.Mh[op].p : nullptr, half ? c.Mhs[op].p : nullptr,
+                    half ? o.Mh[op].p : nullptr, half ? o.Mhs[op].p : nullptr,
+                    (slot && !half) ? o.Mt32[op].p : nullptr, (slot && half) ? o.Mht[op].p : nullptr,
+                    (slot && half) ? o.Mhst[op].p : nullptr,
                     op ? nullptr : c.noise32.p, (!op && c.has_nxy) ? c.nxy32.p : nullptr, c.n, c.G, c.L, c.n_vs,
                     cols};
         cols += c.Lh;
@@ -970,8 +1483,12 @@ tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x
     static const ColKernel table[2][2][3] = {
         {{k_bcol<1, 0, 0>, k_bcol<1, 0, 1>, k_bcol<1, 0, 2>}, {k_bcol<1, 0, 0>, k_bcol<1, 0, 1>, k_bcol<1, 0, 2>}},
         {{k_bcol<4, 0, 0>, k_bcol<4, 0, 1>, k_bcol<4, 0, 2>}, {k_bcol<4, 1, 0>, k_bcol<4, 1, 1>, k_bcol<4, 1, 2>}}};
+    typedef void (*SlotKernel)(const BSys*, const int*, int, int, int, int, int);
+    static const SlotKernel slot_table[2][3] = {{k_bcolt<0, 0>, k_bcolt<0, 1>, k_bcolt<0, 2>},
+                                                {k_bcolt<1, 0>, k_bcolt<1, 1>, k_bcolt<1, 2>}};
     const ColKernel kc = table[(op || vec4) ? 1 : 0][op ? 1 : 0][half];
-    const void* kcol = (const void*)kc;
+    const SlotKernel ks = slot_table[op ? 1 : 0][half];
+    const void* kcol = slot ? (const void*)ks : (const void*)kc;
     TT_HIP(hipFuncSetAttribute(kcol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
     TT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kcol, BT, lds));
@@ -984,7 +1501,11 @@ tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x
     hipLaunchKernelGGL(k_brow_fwd, dim3(fwd_tiles, count), dim3(RBT), 0, c0.stream, dd);
     TT_HIP(hipGetLastError());
     if (phase_ms) TT_HIP(hipEventRecord(c0.bev[1], c0.stream));
-    hipLaunchKernelGGL(kc, dim3(col_grid), dim3(BT), lds, c0.stream, dd, col_sys, cols, S, Lmax);
+    if (slot)
+        hipLaunchKernelGGL(ks, dim3(col_grid), dim3(BT), lds, c0.stream, dd, col_sys, cols, S, (int)off_a, (int)off_f,
+                           (int)off_m);
+    else
+        hipLaunchKernelGGL(kc, dim3(col_grid), dim3(BT), lds, c0.stream, dd, col_sys, cols, S, Lmax);
     TT_HIP(hipGetLastError());
     if (phase_ms) TT_HIP(hipEventRecord(c0.bev[2], c0.stream));
     hipLaunchKernelGGL(k_brow_inv, dim3(inv_tiles, count), dim3(RBT), 0, c0.stream, dd, S);

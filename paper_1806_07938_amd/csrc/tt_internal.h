@@ -191,6 +191,14 @@ struct tt_ctx {
     DevBuf<unsigned short> Mh[2];       // batched operators: slope / preconditioner spectra in FP16 or BF16
     DevBuf<float> Mhs[2];               // their per-frequency factors [Lh][L]
     int mh_kind[2] = {0, 0};            // tt_precision the half copies hold (0: none)
+    // batched operators on a power-of-two L: the same spectra slot-major, [Lh][P][L], the L frequencies of
+    // every column in bit-reversed order (the order of the column FFT's output); FP32, or FP16 / BF16 with
+    // the factors [Lh][L] in that order.  Built on first use by the batched column kernel.
+    DevBuf<float> Mt32[2];
+    DevBuf<unsigned short> Mht[2];
+    DevBuf<float> Mhst[2];
+    bool mt_ready[2] = {false, false};
+    int mht_kind[2] = {0, 0};
     int tuned_S[2] = {0, 0};            // batched product / preconditioner: frequency split chosen by
     std::vector<const tt_ctx*> tuned_for[2];   // tt_tune_batch for this exact batch (this context first)
     DevBuf<float> Minv32;               // circulant preconditioner spectra [Lh][L][C^2] (general Hermitian packing)
