@@ -806,6 +806,193 @@ __global__ __launch_bounds__(BT, 2) void k_bcol(const BSys* __restrict__ sys, co
 }
 
 // ---------------------------------------------------------------------------
+// Column transforms of length m in {64, 128} by single waves: m = 8 Q, each
+// channel taken by Q lanes of one wave (Q = 8 or 16), eight points a lane.
+// Forward, with n = Q n1 + q and k = k1 + 8 k2:
+//   X[k1 + 8 k2] = sum_q w_Q^{q k2} [w_m^{q k1} sum_{n1} x[Q n1 + q] w_8^{n1 k1}],
+// an 8-point DFT in registers (lane q), a twiddle, a transpose through the
+// channel's own LDS buffer (written and read by lanes of one wave, in order:
+// no workgroup barrier), and the Q-point DFTs over q: in registers for Q = 8;
+// for Q = 16 as two 8-point halves (even and odd q) in a lane pair combined by
+// one radix-2 step across the pair (DPP swap).  Input in natural order, output
+// at bit-reversed positions, both in the padded layout pidx; the inverse runs
+// the same steps backwards (exponent +, unnormalised).
+
+// 8-point DFT in registers, natural order in and out; INV: exponent +
+template <bool INV>
+__device__ __forceinline__ void dft8(c32 (&a)[8]) {
+    constexpr float R = 0.70710678118654752f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const c32 u = cadd(a[i], a[i + 4]), v = csub(a[i], a[i + 4]);
+        a[i] = u;
+        a[i + 4] = v;
+    }
+    // twiddles w_8^i on the second half: (1 - i) R, -i, (-1 - i) R (forward; conjugates inverse)
+    a[5] = INV ? c32{(a[5].x - a[5].y) * R, (a[5].x + a[5].y) * R} : c32{(a[5].x + a[5].y) * R, (a[5].y - a[5].x) * R};
+    a[6] = INV ? mul_pi(a[6]) : mul_mi(a[6]);
+    a[7] = INV ? c32{(-a[7].x - a[7].y) * R, (a[7].x - a[7].y) * R} : c32{(a[7].y - a[7].x) * R, -(a[7].x + a[7].y) * R};
+#pragma unroll
+    for (int b = 0; b < 8; b += 4)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const c32 u = cadd(a[b + i], a[b + i + 2]), v = csub(a[b + i], a[b + i + 2]);
+            a[b + i] = u;
+            a[b + i + 2] = i ? (INV ? mul_pi(v) : mul_mi(v)) : v;
+        }
+#pragma unroll
+    for (int i = 0; i < 8; i += 2) {
+        const c32 u = cadd(a[i], a[i + 1]), v = csub(a[i], a[i + 1]);
+        a[i] = u;
+        a[i + 1] = v;
+    }
+    // bit-reversed to natural order
+    c32 t = a[1];
+    a[1] = a[4];
+    a[4] = t;
+    t = a[3];
+    a[3] = a[6];
+    a[6] = t;
+}
+
+// w_16^j, j < 8 (exponent -): (cos, -sin) of j pi / 8
+__device__ __forceinline__ c32 w16(int j) {
+    constexpr float C1 = 0.92387953251128674f, S1 = 0.38268343236508977f, R = 0.70710678118654752f;
+    switch (j) {
+        case 0: return c32{1.f, 0.f};
+        case 1: return c32{C1, -S1};
+        case 2: return c32{R, -R};
+        case 3: return c32{S1, -C1};
+        case 4: return c32{0.f, -1.f};
+        case 5: return c32{-S1, -C1};
+        case 6: return c32{-R, -R};
+        default: return c32{-C1, -S1};
+    }
+}
+
+// value of the partner lane (lane ^ 1)
+__device__ __forceinline__ c32 swap_pair(c32 v) {
+    return c32{__int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v.x), 0xB1, 0xF, 0xF, false)),
+               __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v.y), 0xB1, 0xF, 0xF, false))};
+}
+
+// orders the LDS accesses of the lanes of one wave (the hardware keeps a
+// wave's LDS operations in order; this keeps the compiler from moving them)
+__device__ __forceinline__ void wave_lds_order() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+
+// Padded index pidx(i) = i + i / 16 of the entries a wave-transform lane
+// touches, written as one base per lane plus compile-time offsets (for
+// i = Q n1 + q and i = Q k1 + j with q, j < Q, and for the bit-reversed output
+// positions), so that the compiler keeps one address register per pattern.
+__device__ __forceinline__ int rev3(int v) { return ((v & 1) << 2) | (v & 2) | ((v >> 2) & 1); }
+
+// Forward transform of C channels of length M in place; threads t < C M / 8
+// take part (the others return at once), there is no workgroup barrier inside.
+// Entries from nin on are zero and are not read.
+template <int M>
+__device__ __forceinline__ void fft_wave_fwd(c32* A, const c32* tws, int C, int L, int nin) {
+    constexpr int Q = M / 8, LQ = Q == 16 ? 4 : 3, MP = M + M / 16;
+    const int t = threadIdx.x;
+    if (t >= C * Q) return;
+    const int q = t & (Q - 1), step = L / M;
+    c32* Ac = A + (t >> LQ) * MP;
+    // pidx(Q n1 + q): Q = 16: 17 n1 + q; Q = 8: 8 n1 + n1 / 2 + q
+    auto row = [](int n1) { return Q == 16 ? 17 * n1 : 8 * n1 + (n1 >> 1); };
+    c32 a[8];
+#pragma unroll
+    for (int n1 = 0; n1 < 8; ++n1) a[n1] = Q * n1 + q < nin ? Ac[q + row(n1)] : c32{0.f, 0.f};
+    dft8<false>(a);
+#pragma unroll
+    for (int k1 = 1; k1 < 8; ++k1) a[k1] = cmulc(a[k1], tws[((q * k1) & (M - 1)) * step]);   // w_M^{q k1}
+    wave_lds_order();
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1) Ac[q + row(k1)] = a[k1];   // transposed: pidx(Q k1 + q)
+    wave_lds_order();
+    if constexpr (Q == 8) {
+        const int k1 = q, rb = rev3(k1);
+        c32* Ar = Ac + row(k1);   // pidx(8 k1 + j) = row(k1) + j
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[j] = Ar[j];
+        dft8<false>(a);
+        wave_lds_order();
+        // X[k1 + 8 k2] at bitrev6 = 8 rev3(k1) + rev3(k2): pidx = 8 rb + rb / 2 + rev3(k2)
+        c32* Ao = Ac + 8 * rb + (rb >> 1);
+#pragma unroll
+        for (int k2 = 0; k2 < 8; ++k2) Ao[rev3(k2)] = a[k2];
+    } else {
+        const int k1 = q >> 1, e = q & 1, rb = rev3(k1);
+        c32* Ar = Ac + 17 * k1 + e;   // pidx(16 k1 + 2 j + e) = 17 k1 + 2 j + e
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[j] = Ar[2 * j];
+        dft8<false>(a);   // e = 0: E[j], e = 1: O[j] (even / odd q)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (e) a[j] = cmul(a[j], w16(j));
+            const c32 r = swap_pair(a[j]);
+            a[j] = e ? csub(r, a[j]) : cadd(a[j], r);   // X[k1 + 8 (j + 8 e)] = E + w O, E - w O
+        }
+        wave_lds_order();
+        // bitrev7(k1 + 8 j + 64 e) = 16 rev3(k1) + 2 rev3(j) + e: pidx = 17 rb + 2 rev3(j) + e
+        c32* Ao = Ac + 17 * rb + e;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) Ao[2 * rev3(j)] = a[j];
+    }
+}
+
+// Inverse transform (exponent +, unnormalised) of C channels of length M in
+// place, bit-reversed positions in, natural order out; as fft_wave_fwd.
+template <int M>
+__device__ __forceinline__ void fft_wave_inv(c32* A, const c32* tws, int C, int L) {
+    constexpr int Q = M / 8, LQ = Q == 16 ? 4 : 3, MP = M + M / 16;
+    const int t = threadIdx.x;
+    if (t >= C * Q) return;
+    const int q = t & (Q - 1), step = L / M;
+    c32* Ac = A + (t >> LQ) * MP;
+    auto row = [](int n1) { return Q == 16 ? 17 * n1 : 8 * n1 + (n1 >> 1); };
+    c32 a[8];
+    if constexpr (Q == 8) {
+        const int k1 = q, rb = rev3(k1);
+        const c32* Ai = Ac + 8 * rb + (rb >> 1);
+#pragma unroll
+        for (int k2 = 0; k2 < 8; ++k2) a[k2] = Ai[rev3(k2)];   // X[k1 + 8 k2]
+        dft8<true>(a);   // Z_{k1}[j], j < 8
+#pragma unroll
+        for (int j = 1; j < 8; ++j) a[j] = cmul(a[j], tws[((j * k1) & (M - 1)) * step]);   // w_M^{-j k1}
+        wave_lds_order();
+        c32* Ar = Ac + row(k1);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) Ar[j] = a[j];
+    } else {
+        const int k1 = q >> 1, e = q & 1, rb = rev3(k1);
+        const c32* Ai = Ac + 17 * rb + e;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[j] = Ai[2 * rev3(j)];   // A = X[k1 + 8 j] (e = 0), B = X[k1 + 8 j + 64] (e = 1)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const c32 r = swap_pair(a[j]);
+            a[j] = e ? cmulc(csub(r, a[j]), w16(j)) : cadd(a[j], r);   // A + B; (A - B) w_16^{-j}
+        }
+        dft8<true>(a);   // Z_{k1}[2 j + e]
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int zq = 2 * j + e;
+            if (zq) a[j] = cmul(a[j], tws[((zq * k1) & (M - 1)) * step]);   // w_M^{-q k1}
+        }
+        wave_lds_order();
+        c32* Ar = Ac + 17 * k1 + e;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) Ar[2 * j] = a[j];
+    }
+    wave_lds_order();
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1) a[k1] = Ac[q + row(k1)];   // Z_{k1}[q]
+    dft8<true>(a);
+    wave_lds_order();
+#pragma unroll
+    for (int n1 = 0; n1 < 8; ++n1) Ac[q + row(n1)] = a[n1];   // x[Q n1 + q]
+}
+
+// ---------------------------------------------------------------------------
 // Column kernel for batches whose every L is a power of two.  There the
 // spectra of a column are kept slot-major with the column's L frequencies in
 // bit-reversed order ([Lh][P][L], built once per system by k_slot_major), so
@@ -900,61 +1087,63 @@ __device__ __forceinline__ void pin2(c32& a, c32& b) {
     asm volatile("" : "+v"(a.x), "+v"(a.y), "+v"(b.x), "+v"(b.y)::"memory");
 }
 
-// All 2G outputs of position p, one thread per position, in place: X_c is read
-// from and Y_c written to pidx(c M + p) (M a multiple of 16, so that index is
-// c (M + M / 16) + pidx(p)); no other thread touches position p.  Slope
-// spectra: real 2x2 blocks (g, g); blocks (lo, hi) stored once and used for
-// (lo, hi) and, conjugated, for (hi, lo).  G and M are compile-time, so every
-// LDS offset is an immediate of one base address.  f: the FP16 factor.
+// Slope spectra, two lanes per position (adjacent lanes of one wave): lane e
+// gives the outputs of component e (x: 0, y: 1) of every sensor.  Of a 2x2
+// block it reads the two values its rows need, at slots o + 2e and o + 2 + 2e
+// (xx, xy for e = 0; xy, yy for e = 1; real blocks (g, g): 3g + e, 3g + 1 + e),
+// so every offset is one per-lane base plus an immediate.  X is read by both
+// lanes before either writes (in program order, one wave: no barrier).
 template <int G, int M, int HALF>
-__device__ __forceinline__ void products_pos(const void* Ms, c32* A, int p, float f) {
+__device__ __forceinline__ void products_pos2(const void* Ms, c32* A, int p, int e, float f) {
     constexpr int MP = M + M / 16, NP = G * (G - 1) / 2;
     c32* Ap = A + (p + (p >> 4));
-    c32 x[2 * G], y[2 * G];
+    c32 x[2 * G], y[G];
 #pragma unroll
     for (int c = 0; c < 2 * G; ++c) x[c] = Ap[c * MP];
-    auto v = [&](int j) { return sdec<HALF>(Ms, j * M + p); };
+    const int pe = p + 2 * e * M;   // value j of this lane's rows at j M + pe (real blocks: j M + p + e M)
+    auto v = [&](int j) { return sdec<HALF>(Ms, j * M + pe); };
+    auto vd = [&](int j) { return sdec<HALF>(Ms, j * M + p + e * M); };
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const float xx = v(3 * g), xy = v(3 * g + 1), yy = v(3 * g + 2);
+        const float s0 = vd(3 * g), s1 = vd(3 * g + 1);
         const c32 a = x[2 * g], b = x[2 * g + 1];
-        y[2 * g] = c32{xx * a.x + xy * b.x, xx * a.y + xy * b.y};
-        y[2 * g + 1] = c32{xy * a.x + yy * b.x, xy * a.y + yy * b.y};
-        pin2(y[2 * g], y[2 * g + 1]);
+        y[g] = c32{s0 * a.x + s1 * b.x, s0 * a.y + s1 * b.y};
+        if (g & 1) pin2(y[g - 1], y[g]);
     }
-    // pairs (lo, hi) in storage order, the next pair's six values loading under this pair's products
-    float cur[6];
+    float cur[4];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) cur[i] = v(3 * G + i);
+    for (int i = 0; i < 4; ++i) cur[i] = v(3 * G + i);
     int lo = 0, hi = 1;
 #pragma unroll
     for (int t = 0; t < NP; ++t) {
-        float nxt[6];
+        float nxt[4];
         if (t + 1 < NP) {
 #pragma unroll
-            for (int i = 0; i < 6; ++i) nxt[i] = v(3 * G + 6 * (t + 1) + i);
+            for (int i = 0; i < 4; ++i) nxt[i] = v(3 * G + 6 * (t + 1) + i);
         }
-        const c32 mxx = c32{cur[0], cur[1]}, mxy = c32{cur[2], cur[3]}, myy = c32{cur[4], cur[5]};
-        y[2 * lo] = cfma(cfma(y[2 * lo], mxx, x[2 * hi]), mxy, x[2 * hi + 1]);
-        y[2 * lo + 1] = cfma(cfma(y[2 * lo + 1], mxy, x[2 * hi]), myy, x[2 * hi + 1]);
-        y[2 * hi] = cfmac(cfmac(y[2 * hi], mxx, x[2 * lo]), mxy, x[2 * lo + 1]);
-        y[2 * hi + 1] = cfmac(cfmac(y[2 * hi + 1], mxy, x[2 * lo]), myy, x[2 * lo + 1]);
-        pin4(y[2 * lo], y[2 * lo + 1], y[2 * hi], y[2 * hi + 1]);
+        const c32 ma = c32{cur[0], cur[1]}, mb = c32{cur[2], cur[3]};
+        y[lo] = cfma(cfma(y[lo], ma, x[2 * hi]), mb, x[2 * hi + 1]);
+        y[hi] = cfmac(cfmac(y[hi], ma, x[2 * lo]), mb, x[2 * lo + 1]);
+        pin2(y[lo], y[hi]);
         if (t + 1 < NP) {
 #pragma unroll
-            for (int i = 0; i < 6; ++i) cur[i] = nxt[i];
+            for (int i = 0; i < 4; ++i) cur[i] = nxt[i];
         }
         if (++hi == G) {
             ++lo;
             hi = lo + 1;
         }
     }
+    wave_lds_order();
 #pragma unroll
-    for (int c = 0; c < 2 * G; ++c) Ap[c * MP] = HALF == 1 ? c32{y[c].x * f, y[c].y * f} : y[c];
+    for (int g = 0; g < G; ++g) Ap[(2 * g + e) * MP] = HALF == 1 ? c32{y[g].x * f, y[g].y * f} : y[g];
 }
 
-// the same for the preconditioner's general Hermitian C x C blocks (C^2 reals;
-// the C (C - 1) / 2 entries above the diagonal in storage order, four at a time)
+// All C outputs of position p for the preconditioner's general Hermitian C x C
+// blocks (C^2 reals; the C (C - 1) / 2 entries above the diagonal in storage
+// order), one thread per position, in place: X_c read from and Y_c written to
+// pidx(c M + p) = c (M + M / 16) + pidx(p) (M a multiple of 16); G and M
+// compile-time, so every LDS offset is an immediate.  f: the FP16 factor.
 template <int C, int M, int HALF>
 __device__ __forceinline__ void products_pos_herm(const void* Ms, c32* A, int p, float f) {
     constexpr int MP = M + M / 16, NE = C * (C - 1) / 2;
@@ -992,15 +1181,23 @@ __device__ __forceinline__ void products_pos_herm(const void* Ms, c32* A, int p,
 template <int PACK, int HALF>
 __device__ __forceinline__ bool products_fixed(const void* Ms, c32* A, const float* fac, int m, int G) {
     if ((m != 64 && m != 128) || G < 4 || G > 6) return false;
-    for (int p = threadIdx.x; p < m; p += BT) {
-        const float f = HALF == 1 ? fac[p] : 1.f;
-#define TT_POS(g, mm)                                                            \
-    if (G == g && m == mm) {                                                     \
-        if constexpr (PACK == 0) products_pos<g, mm, HALF>(Ms, A, p, f);          \
-        else products_pos_herm<2 * g, mm, HALF>(Ms, A, p, f);                     \
-    }
-        TT_POS(4, 64) TT_POS(5, 64) TT_POS(6, 64) TT_POS(4, 128) TT_POS(5, 128) TT_POS(6, 128)
+    if constexpr (PACK == 0) {   // two lanes per position
+        const int p = threadIdx.x >> 1, e = threadIdx.x & 1;
+        if (p < m) {
+            const float f = HALF == 1 ? fac[p] : 1.f;
+#define TT_POS(g, mm) \
+    if (G == g && m == mm) products_pos2<g, mm, HALF>(Ms, A, p, e, f);
+            TT_POS(4, 64) TT_POS(5, 64) TT_POS(6, 64) TT_POS(4, 128) TT_POS(5, 128) TT_POS(6, 128)
 #undef TT_POS
+        }
+    } else {
+        for (int p = threadIdx.x; p < m; p += BT) {
+            const float f = HALF == 1 ? fac[p] : 1.f;
+#define TT_POS(g, mm) \
+    if (G == g && m == mm) products_pos_herm<2 * g, mm, HALF>(Ms, A, p, f);
+            TT_POS(4, 64) TT_POS(5, 64) TT_POS(6, 64) TT_POS(4, 128) TT_POS(5, 128) TT_POS(6, 128)
+#undef TT_POS
+        }
     }
     return true;
 }
@@ -1040,36 +1237,41 @@ __global__ __launch_bounds__(BT, 4) void k_bcolt(const BSys* __restrict__ sys, c
     char* Ms = smem_raw + offM;
 
     // direct loads of item (column cl, share hh) of system s: P runs of m values,
-    // 16 bytes a lane, chunk c of the item landing at Ms + 16 c.  Issued round by
-    // round (one direct load per wave, BT / 64 KB per round: chunk c0 + r BT,
-    // the same position BT / cpr rows on) between the passes of the transforms,
-    // so that the transfer is spread over the time to the next products.
-    const E* dg = nullptr;
-    const char* dl = nullptr;
-    int dc = 0, dchunks = 0;
-    size_t dstep = 0;
-    auto dma_begin = [&](const BSys& s, int cl, int hh) {
+    // 16 bytes a lane, chunk c of the item landing at Ms + 16 c, issued by the
+    // waves dw0 .. BT / 64 - 1 round by round (one direct load per wave per
+    // round: chunk (r nd + w - dw0) 64 + lane, the same position nd 64 / cpr
+    // rows on, nd = BT / 64 - dw0).  With the single-wave transforms dw0 is the
+    // first wave without a channel: those waves issue the whole item at once,
+    // under the others' inverse transform; otherwise every wave issues, a few
+    // rounds between the passes of the transforms.  The state is uniform but for
+    // one byte offset per lane.
+    const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+    const char* dbase = nullptr;
+    unsigned doff = 0, dstep = 0;
+    int dround = 0, dchunks = 0, dw0 = 0, dnd = BT / 64;
+    auto dma_begin = [&](const BSys& s, int cl, int hh, int first_wave) {
         const int f2 = cl - s.col0, L = s.L, m = L >> sh, P = PACK ? 4 * s.G * s.G : 3 * s.G * s.G;
         const int run = bitrev_split(hh, sh) * m, lcpr = __builtin_ctz(m / PER);
-        const int c0 = wave * 64 + lane, j0 = c0 >> lcpr, pp = (c0 - (j0 << lcpr)) * PER;
-        dg = (HALF ? (const E*)s.Mht : (const E*)s.Mt) + ((size_t)f2 * P * L + run + (size_t)j0 * L + pp);
-        dstep = (size_t)(BT >> lcpr) * L;
-        dl = Ms + wave * 1024;
-        dc = c0;
-        dchunks = P * m / PER;
+        dw0 = ((BT / 64 - first_wave) * 64) % (m / PER) ? 0 : first_wave;   // whole rows per round
+        dnd = BT / 64 - dw0;
+        const int t = (wave_u - dw0) * 64 + lane, j0 = t >> lcpr, pp = (t - (j0 << lcpr)) * PER;
+        dbase = (const char*)((HALF ? (const E*)s.Mht : (const E*)s.Mt) + ((size_t)f2 * P * L + run));
+        doff = (unsigned)(((size_t)j0 * L + pp) * sizeof(E));
+        dstep = (unsigned)((size_t)((dnd * 64) >> lcpr) * L * sizeof(E));
+        dround = 0;
+        dchunks = wave_u >= dw0 ? P * m / PER : 0;
         if constexpr (HALF == 1) {   // the m factors of these frequencies
             const float* fs = s.Mhst + ((size_t)f2 * L + run);
-            for (int c = c0; c - lane < m / 4; c += BT)
+            for (int c = threadIdx.x; c - lane < m / 4; c += BT)
                 if (c < m / 4) dma16(fs + 4 * c, fac + 4 * (size_t)c);
         }
     };
     auto dma_rounds = [&](int k) {
         for (int i = 0; i < k; ++i) {
-            if (dc - lane >= dchunks) return;   // uniform over the wave
-            if (dc < dchunks) dma16(dg, dl);
-            dc += BT;
-            dg += dstep;
-            dl += BT * 16;
+            const int cw = (dround * dnd + wave_u - dw0) * 64;   // first chunk of this wave's load in this round
+            if (wave_u < dw0 || cw >= dchunks) return;
+            if (cw + lane < dchunks) dma16(dbase + doff + (size_t)dround * dstep, Ms + (size_t)cw * 16);
+            ++dround;
         }
     };
     auto hook = [&]() { dma_rounds(2); };
@@ -1085,7 +1287,7 @@ __global__ __launch_bounds__(BT, 4) void k_bcolt(const BSys* __restrict__ sys, c
             tp[i] = gload(s0.T + (size_t)f20 * Cn0 + (idx < Cn0 ? idx : 0));
         }
         __builtin_amdgcn_s_waitcnt(WAIT_VM0);   // (the compiler then counts no load pending at the first fold)
-        dma_begin(s0, col, h);
+        dma_begin(s0, col, h, 0);
         dma_rounds(1 << 20);
     }
     int qn = q + gridDim.x;
@@ -1145,7 +1347,10 @@ __global__ __launch_bounds__(BT, 4) void k_bcolt(const BSys* __restrict__ sys, c
             if (colnn < total_cols) sinn = col_sys[colnn];
         }
         __syncthreads();
-        fft_dif<BT, true>(A, tws, C, bits, L, n < m ? n : m, hook);   // X at bit-reversed positions
+        // X at bit-reversed positions; the waves without a channel issue their direct loads meanwhile
+        if (m == 128) fft_wave_fwd<128>(A, tws, C, L, n < m ? n : m);
+        else if (m == 64) fft_wave_fwd<64>(A, tws, C, L, n < m ? n : m);
+        else fft_dif<BT, true>(A, tws, C, bits, L, n < m ? n : m, hook);
         dma_rounds(1 << 20);                     // the rest of this item's spectra
         __builtin_amdgcn_s_waitcnt(WAIT_VM0);   // this wave's direct loads (and the next input column) are done
         __syncthreads();                         // ... and every other wave's
@@ -1175,8 +1380,9 @@ __global__ __launch_bounds__(BT, 4) void k_bcolt(const BSys* __restrict__ sys, c
         }
         __syncthreads();   // every read of the spectra and of X is done
         if (more) {
-            dma_begin(sn, coln, hn);
-            dma_rounds(2);
+            const int fw = (m == 64 || m == 128) ? (C * (m / 8) + 63) / 64 : 0;   // waves of the wave transforms
+            dma_begin(sn, coln, hn, fw < BT / 64 ? fw : 0);
+            dma_rounds(dw0 ? (1 << 20) : 2);
         }
         if (!fixed) {
             Walk wk(m);
@@ -1193,7 +1399,14 @@ __global__ __launch_bounds__(BT, 4) void k_bcolt(const BSys* __restrict__ sys, c
         }
 
         // this item's share of the inverse column transform, rows a < n
-        fft_dit_inv<BT, true>(A, tws, C, bits, L, hook);
+        if (m == 128 || m == 64) {
+            if (m == 128) fft_wave_inv<128>(A, tws, C, L);
+            else fft_wave_inv<64>(A, tws, C, L);
+            dma_rounds(4);
+            __syncthreads();
+        } else {
+            fft_dit_inv<BT, true>(A, tws, C, bits, L, hook);
+        }
         {
             c32* Uo = s.U + ((size_t)f2 * S + h) * C * n;
             Walk wk(n);
