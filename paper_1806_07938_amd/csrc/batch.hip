@@ -355,6 +355,93 @@ struct Walk {
     }
 };
 
+// w_16^j, j < 8 (exponent -): (cos, -sin) of j pi / 8
+__device__ __forceinline__ c32 w16(int j) {
+    constexpr float C1 = 0.92387953251128674f, S1 = 0.38268343236508977f, R = 0.70710678118654752f;
+    switch (j) {
+        case 0: return c32{1.f, 0.f};
+        case 1: return c32{C1, -S1};
+        case 2: return c32{R, -R};
+        case 3: return c32{S1, -C1};
+        case 4: return c32{0.f, -1.f};
+        case 5: return c32{-S1, -C1};
+        case 6: return c32{-R, -R};
+        default: return c32{-C1, -S1};
+    }
+}
+
+// orders the LDS accesses of the lanes of one wave (the hardware keeps a
+// wave's LDS operations in order; this keeps the compiler from moving them)
+__device__ __forceinline__ void wave_lds_order() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+
+// w_16^j, j < 16
+__device__ __forceinline__ c32 w16f(int j) {
+    const c32 w = w16(j & 7);
+    return (j & 8) ? c32{-w.x, -w.y} : w;
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(c32& a0, c32& a1, c32& a2, c32& a3) {
+    const c32 s02 = cadd(a0, a2), d02 = csub(a0, a2), s13 = cadd(a1, a3), d13 = csub(a1, a3);
+    const c32 r = INV ? mul_pi(d13) : mul_mi(d13);
+    a0 = cadd(s02, s13);
+    a1 = cadd(d02, r);
+    a2 = csub(s02, s13);
+    a3 = csub(d02, r);
+}
+
+// 16-point DFT in registers, natural order in and out (n = 4 n1 + n2,
+// k = k1 + 4 k2: 4-point DFTs over n1, twiddles w_16^{n2 k1}, 4-point DFTs
+// over n2); INV: exponent +
+template <bool INV>
+__device__ __forceinline__ void dft16(c32 (&a)[16]) {
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4<INV>(a[n2], a[4 + n2], a[8 + n2], a[12 + n2]);   // slot 4 k1 + n2
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1)
+#pragma unroll
+        for (int n2 = 1; n2 < 4; ++n2) {
+            const c32 w = w16f(n2 * k1);
+            a[4 * k1 + n2] = INV ? cmulc(a[4 * k1 + n2], w) : cmul(a[4 * k1 + n2], w);
+        }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4<INV>(a[4 * k1], a[4 * k1 + 1], a[4 * k1 + 2], a[4 * k1 + 3]);   // slot 4 k1 + k2
+    c32 t[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) t[k1 + 4 * k2] = a[4 * k1 + k2];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) a[i] = t[i];
+}
+
+// 256-point DFT of one row by the 16 lanes q of a group of one wave: the row
+// at R in the padded layout pidx (entry i at i + i / 16), natural order in and
+// out; n = 16 n1 + q, k = k1 + 16 k2: 16-point DFTs over n1 in registers,
+// twiddles w_256^{q k1} (tws: the 256 twiddles of exp(+2 pi i k / 256)), a
+// transpose through R, 16-point DFTs over q.  INV: exponent +.
+template <bool INV>
+__device__ __forceinline__ void fft256_group(c32* R, const c32* tws, int q) {
+    c32 a[16];
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) a[n1] = R[17 * n1 + q];   // pidx(16 n1 + q)
+    dft16<INV>(a);
+#pragma unroll
+    for (int k1 = 1; k1 < 16; ++k1) a[k1] = INV ? cmul(a[k1], tws[q * k1]) : cmulc(a[k1], tws[q * k1]);
+    wave_lds_order();
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) R[17 * k1 + q] = a[k1];   // C_q[k1] at pidx(16 k1 + q)
+    wave_lds_order();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) a[j] = R[17 * q + j];   // lane q as k1: C_j[q]
+    dft16<INV>(a);
+    wave_lds_order();
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) R[q + 17 * k2] = a[k2];   // Z[q + 16 k2] at pidx(q + 16 k2)
+}
+
+constexpr int RS256 = 272;   // row stride of the L = 256 row transforms (pidx(255) = 270)
+
 // Row phases: grid (row tile, system).  A workgroup takes consecutive rows a
 // of one channel c, so that for every f2 its entries of T and U are contiguous
 // in memory; tiles beyond a system's channels exit.  When L is a power of two
@@ -368,11 +455,49 @@ __host__ __device__ inline bool is_pow2(int v) { return (v & (v - 1)) == 0; }
 __host__ __device__ inline int row_tile_fwd(int L) { return is_pow2(L) ? (RLDS / 8 / L < 16 ? RLDS / 8 / L : 16) : 16; }
 __host__ __device__ inline int row_tile_inv(int L) { return is_pow2(L) ? (RLDS / 8 / L < 16 ? RLDS / 8 / L : 16) : 8; }
 
+// L = 256: a workgroup takes 16 consecutive rows a of one channel c, each row
+// transformed by 16 lanes of one wave (fft256_group: no workgroup barrier
+// inside the transform).  Each real row is transformed on its own (a complex
+// transform with zero imaginary part): packing two channels into the real and
+// imaginary parts of one transform would halve the work but leaks each
+// channel's rounding into the other (errors of order u |X_other|, not
+// u |X_own|), which stalls CG on the least damped systems.
+static_assert(16 * RS256 * sizeof(c32) + 256 * sizeof(c32) <= RLDS + 1024 * sizeof(c32), "row LDS");
+
 __global__ __launch_bounds__(RBT) void k_brow_fwd(const BSys* __restrict__ sys) {
     __shared__ __align__(16) char lds[RLDS + 1024 * sizeof(c32)];
     c32* tws = reinterpret_cast<c32*>(lds + RLDS);
     const BSys s = sys[blockIdx.y];
     const int n = s.n, L = s.L, Lh = L / 2 + 1, C = 2 * s.G;
+    if (L == 256) {
+        const int tiles16 = (n + 15) / 16, c = blockIdx.x / tiles16, a0 = (blockIdx.x - c * tiles16) * 16;
+        if (c >= C) return;
+        c32* A = reinterpret_cast<c32*>(lds);   // 16 rows of RS256
+        c32* tw = A + 16 * RS256;
+        for (int k = threadIdx.x; k < 256; k += RBT) tw[k] = s.tw[k];
+        const int r = threadIdx.x >> 4, q = threadIdx.x & 15, a = a0 + r;
+        c32* R = A + r * RS256;
+        const float* xc = s.x + (long)c * s.n_vs;
+#pragma unroll
+        for (int n1 = 0; n1 < 16; ++n1) {
+            const int b = 16 * n1 + q;
+            float v = 0.f;
+            if (a < n && b < n) {
+                const int vi = s.vmap[a * n + b];
+                if (vi >= 0) v = xc[vi];
+            }
+            R[17 * n1 + q] = c32{v, 0.f};   // pidx(b)
+        }
+        __syncthreads();   // the twiddles
+        fft256_group<false>(R, tw, q);
+        __syncthreads();
+        const int rows = min(16, n - a0);
+        for (int idx = threadIdx.x; idx < Lh * 16; idx += RBT) {
+            const int f = idx >> 4, rr = idx & 15;
+            if (rr < rows) s.T[((long)f * C + c) * n + a0 + rr] = A[rr * RS256 + f + (f >> 4)];
+        }
+        return;
+    }
     const int rt = row_tile_fwd(L), tiles = (n + rt - 1) / rt;
     const int c = blockIdx.x / tiles, a0 = (blockIdx.x - c * tiles) * rt;
     if (c >= C) return;
@@ -424,6 +549,55 @@ __global__ __launch_bounds__(RBT) void k_brow_inv(const BSys* __restrict__ sys, 
     c32* tws = reinterpret_cast<c32*>(lds + RLDS);
     const BSys s = sys[blockIdx.y];
     const int n = s.n, L = s.L, Lh = L / 2 + 1, C = 2 * s.G;
+    if (L == 256) {
+        const int tiles16 = (n + 15) / 16, c = blockIdx.x / tiles16, a0 = (blockIdx.x - c * tiles16) * 16;
+        if (c >= C) return;
+        c32* A = reinterpret_cast<c32*>(lds);   // 16 rows of RS256
+        c32* tw = A + 16 * RS256;
+        for (int k = threadIdx.x; k < 256; k += RBT) tw[k] = s.tw[k];
+        const int rows = min(16, n - a0);
+        // Z[f] = U_c[f] and Z[L - f] = conj U_c[f] (the S column shares summed; real part only at f = 0
+        // and L / 2): the Hermitian extension, whose transform is real
+        for (int idx = threadIdx.x; idx < Lh * 16; idx += RBT) {
+            const int f = idx >> 4, rr = idx & 15;
+            c32 u = c32{0.f, 0.f};
+            if (rr < rows)
+                for (int h = 0; h < S; ++h) {
+                    const c32 v = s.U[(((long)f * S + h) * C + c) * n + a0 + rr];
+                    u.x += v.x;
+                    u.y += v.y;
+                }
+            c32* Rr = A + rr * RS256;
+            if (f == 0 || f == 128) {
+                Rr[f + (f >> 4)] = c32{u.x, 0.f};
+            } else {
+                const int fc = 256 - f;
+                Rr[f + (f >> 4)] = u;
+                Rr[fc + (fc >> 4)] = c32{u.x, -u.y};
+            }
+        }
+        __syncthreads();
+        const int r = threadIdx.x >> 4, q = threadIdx.x & 15, a = a0 + r;
+        c32* R = A + r * RS256;
+        fft256_group<true>(R, tw, q);
+        // outputs b = q + 16 k of row a: written by this lane group (one wave, in order)
+        if (a < n) {
+            const float inv = 1.f / (256.f * 256.f);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int b = q + 16 * k;
+                if (b >= n) break;
+                const int v = s.vmap[a * n + b];
+                if (v < 0) continue;
+                const long i = (long)c * s.n_vs + v;
+                float out = R[b + k].x * inv;   // pidx(b) = b + b / 16
+                if (s.noise) out += s.noise[i] * s.x[i];
+                if (s.nxy) out += s.nxy[(long)(c >> 1) * s.n_vs + v] * s.x[(long)(c ^ 1) * s.n_vs + v];
+                s.y[i] = out;
+            }
+        }
+        return;
+    }
     const int rt = row_tile_inv(L), tiles = (n + rt - 1) / rt;
     const int c = blockIdx.x / tiles, a0 = (blockIdx.x - c * tiles) * rt;
     if (c >= C) return;
@@ -855,30 +1029,11 @@ __device__ __forceinline__ void dft8(c32 (&a)[8]) {
     a[6] = t;
 }
 
-// w_16^j, j < 8 (exponent -): (cos, -sin) of j pi / 8
-__device__ __forceinline__ c32 w16(int j) {
-    constexpr float C1 = 0.92387953251128674f, S1 = 0.38268343236508977f, R = 0.70710678118654752f;
-    switch (j) {
-        case 0: return c32{1.f, 0.f};
-        case 1: return c32{C1, -S1};
-        case 2: return c32{R, -R};
-        case 3: return c32{S1, -C1};
-        case 4: return c32{0.f, -1.f};
-        case 5: return c32{-S1, -C1};
-        case 6: return c32{-R, -R};
-        default: return c32{-C1, -S1};
-    }
-}
-
 // value of the partner lane (lane ^ 1)
 __device__ __forceinline__ c32 swap_pair(c32 v) {
     return c32{__int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v.x), 0xB1, 0xF, 0xF, false)),
                __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v.y), 0xB1, 0xF, 0xF, false))};
 }
-
-// orders the LDS accesses of the lanes of one wave (the hardware keeps a
-// wave's LDS operations in order; this keeps the compiler from moving them)
-__device__ __forceinline__ void wave_lds_order() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
 
 // Padded index pidx(i) = i + i / 16 of the entries a wave-transform lane
 // touches, written as one base per lane plus compile-time offsets (for

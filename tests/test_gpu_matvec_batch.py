@@ -84,7 +84,8 @@ def test_batch_with_2x2_noise():
     say("matvec batch with 2x2 noise blocks")
     ctxs, refs, xd = [], [], []
     rng = np.random.default_rng(6)
-    for case, xy in ((EVEN[0], True), (("lgs3_10x10", 20), True), (EVEN[1], False)):
+    l256 = dict(n=7, n_gs=4, lgs=True, n_layer=2, seed=8, pad_L=256)   # the packed-channel L = 256 row transforms
+    for case, xy in ((EVEN[0], True), (("lgs3_10x10", 20), True), (EVEN[1], False), (l256, True)):
         wl = _wl(case)
         var, cxy = W.elongated_noise(wl)
         ctx = Context(0)

@@ -130,7 +130,10 @@ def test_uneven_64_system_batch(uneven):
     its FP64 true residual, and the first four (the systems the oracle operators
     of this module belong to) by the oracle's operator.  Right-hand sides are
     seeded white noise (the solver's correctness does not depend on their
-    statistics; the benchmark uses measured frames)."""
+    statistics; the benchmark uses measured frames).  The least damped system
+    (uneven_62: 8 LGS, noise variance 0.016 rad^2) needs 11-20 thousand plain-CG
+    iterations for such right-hand sides, a count that moves by thousands with
+    the rounding of the FP32 product, so the cap is well above it."""
     import torch
     from paper_1806_07938_amd import solve_batch
     from paper_1806_07938_amd.tt import SOLVER_BATCHED
@@ -142,7 +145,7 @@ def test_uneven_64_system_batch(uneven):
     S = [rng.standard_normal(wl.n_slopes).astype(np.float32) for wl in wls]
     tol = 1e-6
     zs, _, infos, st = solve_batch([c for c, k in systems], [torch.tensor(s, device=dev) for s in S], tol=tol,
-                                   solver=SOLVER_BATCHED)
+                                   solver=SOLVER_BATCHED, max_iter=60000)
     its = [inf.iterations for inf in infos]
     say(f"64 uneven systems: status {st}, iterations {min(its)}-{max(its)}, max rel residual "
         f"{max(inf.rel_residual for inf in infos):.2e}")
