@@ -132,9 +132,9 @@ def cpu_baseline(wl, frames, tol):
 
 def batch_traffic_record():
     """HBM traffic of the batched column kernel measured with rocprofv3 counters
-    (profiles/k_bcol_*_traffic.md), valid only while its source is unchanged."""
+    (profiles/k_bcolt_*_traffic.md), valid only while its source is unchanged."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_bcol_f32_74x74_L256_x64_traffic.md")
+    path = os.path.join(ROOT, "profiles", "k_bcolt_f32_74x74_L256_x64_traffic.md")
     src = os.path.join(ROOT, "paper_1806_07938_amd", "csrc", "batch.hip")
     try:
         rec = {}

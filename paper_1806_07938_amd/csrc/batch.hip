@@ -470,36 +470,31 @@ __global__ __launch_bounds__(RBT) void k_brow_fwd(const BSys* __restrict__ sys) 
     const BSys s = sys[blockIdx.y];
     const int n = s.n, L = s.L, Lh = L / 2 + 1, C = 2 * s.G;
     if (L == 256) {
-        const int c = blockIdx.x;
+        const int tiles16 = (n + 15) / 16, c = blockIdx.x / tiles16, a0 = (blockIdx.x - c * tiles16) * 16;
         if (c >= C) return;
         c32* A = reinterpret_cast<c32*>(lds);   // 16 rows of RS256
         c32* tw = A + 16 * RS256;
         for (int k = threadIdx.x; k < 256; k += RBT) tw[k] = s.tw[k];
-        const int r = threadIdx.x >> 4, q = threadIdx.x & 15;
+        const int r = threadIdx.x >> 4, q = threadIdx.x & 15, a = a0 + r;
         c32* R = A + r * RS256;
         const float* xc = s.x + (long)c * s.n_vs;
-        for (int a0 = 0; a0 < n; a0 += 16) {   // the channel's row tiles in turn: T rows of 128 B shared by
-                                              // neighbouring tiles meet in this XCD's L2
-            const int a = a0 + r;
-            if (a0) __syncthreads();   // the previous tile's reads of A are done
 #pragma unroll
-            for (int n1 = 0; n1 < 16; ++n1) {
-                const int b = 16 * n1 + q;
-                float v = 0.f;
-                if (a < n && b < n) {
-                    const int vi = s.vmap[a * n + b];
-                    if (vi >= 0) v = xc[vi];
-                }
-                R[17 * n1 + q] = c32{v, 0.f};   // pidx(b)
+        for (int n1 = 0; n1 < 16; ++n1) {
+            const int b = 16 * n1 + q;
+            float v = 0.f;
+            if (a < n && b < n) {
+                const int vi = s.vmap[a * n + b];
+                if (vi >= 0) v = xc[vi];
             }
-            __syncthreads();   // the twiddles (first tile)
-            fft256_group<false>(R, tw, q);
-            __syncthreads();
-            const int rows = min(16, n - a0);
-            for (int idx = threadIdx.x; idx < Lh * 16; idx += RBT) {
-                const int f = idx >> 4, rr = idx & 15;
-                if (rr < rows) s.T[((long)f * C + c) * n + a0 + rr] = A[rr * RS256 + f + (f >> 4)];
-            }
+            R[17 * n1 + q] = c32{v, 0.f};   // pidx(b)
+        }
+        __syncthreads();   // the twiddles
+        fft256_group<false>(R, tw, q);
+        __syncthreads();
+        const int rows = min(16, n - a0);
+        for (int idx = threadIdx.x; idx < Lh * 16; idx += RBT) {
+            const int f = idx >> 4, rr = idx & 15;
+            if (rr < rows) s.T[((long)f * C + c) * n + a0 + rr] = A[rr * RS256 + f + (f >> 4)];
         }
         return;
     }
@@ -555,54 +550,50 @@ __global__ __launch_bounds__(RBT) void k_brow_inv(const BSys* __restrict__ sys, 
     const BSys s = sys[blockIdx.y];
     const int n = s.n, L = s.L, Lh = L / 2 + 1, C = 2 * s.G;
     if (L == 256) {
-        const int c = blockIdx.x;
+        const int tiles16 = (n + 15) / 16, c = blockIdx.x / tiles16, a0 = (blockIdx.x - c * tiles16) * 16;
         if (c >= C) return;
         c32* A = reinterpret_cast<c32*>(lds);   // 16 rows of RS256
         c32* tw = A + 16 * RS256;
         for (int k = threadIdx.x; k < 256; k += RBT) tw[k] = s.tw[k];
-        for (int a0 = 0; a0 < n; a0 += 16) {   // the channel's row tiles in turn (U rows of 128 B shared by
-                                              // neighbouring tiles meet in this XCD's L2)
-            if (a0) __syncthreads();   // the previous tile's reads of A are done
-            const int rows = min(16, n - a0);
-            // Z[f] = U_c[f] and Z[L - f] = conj U_c[f] (the S column shares summed; real part only at f = 0
-            // and L / 2): the Hermitian extension, whose transform is real
-            for (int idx = threadIdx.x; idx < Lh * 16; idx += RBT) {
-                const int f = idx >> 4, rr = idx & 15;
-                c32 u = c32{0.f, 0.f};
-                if (rr < rows)
-                    for (int h = 0; h < S; ++h) {
-                        const c32 v = s.U[(((long)f * S + h) * C + c) * n + a0 + rr];
-                        u.x += v.x;
-                        u.y += v.y;
-                    }
-                c32* Rr = A + rr * RS256;
-                if (f == 0 || f == 128) {
-                    Rr[f + (f >> 4)] = c32{u.x, 0.f};
-                } else {
-                    const int fc = 256 - f;
-                    Rr[f + (f >> 4)] = u;
-                    Rr[fc + (fc >> 4)] = c32{u.x, -u.y};
+        const int rows = min(16, n - a0);
+        // Z[f] = U_c[f] and Z[L - f] = conj U_c[f] (the S column shares summed; real part only at f = 0
+        // and L / 2): the Hermitian extension, whose transform is real
+        for (int idx = threadIdx.x; idx < Lh * 16; idx += RBT) {
+            const int f = idx >> 4, rr = idx & 15;
+            c32 u = c32{0.f, 0.f};
+            if (rr < rows)
+                for (int h = 0; h < S; ++h) {
+                    const c32 v = s.U[(((long)f * S + h) * C + c) * n + a0 + rr];
+                    u.x += v.x;
+                    u.y += v.y;
                 }
+            c32* Rr = A + rr * RS256;
+            if (f == 0 || f == 128) {
+                Rr[f + (f >> 4)] = c32{u.x, 0.f};
+            } else {
+                const int fc = 256 - f;
+                Rr[f + (f >> 4)] = u;
+                Rr[fc + (fc >> 4)] = c32{u.x, -u.y};
             }
-            __syncthreads();
-            const int r = threadIdx.x >> 4, q = threadIdx.x & 15, a = a0 + r;
-            c32* R = A + r * RS256;
-            fft256_group<true>(R, tw, q);
-            // outputs b = q + 16 k of row a: written by this lane group (one wave, in order)
-            if (a < n) {
-                const float inv = 1.f / (256.f * 256.f);
+        }
+        __syncthreads();
+        const int r = threadIdx.x >> 4, q = threadIdx.x & 15, a = a0 + r;
+        c32* R = A + r * RS256;
+        fft256_group<true>(R, tw, q);
+        // outputs b = q + 16 k of row a: written by this lane group (one wave, in order)
+        if (a < n) {
+            const float inv = 1.f / (256.f * 256.f);
 #pragma unroll
-                for (int k = 0; k < 16; ++k) {
-                    const int b = q + 16 * k;
-                    if (b >= n) break;
-                    const int v = s.vmap[a * n + b];
-                    if (v < 0) continue;
-                    const long i = (long)c * s.n_vs + v;
-                    float out = R[b + k].x * inv;   // pidx(b) = b + b / 16
-                    if (s.noise) out += s.noise[i] * s.x[i];
-                    if (s.nxy) out += s.nxy[(long)(c >> 1) * s.n_vs + v] * s.x[(long)(c ^ 1) * s.n_vs + v];
-                    s.y[i] = out;
-                }
+            for (int k = 0; k < 16; ++k) {
+                const int b = q + 16 * k;
+                if (b >= n) break;
+                const int v = s.vmap[a * n + b];
+                if (v < 0) continue;
+                const long i = (long)c * s.n_vs + v;
+                float out = R[b + k].x * inv;   // pidx(b) = b + b / 16
+                if (s.noise) out += s.noise[i] * s.x[i];
+                if (s.nxy) out += s.nxy[(long)(c >> 1) * s.n_vs + v] * s.x[(long)(c ^ 1) * s.n_vs + v];
+                s.y[i] = out;
             }
         }
         return;
@@ -1103,10 +1094,18 @@ __device__ __forceinline__ void fft_wave_fwd(c32* A, const c32* tws, int C, int 
     }
 }
 
-// Inverse transform (exponent +, unnormalised) of C channels of length M in
-// place, bit-reversed positions in, natural order out; as fft_wave_fwd.
-template <int M>
-__device__ __forceinline__ void fft_wave_inv(c32* A, const c32* tws, int C, int L) {
+// Inverse transform (exponent +, unnormalised) of C channels of length M,
+// bit-reversed positions in; output x[a] of channel c goes to out(c, a, x)
+// from the registers of the lane that computes it (natural order in the
+// channel's buffer when out is WriteBack); as fft_wave_fwd.
+struct WriteBack {
+    c32* A;
+    int mp;   // channel stride of the padded buffer
+    __device__ void operator()(int c, int a, c32 v) const { A[c * mp + a + (a >> 4)] = v; }
+};
+
+template <int M, typename Out>
+__device__ __forceinline__ void fft_wave_inv(c32* A, const c32* tws, int C, int L, Out out) {
     constexpr int Q = M / 8, LQ = Q == 16 ? 4 : 3, MP = M + M / 16;
     const int t = threadIdx.x;
     if (t >= C * Q) return;
@@ -1152,8 +1151,9 @@ __device__ __forceinline__ void fft_wave_inv(c32* A, const c32* tws, int C, int 
     for (int k1 = 0; k1 < 8; ++k1) a[k1] = Ac[q + row(k1)];   // Z_{k1}[q]
     dft8<true>(a);
     wave_lds_order();
+    const int c = t >> LQ;
 #pragma unroll
-    for (int n1 = 0; n1 < 8; ++n1) Ac[q + row(n1)] = a[n1];   // x[Q n1 + q]
+    for (int n1 = 0; n1 < 8; ++n1) out(c, Q * n1 + q, a[n1]);   // x[Q n1 + q]
 }
 
 // ---------------------------------------------------------------------------
@@ -1563,16 +1563,31 @@ __global__ __launch_bounds__(BT, 4) void k_bcolt(const BSys* __restrict__ sys, c
         }
 
         // this item's share of the inverse column transform, rows a < n
-        if (m == 128 || m == 64) {
-            if (m == 128) fft_wave_inv<128>(A, tws, C, L);
-            else fft_wave_inv<64>(A, tws, C, L);
+        c32* Uo = s.U + ((size_t)f2 * S + h) * C * n;
+        if (PACK == 0 && (m == 128 || m == 64) && n <= m) {
+            // rows a < n <= m straight from the transform's registers (no fold to undo)
+            auto out = [&](int c, int a, c32 v) {
+                if (a < n) {
+                    if (h) {
+                        int hw = h * a;
+                        if (hw >= L) hw -= L;
+                        v = cmul(v, tws[hw]);   // w_L^{-h a}
+                    }
+                    gstore(Uo + c * n + a, v);
+                }
+            };
+            if (m == 128) fft_wave_inv<128>(A, tws, C, L, out);
+            else fft_wave_inv<64>(A, tws, C, L, out);
             dma_rounds(4);
-            __syncthreads();
         } else {
-            fft_dit_inv<BT, true>(A, tws, C, bits, L, hook);
-        }
-        {
-            c32* Uo = s.U + ((size_t)f2 * S + h) * C * n;
+            if (m == 128 || m == 64) {
+                if (m == 128) fft_wave_inv<128>(A, tws, C, L, WriteBack{A, 128 + 8});
+                else fft_wave_inv<64>(A, tws, C, L, WriteBack{A, 64 + 4});
+                dma_rounds(4);
+                __syncthreads();
+            } else {
+                fft_dit_inv<BT, true>(A, tws, C, bits, L, hook);
+            }
             Walk wk(n);
             for (int idx = threadIdx.x; idx < C * n; idx += BT, wk.next()) {
                 const int a = wk.c;   // V at a mod m, a < n <= 2m
@@ -1793,8 +1808,8 @@ tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x
         f_max = std::max(f_max, half == 1 ? a16(m * sizeof(float)) : size_t(0));
         m_max = std::max(m_max, a16(P * m * ebytes));
         Lmax = std::max(Lmax, c.L);
-        fwd_tiles = std::max(fwd_tiles, c.L == 256 ? c.C : c.C * (int)cdiv(c.n, row_tile_fwd(c.L)));
-        inv_tiles = std::max(inv_tiles, c.L == 256 ? c.C : c.C * (int)cdiv(c.n, row_tile_inv(c.L)));
+        fwd_tiles = std::max(fwd_tiles, c.C * (int)cdiv(c.n, row_tile_fwd(c.L)));
+        inv_tiles = std::max(inv_tiles, c.C * (int)cdiv(c.n, row_tile_inv(c.L)));
     }
     const size_t off_a = a16((size_t)Lmax * sizeof(c32)), off_f = off_a + a_max, off_m = off_f + f_max;
     const size_t lds = slot ? off_m + m_max : off_a + work;
