@@ -1041,11 +1041,12 @@ __device__ __forceinline__ c32 swap_pair(c32 v) {
 // positions), so that the compiler keeps one address register per pattern.
 __device__ __forceinline__ int rev3(int v) { return ((v & 1) << 2) | (v & 2) | ((v >> 2) & 1); }
 
-// Forward transform of C channels of length M in place; threads t < C M / 8
-// take part (the others return at once), there is no workgroup barrier inside.
-// Entries from nin on are zero and are not read.
-template <int M>
-__device__ __forceinline__ void fft_wave_fwd(c32* A, const c32* tws, int C, int L, int nin) {
+// Forward transform of C channels of length M into the channel buffers;
+// threads t < C M / 8 take part (the others return at once), there is no
+// workgroup barrier inside.  The input x[i] of channel c comes from in(c, i)
+// (the caller folds and twists it there, from wherever it is staged).
+template <int M, typename In>
+__device__ __forceinline__ void fft_wave_fwd(c32* A, const c32* tws, int C, int L, In in) {
     constexpr int Q = M / 8, LQ = Q == 16 ? 4 : 3, MP = M + M / 16;
     const int t = threadIdx.x;
     if (t >= C * Q) return;
@@ -1055,7 +1056,7 @@ __device__ __forceinline__ void fft_wave_fwd(c32* A, const c32* tws, int C, int 
     auto row = [](int n1) { return Q == 16 ? 17 * n1 : 8 * n1 + (n1 >> 1); };
     c32 a[8];
 #pragma unroll
-    for (int n1 = 0; n1 < 8; ++n1) a[n1] = Q * n1 + q < nin ? Ac[q + row(n1)] : c32{0.f, 0.f};
+    for (int n1 = 0; n1 < 8; ++n1) a[n1] = in(t >> LQ, Q * n1 + q);   // x[Q n1 + q] of channel t / Q
     dft8<false>(a);
 #pragma unroll
     for (int k1 = 1; k1 < 8; ++k1) a[k1] = cmulc(a[k1], tws[((q * k1) & (M - 1)) * step]);   // w_M^{q k1}
@@ -1172,7 +1173,6 @@ __device__ __forceinline__ void fft_wave_inv(c32* A, const c32* tws, int C, int 
 // the next item loads into registers during this item's forward transform;
 // one wait on all vector memory operations before the products covers both.
 constexpr unsigned WAIT_VM0 = 0x0F70;   // s_waitcnt vmcnt(0), lgkmcnt and expcnt not waited
-constexpr int TPFT = 3;                 // entries of the input column held per thread (C n <= 1536 without waits)
 
 __device__ __forceinline__ int bitrev_split(int h, int sh) {   // bit reversal of h < 2^sh, sh <= 2
     return sh == 2 ? (((h & 1) << 1) | (h >> 1)) : h;
@@ -1380,13 +1380,28 @@ __device__ __forceinline__ void dma16(const void* g, const void* lds) {
 }
 #pragma clang diagnostic pop
 
+// s_waitcnt vmcnt(min(k, 15)) for a wave-uniform k: the wait of a wave for its
+// own direct loads older than its last k vector-memory instructions (memory
+// instructions of a wave complete in order)
+__device__ __forceinline__ void wait_vm_le(int k) {
+    switch (k < 15 ? k : 15) {
+#define TT_W(i) \
+    case i: asm volatile("s_waitcnt vmcnt(" #i ")" ::: "memory"); break;
+        TT_W(0) TT_W(1) TT_W(2) TT_W(3) TT_W(4) TT_W(5) TT_W(6) TT_W(7)
+        TT_W(8) TT_W(9) TT_W(10) TT_W(11) TT_W(12) TT_W(13) TT_W(14)
+#undef TT_W
+        default: asm volatile("s_waitcnt vmcnt(15)" ::: "memory"); break;
+    }
+}
+
 // LDS (bytes from the start of dynamic shared memory): twiddles at 0, the
-// transform buffer at offA, the FP16 factors at offF, the spectra at offM; the
-// host sizes each region for the largest system of the batch, so the direct
-// loads of the next item never reach the buffers the current item still uses.
+// transform buffer at offA, the FP16 factors at offF, the input column at offT,
+// the spectra at offM; the host sizes each region for the largest system of the
+// batch, so the direct loads of the next item never reach the buffers the
+// current item still uses.
 template <int PACK, int HALF>
 __global__ __launch_bounds__(BT, 4) void k_bcolt(const BSys* __restrict__ sys, const int* __restrict__ col_sys,
-                                                  int total_cols, int S, int offA, int offF, int offM) {
+                                                  int total_cols, int S, int offA, int offF, int offT, int offM) {
     extern __shared__ __align__(16) char smem_raw[];
     typedef typename std::conditional<HALF != 0, unsigned short, float>::type E;
     constexpr int PER = 16 / (int)sizeof(E);   // values per lane of one direct load
@@ -1398,37 +1413,56 @@ __global__ __launch_bounds__(BT, 4) void k_bcolt(const BSys* __restrict__ sys, c
     c32* tws = reinterpret_cast<c32*>(smem_raw);
     c32* A = reinterpret_cast<c32*>(smem_raw + offA);
     float* fac = reinterpret_cast<float*>(smem_raw + offF);
+    c32* Tst = reinterpret_cast<c32*>(smem_raw + offT);
     char* Ms = smem_raw + offM;
 
-    // direct loads of item (column cl, share hh) of system s: P runs of m values,
-    // 16 bytes a lane, chunk c of the item landing at Ms + 16 c, issued by the
-    // waves dw0 .. BT / 64 - 1 round by round (one direct load per wave per
-    // round: chunk (r nd + w - dw0) 64 + lane, the same position nd 64 / cpr
-    // rows on, nd = BT / 64 - dw0).  With the single-wave transforms dw0 is the
-    // first wave without a channel: those waves issue the whole item at once,
-    // under the others' inverse transform; otherwise every wave issues, a few
-    // rounds between the passes of the transforms.  The state is uniform but for
-    // one byte offset per lane.
+    // Direct loads of item (column cl, share hh) of system s, issued by the
+    // waves dw0 .. BT / 64 - 1 (with the single-wave transforms dw0 is the first
+    // wave without a channel: those waves issue the whole item at once, under
+    // the others' inverse transform; otherwise every wave issues, a few rounds
+    // between the passes of the transforms):
+    // * first the input column T[f2][c][a] (C n complex, 16 bytes a lane) to
+    //   the staging buffer Tst, which the next fold reads: each issuing wave
+    //   waits for its share at the top of the next item (its loads issued
+    //   after those are counted, dafter) and the workgroup barrier there
+    //   publishes it;
+    // * then P runs of m values of the spectra, chunk c of the item landing at
+    //   Ms + 16 c, round by round (one load per wave per round: chunk
+    //   (r nd + w - dw0) 64 + lane, the same position nd 64 / cpr rows on,
+    //   nd = BT / 64 - dw0), waited for before the products.
+    // The state is uniform but for one byte offset per lane.
     const int wave_u = __builtin_amdgcn_readfirstlane(wave);
     const char* dbase = nullptr;
     unsigned doff = 0, dstep = 0;
-    int dround = 0, dchunks = 0, dw0 = 0, dnd = BT / 64;
+    int dround = 0, dchunks = 0, dw0 = 0, dnd = BT / 64, dafter = 0;
     auto dma_begin = [&](const BSys& s, int cl, int hh, int first_wave) {
         const int f2 = cl - s.col0, L = s.L, m = L >> sh, P = PACK ? 4 * s.G * s.G : 3 * s.G * s.G;
         const int run = bitrev_split(hh, sh) * m, lcpr = __builtin_ctz(m / PER);
         dw0 = ((BT / 64 - first_wave) * 64) % (m / PER) ? 0 : first_wave;   // whole rows per round
         dnd = BT / 64 - dw0;
-        const int t = (wave_u - dw0) * 64 + lane, j0 = t >> lcpr, pp = (t - (j0 << lcpr)) * PER;
-        dbase = (const char*)((HALF ? (const E*)s.Mht : (const E*)s.Mt) + ((size_t)f2 * P * L + run));
-        doff = (unsigned)(((size_t)j0 * L + pp) * sizeof(E));
-        dstep = (unsigned)((size_t)((dnd * 64) >> lcpr) * L * sizeof(E));
-        dround = 0;
-        dchunks = wave_u >= dw0 ? P * m / PER : 0;
-        if constexpr (HALF == 1) {   // the m factors of these frequencies
-            const float* fs = s.Mhst + ((size_t)f2 * L + run);
-            for (int c = threadIdx.x; c - lane < m / 4; c += BT)
-                if (c < m / 4) dma16(fs + 4 * c, fac + 4 * (size_t)c);
+        dafter = 0;
+        if (wave_u < dw0) {
+            dchunks = 0;
+        } else {
+            const int t = (wave_u - dw0) * 64 + lane;
+            const int Cn = 2 * s.G * s.n, tch = Cn / 2;   // 16-byte chunks of the input column
+            const char* tsrc = (const char*)(s.T + (size_t)f2 * Cn);
+            for (int c = t; c - lane < tch; c += dnd * 64)
+                if (c < tch) dma16(tsrc + 16 * (size_t)c, (const char*)Tst + 16 * (size_t)c);
+            const int j0 = t >> lcpr, pp = (t - (j0 << lcpr)) * PER;
+            dbase = (const char*)((HALF ? (const E*)s.Mht : (const E*)s.Mt) + ((size_t)f2 * P * L + run));
+            doff = (unsigned)(((size_t)j0 * L + pp) * sizeof(E));
+            dstep = (unsigned)((size_t)((dnd * 64) >> lcpr) * L * sizeof(E));
+            dchunks = P * m / PER;
+            if constexpr (HALF == 1) {   // the m factors of these frequencies
+                const float* fs = s.Mhst + ((size_t)f2 * L + run);
+                for (int c = t; c - lane < m / 4; c += dnd * 64) {
+                    if (c < m / 4) dma16(fs + 4 * c, fac + 4 * (size_t)c);
+                    ++dafter;
+                }
+            }
         }
+        dround = 0;
     };
     auto dma_rounds = [&](int k) {
         for (int i = 0; i < k; ++i) {
@@ -1436,24 +1470,14 @@ __global__ __launch_bounds__(BT, 4) void k_bcolt(const BSys* __restrict__ sys, c
             if (wave_u < dw0 || cw >= dchunks) return;
             if (cw + lane < dchunks) dma16(dbase + doff + (size_t)dround * dstep, Ms + (size_t)cw * 16);
             ++dround;
+            ++dafter;
         }
     };
     auto hook = [&]() { dma_rounds(2); };
 
-    c32 tp[TPFT];
     int si = col_sys[col];
-    {
-        const BSys& s0 = sys[si];
-        const int f20 = col - s0.col0, Cn0 = 2 * s0.G * s0.n;
-#pragma unroll
-        for (int i = 0; i < TPFT; ++i) {
-            const int idx = threadIdx.x + i * BT;
-            tp[i] = gload(s0.T + (size_t)f20 * Cn0 + (idx < Cn0 ? idx : 0));
-        }
-        __builtin_amdgcn_s_waitcnt(WAIT_VM0);   // (the compiler then counts no load pending at the first fold)
-        dma_begin(s0, col, h, 0);
-        dma_rounds(1 << 20);
-    }
+    dma_begin(sys[si], col, h, 0);
+    dma_rounds(1 << 20);
     int qn = q + gridDim.x;
     int coln = ((qn >> 3) >> sh) * 8 + (qn & 7);
     int sin_ = coln < total_cols ? col_sys[coln] : 0;
@@ -1467,56 +1491,55 @@ __global__ __launch_bounds__(BT, 4) void k_bcolt(const BSys* __restrict__ sys, c
         const bool more = coln < total_cols;
         const int hn = (qn >> 3) & hm;
         const BSys& sn = sys[sin_];
+        int sinn = 0, qnn = qn + gridDim.x;
+        const int colnn = ((qnn >> 3) >> sh) * 8 + (qnn & 7);
+        if (more && colnn < total_cols) sinn = col_sys[colnn];
 
-        __syncthreads();   // the previous item's last reads of A and of the twiddles are done
+        if (wave_u >= dw0) wait_vm_le(dafter);   // this wave's share of the input column has landed
+        __syncthreads();   // ... every wave's; the previous item's last reads of A and of the twiddles are done
         if (L != prevL) {
             for (int i = threadIdx.x; i < L; i += BT) tws[i] = gload(s.tw + i);
             prevL = L;
             __syncthreads();
         }
-        // twisted input column folded to length m (entry a < n to a mod m, m >= n / 2)
-        {
-            const c32* Tc = s.T + (size_t)f2 * C * n;
-            auto fold = [&](c32 v, int c, int a, bool add) {
+        // twisted input column folded to length m: x[i] = sum over a = i, i + m (< n) of T[c][a] w_L^{h a}
+        // (m >= n / 2: at most two terms)
+        auto twisted = [&](int c, int a) {
+            c32 v = Tst[c * n + a];
+            if (h) {
                 int hw = h * a;   // < 2L
                 if (hw >= L) hw -= L;
-                if (h) v = cmulc(v, tws[hw]);   // w_L^{h a}
-                const int li = pidx<true>(c * m + (add ? a - m : a));
-                A[li] = add ? cadd(A[li], v) : v;
+                v = cmulc(v, tws[hw]);   // w_L^{h a}
+            }
+            return v;
+        };
+        // X at bit-reversed positions; the waves without a channel issue their direct loads meanwhile
+        if (m == 128 || m == 64) {
+            auto in = [&](int c, int i) {
+                c32 v = c32{0.f, 0.f};
+                if (i < n) v = twisted(c, i);
+                if (i + m < n) v = cadd(v, twisted(c, i + m));
+                return v;
             };
+            if (m == 128) fft_wave_fwd<128>(A, tws, C, L, in);
+            else fft_wave_fwd<64>(A, tws, C, L, in);
+        } else {
             for (int pass = 0; pass < (n > m ? 2 : 1); ++pass) {
                 if (pass) __syncthreads();
                 Walk wk(n);
-#pragma unroll
-                for (int i = 0; i < TPFT; ++i, wk.next()) {
-                    const int idx = threadIdx.x + i * BT;
-                    keep(tp[i]);
-                    if (idx < C * n && (wk.c >= m) == (pass == 1)) fold(tp[i], wk.r, wk.c, pass == 1);
-                }
-                for (int idx = threadIdx.x + TPFT * BT; idx < C * n; idx += BT, wk.next())
-                    if ((wk.c >= m) == (pass == 1)) fold(gload(Tc + idx), wk.r, wk.c, pass == 1);
+                for (int idx = threadIdx.x; idx < C * n; idx += BT, wk.next())
+                    if ((wk.c >= m) == (pass == 1)) {
+                        const c32 v = twisted(wk.r, wk.c);
+                        const int li = pidx<true>(wk.r * m + (pass ? wk.c - m : wk.c));
+                        A[li] = pass ? cadd(A[li], v) : v;
+                    }
             }
+            dma_rounds(2);
+            __syncthreads();
+            fft_dif<BT, true>(A, tws, C, bits, L, n < m ? n : m, hook);
         }
-        dma_rounds(2);
-        // the next item's input column loads under this item's transforms
-        int sinn = 0, qnn = qn + gridDim.x;
-        const int colnn = ((qnn >> 3) >> sh) * 8 + (qnn & 7);
-        if (more) {
-            const int f2n = coln - sn.col0, Cnn = 2 * sn.G * sn.n;
-#pragma unroll
-            for (int i = 0; i < TPFT; ++i) {
-                const int idx = threadIdx.x + i * BT;
-                tp[i] = gload(sn.T + (size_t)f2n * Cnn + (idx < Cnn ? idx : 0));
-            }
-            if (colnn < total_cols) sinn = col_sys[colnn];
-        }
-        __syncthreads();
-        // X at bit-reversed positions; the waves without a channel issue their direct loads meanwhile
-        if (m == 128) fft_wave_fwd<128>(A, tws, C, L, n < m ? n : m);
-        else if (m == 64) fft_wave_fwd<64>(A, tws, C, L, n < m ? n : m);
-        else fft_dif<BT, true>(A, tws, C, bits, L, n < m ? n : m, hook);
         dma_rounds(1 << 20);                     // the rest of this item's spectra
-        __builtin_amdgcn_s_waitcnt(WAIT_VM0);   // this wave's direct loads (and the next input column) are done
+        __builtin_amdgcn_s_waitcnt(WAIT_VM0);   // this wave's direct loads are done
         __syncthreads();                         // ... and every other wave's
 
         // per-frequency products: one thread per position (in place) for the usual sizes, else
@@ -1542,7 +1565,7 @@ __global__ __launch_bounds__(BT, 4) void k_bcolt(const BSys* __restrict__ sys, c
                 }
             }
         }
-        __syncthreads();   // every read of the spectra and of X is done
+        __syncthreads();   // every read of the spectra, of X and of the input column is done
         if (more) {
             const int fw = (m == 64 || m == 128) ? (C * (m / 8) + 63) / 64 : 0;   // waves of the wave transforms
             dma_begin(sn, coln, hn, fw < BT / 64 ? fw : 0);
@@ -1562,19 +1585,21 @@ __global__ __launch_bounds__(BT, 4) void k_bcolt(const BSys* __restrict__ sys, c
             __syncthreads();
         }
 
-        // this item's share of the inverse column transform, rows a < n
+        // this item's share of the inverse column transform, rows a < n (V at a mod m, a < n <= 2m)
         c32* Uo = s.U + ((size_t)f2 * S + h) * C * n;
-        if (PACK == 0 && (m == 128 || m == 64) && n <= m) {
-            // rows a < n <= m straight from the transform's registers (no fold to undo)
-            auto out = [&](int c, int a, c32 v) {
-                if (a < n) {
-                    if (h) {
-                        int hw = h * a;
-                        if (hw >= L) hw -= L;
-                        v = cmul(v, tws[hw]);   // w_L^{-h a}
-                    }
-                    gstore(Uo + c * n + a, v);
-                }
+        auto store_u = [&](int c, int a, c32 v) {
+            if (h) {
+                int hw = h * a;
+                if (hw >= L) hw -= L;
+                v = cmul(v, tws[hw]);   // w_L^{-h a}
+            }
+            gstore(Uo + c * n + a, v);
+        };
+        if (PACK == 0 && (m == 128 || m == 64)) {
+            // straight from the transform's registers: entry i gives rows i and i + m
+            auto out = [&](int c, int i, c32 v) {
+                if (i < n) store_u(c, i, v);
+                if (i + m < n) store_u(c, i + m, v);
             };
             if (m == 128) fft_wave_inv<128>(A, tws, C, L, out);
             else fft_wave_inv<64>(A, tws, C, L, out);
@@ -1589,16 +1614,8 @@ __global__ __launch_bounds__(BT, 4) void k_bcolt(const BSys* __restrict__ sys, c
                 fft_dit_inv<BT, true>(A, tws, C, bits, L, hook);
             }
             Walk wk(n);
-            for (int idx = threadIdx.x; idx < C * n; idx += BT, wk.next()) {
-                const int a = wk.c;   // V at a mod m, a < n <= 2m
-                c32 v = A[pidx<true>(wk.r * m + (a < m ? a : a - m))];
-                if (h) {
-                    int hw = h * a;
-                    if (hw >= L) hw -= L;
-                    v = cmul(v, tws[hw]);   // w_L^{-h a}
-                }
-                gstore(Uo + idx, v);
-            }
+            for (int idx = threadIdx.x; idx < C * n; idx += BT, wk.next())
+                store_u(wk.r, wk.c, A[pidx<true>(wk.r * m + (wk.c < m ? wk.c : wk.c - m))]);
         }
         dma_rounds(2);
         if (!more) break;
@@ -1794,7 +1811,7 @@ tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x
     bool slot = true;
     for (int i = 0; i < count; ++i)
         if (!is_pow2(systems[i]->L) || (systems[i]->L / S) * ebytes < 16) slot = false;
-    size_t work = 0, a_max = 0, f_max = 0, m_max = 0;
+    size_t work = 0, a_max = 0, f_max = 0, t_max = 0, m_max = 0;
     int Lmax = 0, fwd_tiles = 0, inv_tiles = 0;
     auto a16 = [](size_t b) { return (b + 15) & ~size_t(15); };
     for (int i = 0; i < count; ++i) {
@@ -1807,11 +1824,13 @@ tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x
         a_max = std::max(a_max, a16(((size_t)c.C * m + (size_t)c.C * m / 16 + 1) * sizeof(c32)));
         f_max = std::max(f_max, half == 1 ? a16(m * sizeof(float)) : size_t(0));
         m_max = std::max(m_max, a16(P * m * ebytes));
+        t_max = std::max(t_max, a16((size_t)c.C * c.n * sizeof(c32)));
         Lmax = std::max(Lmax, c.L);
         fwd_tiles = std::max(fwd_tiles, c.C * (int)cdiv(c.n, row_tile_fwd(c.L)));
         inv_tiles = std::max(inv_tiles, c.C * (int)cdiv(c.n, row_tile_inv(c.L)));
     }
-    const size_t off_a = a16((size_t)Lmax * sizeof(c32)), off_f = off_a + a_max, off_m = off_f + f_max;
+    const size_t off_a = a16((size_t)Lmax * sizeof(c32)), off_f = off_a + a_max, off_t = off_f + f_max,
+                 off_m = off_t + t_max;
     const size_t lds = slot ? off_m + m_max : off_a + work;
     TT_REQUIRE(lds <= 160 * 1024, "system too large for the batched product: " + std::to_string(lds) +
                                       " bytes of LDS per column item");
@@ -1875,7 +1894,7 @@ tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x
     static const ColKernel table[2][2][3] = {
         {{k_bcol<1, 0, 0>, k_bcol<1, 0, 1>, k_bcol<1, 0, 2>}, {k_bcol<1, 0, 0>, k_bcol<1, 0, 1>, k_bcol<1, 0, 2>}},
         {{k_bcol<4, 0, 0>, k_bcol<4, 0, 1>, k_bcol<4, 0, 2>}, {k_bcol<4, 1, 0>, k_bcol<4, 1, 1>, k_bcol<4, 1, 2>}}};
-    typedef void (*SlotKernel)(const BSys*, const int*, int, int, int, int, int);
+    typedef void (*SlotKernel)(const BSys*, const int*, int, int, int, int, int, int);
     static const SlotKernel slot_table[2][3] = {{k_bcolt<0, 0>, k_bcolt<0, 1>, k_bcolt<0, 2>},
                                                 {k_bcolt<1, 0>, k_bcolt<1, 1>, k_bcolt<1, 2>}};
     const ColKernel kc = table[(op || vec4) ? 1 : 0][op ? 1 : 0][half];
@@ -1895,7 +1914,7 @@ tt_status batch_apply(tt_ctx* const* systems, int count, const float* const* d_x
     if (phase_ms) TT_HIP(hipEventRecord(c0.bev[1], c0.stream));
     if (slot)
         hipLaunchKernelGGL(ks, dim3(col_grid), dim3(BT), lds, c0.stream, dd, col_sys, cols, S, (int)off_a, (int)off_f,
-                           (int)off_m);
+                           (int)off_t, (int)off_m);
     else
         hipLaunchKernelGGL(kc, dim3(col_grid), dim3(BT), lds, c0.stream, dd, col_sys, cols, S, Lmax);
     TT_HIP(hipGetLastError());
