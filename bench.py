@@ -65,6 +65,10 @@ def parse():
                          "many measured frames of lgs6_74x74 as right-hand sides")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner records")
     ap.add_argument("--learned-only", action="store_true", help="run only the learned-preconditioner records")
+    ap.add_argument("--learned-pad-74", type=int, default=256,
+                    help="padding of the 74x74 system in the batched (learned and plain) solves of the learned record")
+    ap.add_argument("--learned-pad-10", type=int, default=20,
+                    help="padding of the 10x10 system in the batched solves of the learned record")
     ap.add_argument("--no-multi", action="store_true", help="skip the many-frames-of-one-system records")
     ap.add_argument("--learned-steps", type=int, default=3000, help="optimiser steps of the learned preconditioner")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -334,15 +338,17 @@ def batch_matvec(args, ctxs, setup_s, precision=0, label=None, split=2):
     }
 
 
-def learned_record(wl_of, family, n_systems, steps, frames, tol, label):
+def learned_record(wl_of, family, n_systems, steps, frames, tol, label, pad_batched=None):
     """Train the learned preconditioner on n_systems systems of one geometry
     (family(i): random r0 and layer weights; 20000 (r = A e, e) pairs drawn by
     the library), then solve `frames` of the nominal system wl_of() with
     flexible CG preconditioned by it and with plain CG, both in the batched
-    solver (one frame per call), and the persistent plain CG."""
+    solver (one frame per call), and the persistent plain CG.  The batched
+    solves use the same system padded to pad_batched (the power-of-two
+    transforms of the batched kernels), the persistent one its own padding."""
     import torch
     from paper_1806_07938_amd import Context, Learned, system_from
-    from paper_1806_07938_amd.tt import PRECOND_LEARNED, SOLVER_BATCHED, SOLVER_PERSISTENT, TT_NOT_CONVERGED
+    from paper_1806_07938_amd.tt import PRECOND_LEARNED, SOLVER_BATCHED, SOLVER_PERSISTENT, TT_NOT_CONVERGED, tune_batch
     ctxs, keep = [], []
     for i in range(n_systems):
         c = Context(0)
@@ -358,24 +364,34 @@ def learned_record(wl_of, family, n_systems, steps, frames, tol, label):
         c.close()
     ctx = Context(0)
     kk = system_from(ctx, wl, target=True)
-    ctx.set_learned(net)
+    ctxb, kkb = ctx, None
+    if pad_batched and pad_batched != wl.pad_L:
+        ctxb = Context(0)
+        kkb = system_from(ctxb, wl_of(pad_batched), target=True)
+    ctxb.set_learned(net)
+    tune_batch([ctxb])
     S = [torch.tensor(f, device="cuda:0") for f in frames]
     res = {}
     allow = (0, TT_NOT_CONVERGED)
     for name, sv, pcm in (("learned_fpcg", SOLVER_BATCHED, PRECOND_LEARNED), ("batched_plain_cg", SOLVER_BATCHED, 0),
                           ("persistent_plain_cg", SOLVER_PERSISTENT, 0)):
         gr = sv == SOLVER_BATCHED
-        ctx.solve(S[0], tol=tol, solver=sv, preconditioner=pcm, allow=allow, graph=gr)
+        cx = ctxb if gr else ctx
+        cx.solve(S[0], tol=tol, solver=sv, preconditioner=pcm, allow=allow, graph=gr)
         torch.cuda.synchronize()
         ii = []
         t0 = time.perf_counter()
         for s in S:
-            ii.append(ctx.solve(s, tol=tol, solver=sv, preconditioner=pcm, allow=allow, graph=gr)[2])
+            ii.append(cx.solve(s, tol=tol, solver=sv, preconditioner=pcm, allow=allow, graph=gr)[2])
         torch.cuda.synchronize()
         res[name] = {"ms_per_solve": round((time.perf_counter() - t0) * 1e3 / len(S), 3),
+                     "pad_L": cx.info["pad_L"],
                      "iterations_mean": round(float(np.mean([i.iterations for i in ii])), 1),
                      "converged": all(i.status == 0 and i.rel_residual <= tol for i in ii),
                      "fallback": [int(i.fallback) for i in ii] if pcm else None}
+    if kkb is not None:
+        ctxb.close()
+        kkb.close()
     ctx.close()
     kk.close()
     net.close()
@@ -390,16 +406,17 @@ def learned_records(args, W, frames):
     c1 = W.lgs3_10x10()
     return {
         "learned_74x74": learned_record(
-            lambda: W.lgs6_74x74(pad_L=args.pad), lambda i: W.lgs6_74x74_family(i, pad_L=args.pad), 8,
+            lambda pad=args.pad: W.lgs6_74x74(pad_L=pad), lambda i: W.lgs6_74x74_family(i, pad_L=args.pad), 8,
             args.learned_steps, frames[:3], args.tol,
             "learned preconditioner (P = K^T K, 4-layer masked CNN, 32 channels) trained on 8 systems of the "
             "74x74 / 6 LGS geometry with random r0 and layer weights, then flexible CG on 3 frames of the "
-            f"nominal system to rel. residual {args.tol:g}, against plain CG"),
+            f"nominal system to rel. residual {args.tol:g}, against plain CG",
+            pad_batched=args.learned_pad_74),
         "learned_10x10": learned_record(
-            W.lgs3_10x10, W.lgs3_10x10_family, 8, args.learned_steps,
+            lambda pad=c1.pad_L: W.lgs3_10x10(pad_L=pad), W.lgs3_10x10_family, 8, args.learned_steps,
             W.turbulent_slopes(c1, frames=5).astype(np.float32), 1e-10,
             "the same at 10x10 / 3 LGS (8 training systems with random r0 and layer weights), 5 frames of "
-            "lgs3_10x10 to rel. residual 1e-10"),
+            "lgs3_10x10 to rel. residual 1e-10", pad_batched=args.learned_pad_10),
     }
 
 

@@ -61,15 +61,26 @@ struct ConvArgs {
     float* out;                 // [B][cout][n][n]
     const unsigned short* w;    // [16 MT][KP]
     const int* vmap;            // n*n valid index or -1 (zero those outputs), or null
-    int n, cin, cinp, cout, KP;
+    // Optional vector ends of the network (one launch fewer at each end):
+    // vin[b] (C n_vs valid slopes, channel-major) replaces in as map b, read
+    // through imap (n*n valid index or -1); vout[b] receives the valid outputs
+    // of map b in place of out (vmap required).
+    const int* imap;
+    const float* const* vin;
+    float* const* vout;
+    int n, cin, cinp, cout, KP, n_vs;
 };
 
 constexpr int CMAXP = 32;      // largest padded channel count
 constexpr int TW = 18;         // tile width: 16 pixels + halo
 constexpr int CR = 4;          // grid rows (waves) per block
 constexpr int KPMAX = 9 * CMAXP;
-
+constexpr int NT = 64 * CR;                                   // threads of a convolution block
+constexpr int NST = ((CR + 2) * TW * CMAXP + NT - 1) / NT;    // staged inputs per thread
 template <int MT>
+constexpr int NWV = (16 * MT * KPMAX / 8 + NT - 1) / NT;      // 16-byte weight words per thread
+
+template <int MT, bool VIN>
 __global__ __launch_bounds__(64 * CR) void k_conv(ConvArgs a) {
     __shared__ __align__(16) unsigned short th[(CR + 2) * TW * CMAXP];
     __shared__ __align__(16) unsigned short tl[(CR + 2) * TW * CMAXP];
@@ -77,23 +88,70 @@ __global__ __launch_bounds__(64 * CR) void k_conv(ConvArgs a) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int x0 = blockIdx.x * 16, y0 = blockIdx.y * CR, b = blockIdx.z;
     const int n = a.n, cinp = a.cinp;
-    const float* inb = a.in + (long)b * a.cin * n * n;
-    for (int idx = tid; idx < (CR + 2) * TW * cinp; idx += 64 * CR) {
+    const float* inb = a.in ? a.in + (long)b * a.cin * n * n : nullptr;
+    // Every global load of the staging is issued before the first one is
+    // used (addresses clamped to the map's first element where the position
+    // is padding), so the block waits for one memory round trip, not one per
+    // element.
+    const int total = (CR + 2) * TW * cinp;
+    const int nwv = 16 * MT * a.KP / 8;
+    const uint4* wsrc = reinterpret_cast<const uint4*>(a.w);
+    float v[NST];
+    int kv[NST];
+    uint4 wv[NWV<MT>];
+#pragma unroll
+    for (int j = 0; j < NST; ++j) {
+        const int idx = tid + NT * j;
         const int col = idx % TW;
         const int r = (idx / TW) % (CR + 2);
         const int c = idx / ((CR + 2) * TW);
         const int yy = y0 - 1 + r, xx = x0 - 1 + col;
-        float v = 0.0f;
-        if (c < a.cin && yy >= 0 && yy < n && xx >= 0 && xx < n) v = inb[((long)c * n + yy) * n + xx];
-        const unsigned short hi = bf16_rne(v);
-        const unsigned short lo = bf16_rne(v - bf16_to_f32(hi));
-        th[(r * TW + col) * cinp + c] = hi;
-        tl[(r * TW + col) * cinp + c] = lo;
+        const bool ok = idx < total && c < a.cin && yy >= 0 && yy < n && xx >= 0 && xx < n;
+        if constexpr (VIN) {   // the position's index in the valid-slope vector, or -1
+            const int k = a.imap[ok ? yy * n + xx : 0];
+            kv[j] = ok && k >= 0 ? c * a.n_vs + k : -1;
+        } else {
+            const float t = inb[ok ? ((long)c * n + yy) * n + xx : 0];
+            v[j] = ok ? t : 0.0f;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NWV<MT>; ++j) {
+        const int i = tid + NT * j;
+        wv[j] = wsrc[i < nwv ? i : 0];
+    }
+    if constexpr (VIN) {
+        const float* vb = a.vin[b];
+#pragma unroll
+        for (int j = 0; j < NST; ++j) {
+            const float t = vb[kv[j] >= 0 ? kv[j] : 0];
+            v[j] = kv[j] >= 0 ? t : 0.0f;
+        }
+    }
+    // (keeps the weight loads here: otherwise the compiler sinks each into
+    // its conditional store below and waits for it there, one at a time)
+#pragma unroll
+    for (int j = 0; j < NWV<MT>; ++j) asm volatile("" : "+v"(wv[j].x), "+v"(wv[j].y), "+v"(wv[j].z), "+v"(wv[j].w));
+#pragma unroll
+    for (int j = 0; j < NST; ++j) {
+        const int idx = tid + NT * j;
+        if (idx < total) {
+            const int col = idx % TW;
+            const int r = (idx / TW) % (CR + 2);
+            const int c = idx / ((CR + 2) * TW);
+            const unsigned short hi = bf16_rne(v[j]);
+            const unsigned short lo = bf16_rne(v[j] - bf16_to_f32(hi));
+            th[(r * TW + col) * cinp + c] = hi;
+            tl[(r * TW + col) * cinp + c] = lo;
+        }
     }
     {
-        const uint4* src = reinterpret_cast<const uint4*>(a.w);
         uint4* dst = reinterpret_cast<uint4*>(ws);
-        for (int i = tid; i < 16 * MT * a.KP / 8; i += 64 * CR) dst[i] = src[i];
+#pragma unroll
+        for (int j = 0; j < NWV<MT>; ++j) {
+            const int i = tid + NT * j;
+            if (i < nwv) dst[i] = wv[j];
+        }
     }
     __syncthreads();
     const int y = y0 + wave;
@@ -121,6 +179,17 @@ __global__ __launch_bounds__(64 * CR) void k_conv(ConvArgs a) {
     }
     const int x = x0 + lc;
     if (x >= n) return;
+    if (a.vout) {
+        const int k = a.vmap[y * n + x];
+        if (k < 0) return;
+        float* vb = a.vout[b];
+        for (int m = 0; m < MT; ++m)
+            for (int v = 0; v < 4; ++v) {
+                const int o = 16 * m + 4 * kq + v;
+                if (o < a.cout) vb[(long)o * a.n_vs + k] = acc[m][v];
+            }
+        return;
+    }
     const bool keep = !a.vmap || a.vmap[y * n + x] >= 0;
     float* outb = a.out + (long)b * a.cout * n * n;
     for (int m = 0; m < MT; ++m)
@@ -141,19 +210,6 @@ __global__ void k_scatter(const float* const* __restrict__ vec, const int* __res
         const int c = (int)(i / (n * n));
         const int k = vmap[pix];
         maps[(long)b * per + i] = k >= 0 ? v[(long)c * n_vs + k] : 0.0f;
-    }
-}
-
-// maps -> valid-slope vectors
-__global__ void k_gather(const float* __restrict__ maps, const int* __restrict__ vidx, float* const* __restrict__ vec,
-                         int C, int n, int n_vs) {
-    const int b = blockIdx.y;
-    float* v = vec[b];
-    const long per = (long)C * n * n;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)C * n_vs;
-         i += (long)gridDim.x * blockDim.x) {
-        const int c = (int)(i / n_vs), k = (int)(i % n_vs);
-        v[i] = maps[(long)b * per + (long)c * n * n + vidx[k]];
     }
 }
 
@@ -555,11 +611,16 @@ tt_status prep_weights(tt_learned& L, hipStream_t s) {
 
 // out = conv(in) with layer l's forward (adj = false) or adjoint operand, B maps
 tt_status conv(const tt_learned& L, int l, bool adj, const float* in, float* out, int B, int n, const int* vmap,
-               hipStream_t s) {
+               hipStream_t s, const int* imap = nullptr, const float* const* vin = nullptr,
+               float* const* vout = nullptr, int n_vs = 0) {
     ConvArgs a;
     a.in = in;
     a.out = out;
     a.vmap = vmap;
+    a.imap = imap;
+    a.vin = vin;
+    a.vout = vout;
+    a.n_vs = n_vs;
     a.n = n;
     if (!adj) {
         a.w = L.wf.p + L.wfoff[l];
@@ -579,10 +640,17 @@ tt_status conv(const tt_learned& L, int l, bool adj, const float* in, float* out
         return TT_INVALID_ARG;
     }
     const dim3 grid(cdiv(n, 16), cdiv(n, CR), B);
-    if (a.cout <= 16)
-        hipLaunchKernelGGL(k_conv<1>, grid, dim3(64 * CR), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_conv<2>, grid, dim3(64 * CR), 0, s, a);
+    if (a.cout <= 16) {
+        if (vin)
+            hipLaunchKernelGGL((k_conv<1, true>), grid, dim3(64 * CR), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_conv<1, false>), grid, dim3(64 * CR), 0, s, a);
+    } else {
+        if (vin)
+            hipLaunchKernelGGL((k_conv<2, true>), grid, dim3(64 * CR), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_conv<2, false>), grid, dim3(64 * CR), 0, s, a);
+    }
     TT_HIP(hipGetLastError());
     return TT_OK;
 }
@@ -618,19 +686,16 @@ tt_status learned_apply_batch(tt_learned& L, const tt_ctx& c, const float* const
         thost = hp;
         TT_HIP(hipMemcpyAsync(tdev.p, thost.data(), sizeof(float*) * 2 * B, hipMemcpyHostToDevice, s));
     }
-    const unsigned gx = std::min<unsigned>(cdiv((size_t)c.C * n * n, 256), 1024);
-    hipLaunchKernelGGL(k_scatter, dim3(gx, B), dim3(256), 0, s, tdev.p, c.vmap.p, m0, c.C, n, c.n_vs);
-    TT_HIP(hipGetLastError());
-    TT_CHECK(conv(L, 0, false, m0, m1, B, n, nullptr, s));
+    // the first layer reads the vectors through the valid map, the last one
+    // writes the valid outputs to the vectors
+    TT_CHECK(conv(L, 0, false, nullptr, m1, B, n, nullptr, s, c.vmap.p, tdev.p, nullptr, c.n_vs));
     TT_CHECK(conv(L, 1, false, m1, m0, B, n, nullptr, s));
     TT_CHECK(conv(L, 2, false, m0, m1, B, n, nullptr, s));
     TT_CHECK(conv(L, 3, false, m1, m0, B, n, c.vmap.p, s));   // K r on the valid subapertures
     TT_CHECK(conv(L, 3, true, m0, m1, B, n, nullptr, s));
     TT_CHECK(conv(L, 2, true, m1, m0, B, n, nullptr, s));
     TT_CHECK(conv(L, 1, true, m0, m1, B, n, nullptr, s));
-    TT_CHECK(conv(L, 0, true, m1, m0, B, n, nullptr, s));
-    hipLaunchKernelGGL(k_gather, dim3(gx, B), dim3(256), 0, s, m0, c.vidx.p, tdev.p + B, c.C, n, c.n_vs);
-    TT_HIP(hipGetLastError());
+    TT_CHECK(conv(L, 0, true, m1, nullptr, B, n, c.vmap.p, s, nullptr, nullptr, tdev.p + B, c.n_vs));
     return TT_OK;
 }
 
