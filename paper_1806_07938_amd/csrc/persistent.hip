@@ -760,10 +760,26 @@ __device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, int par, double*
         const R* gcol = gsrc + ((long)f2 * L + f1a) * Pn;   // this block's spectra, [j][reals]
         {
             R m = 0;
-            for (int i = threadIdx.x; i < C * n; i += PT) {
-                const cplx<R> q = a.T[(long)f2 * C * n + i];
-                Tc[i] = q;
-                if constexpr (MF >= 2) m = fmaxf(m, fmaxf(fabsf(q.x), fabsf(q.y)));
+            // the column's C n inputs, up to four per thread and pass with every
+            // load issued before the first store (one memory round trip a pass)
+            const cplx<R>* Tg = a.T + (long)f2 * C * n;
+            for (int i0 = 0; i0 < C * n; i0 += 4 * PT) {
+                cplx<R> q[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = i0 + u * PT + threadIdx.x;
+                    q[u] = Tg[i < C * n ? i : 0];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) asm volatile("" : "+v"(q[u].x), "+v"(q[u].y));
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = i0 + u * PT + threadIdx.x;
+                    if (i < C * n) {
+                        Tc[i] = q[u];
+                        if constexpr (MF >= 2) m = fmaxf(m, fmaxf(fabsf(q[u].x), fabsf(q[u].y)));
+                    }
+                }
             }
             if (stage)
                 for (int i = threadIdx.x; i < Pn * Lr; i += PT) t.Ms[(i % Pn) * Lrm + i / Pn] = gcol[i];
