@@ -781,8 +781,24 @@ __device__ void col_phase(const PArgs<R>& a, const Tiles<R>& t, int par, double*
                     }
                 }
             }
-            if (stage)
-                for (int i = threadIdx.x; i < Pn * Lr; i += PT) t.Ms[(i % Pn) * Lrm + i / Pn] = gcol[i];
+            if (stage) {   // this block's spectra, [j][reals] -> [reals][j], the same way
+                const int tot = Pn * Lr;
+                for (int i0 = 0; i0 < tot; i0 += 16 * PT) {
+                    R g[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        const int i = i0 + u * PT + threadIdx.x;
+                        g[u] = gcol[i < tot ? i : 0];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) asm volatile("" : "+v"(g[u]));
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        const int i = i0 + u * PT + threadIdx.x;
+                        if (i < tot) t.Ms[(i % Pn) * Lrm + i / Pn] = g[u];
+                    }
+                }
+            }
             if constexpr (MF >= 2) block_max_bits(m, s_mx);
         }
         __syncthreads();
