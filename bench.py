@@ -164,7 +164,9 @@ def batch_uneven(args):
     """args.uneven systems of workloads.uneven_family (grids 40 / 60 / 74 / 84 in
     turn, 4-8 LGS, 10-35 layers, noise 0.01-0.5 rad^2, L the power of two >= 2n):
     the batched product (with the column kernel's roofline) and one measured
-    frame per system solved together by lockstep plain CG."""
+    frame per system solved together by lockstep plain CG, and by lockstep CG
+    preconditioned by the block-circulant inverse with its spectra stored in
+    FP16."""
     import multiprocessing as mp
     import torch
     import workloads as W
@@ -185,7 +187,10 @@ def batch_uneven(args):
              "0.01-0.5 rad^2, r0 0.10-0.25 m, L = 128 / 256)")
     out = {"batch_tuning_uneven": tune(ctxs, 0),
            "batch_matvec_uneven": batch_matvec(args, ctxs, setup_s, label=label, split=0),
-           "batch_solve_uneven": batch_solve(args, ctxs, frames, 0, label=label)}
+           "batch_solve_uneven": batch_solve(args, ctxs, frames, 0, label=label),
+           # mixed precision on the uneven mix: the block-circulant preconditioner
+           # with its spectra stored in FP16, the operator in FP32
+           "batch_solve_uneven_pcg_f16": batch_solve(args, ctxs, frames, 1, precision=2, label=label)}
     for c in ctxs + keep:
         c.close()
     return out
