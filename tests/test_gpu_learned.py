@@ -58,6 +58,36 @@ def test_learned_apply_matches_oracle(wl_name):
     k.close()
 
 
+def test_learned_fpcg_batched_frames_equal_solo_solves():
+    """Flexible CG over four frames of one system (context views sharing the
+    network: one application of the network to four vectors per iteration,
+    the first and last layers reading and writing each vector through the
+    valid map) gives, frame by frame, bitwise the solve of that frame alone."""
+    import torch
+    from paper_1806_07938_amd import Learned, solve_batch
+    from paper_1806_07938_amd.tt import PRECOND_LEARNED, SOLVER_BATCHED
+    wl = W.lgs3_10x10()
+    base, k = make_system(wl, target=False)
+    net = Learned(wl.n_gs, 32, seed=7)
+    net.set_weights(_seeded_weights(net, 41))
+    base.set_learned(net)
+    views = [base.view() for _ in range(3)]   # created after set_learned: they share the network
+    frames = W.turbulent_slopes(wl, seed=79, frames=4).astype(np.float32)
+    S = [torch.tensor(f, device=torch_dev()) for f in frames]
+    zs, _, infos, st = solve_batch([base] + views, S, tol=1e-8, solver=SOLVER_BATCHED, preconditioner=PRECOND_LEARNED)
+    assert st == 0
+    for i, (z, inf) in enumerate(zip(zs, infos)):
+        z1, _, inf1 = base.solve(S[i], tol=1e-8, solver=SOLVER_BATCHED, preconditioner=PRECOND_LEARNED, project=False)
+        say(f"frame {i}: batched {inf.iterations} iterations, alone {inf1.iterations}, fallback {inf.fallback}")
+        assert inf.iterations == inf1.iterations
+        assert np.array_equal(z.cpu().numpy(), z1.cpu().numpy())
+    for v in views:
+        v.close()
+    base.close()
+    k.close()
+    net.close()
+
+
 def test_learned_train_step_matches_oracle():
     import torch
     from paper_1806_07938_amd import Learned
